@@ -1,0 +1,339 @@
+"""Pins of the CPU oracle against facts that do not come from the oracle itself.
+
+Each test fixes the oracle to something independent: the known behaviour of Life
+patterns, brute force over every small neighbourhood (popcount of the pattern),
+closed forms of the box count, a SciPy convolution, the band-matrix product of
+the paper's Eq. 2-3, symmetry, the M0/M1 equivalence and the decay countdown.
+Both oracle implementations (C and NumPy) are checked against the same pins and
+against each other.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2406_17284_amd import inputs
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+LIFE = inputs.LIFE
+LIFE_M0 = inputs.Rule(1, 2, 0, 2, 3, 3, 3)  # the same automaton in the paper's Table 4 form
+
+
+def load_patterns():
+    pats = {}
+    with open(os.path.join(GOLDEN, "life_patterns.txt")) as f:
+        lines = [ln.rstrip("\n") for ln in f if not ln.startswith("#")]
+    k = 0
+    while k < len(lines):
+        ln = lines[k].strip()
+        k += 1
+        if not ln:
+            continue
+        parts = ln.split()
+        assert parts[0] == "pattern"
+        name, period, di, dj = parts[1], int(parts[3]), int(parts[5]), int(parts[6])
+        rows = []
+        while lines[k].strip() != "end":
+            rows.append(lines[k].strip())
+            k += 1
+        k += 1
+        a = np.array([[1 if ch == "O" else 0 for ch in row] for row in rows], dtype=np.uint8)
+        pats[name] = (a, period, di, dj)
+    return pats
+
+
+PATTERNS = load_patterns()
+
+
+def place(pat, H=40, W=40, at=(14, 14)):
+    g = np.zeros((H, W), dtype=np.uint8)
+    g[at[0]:at[0] + pat.shape[0], at[1]:at[1] + pat.shape[1]] = pat
+    return g
+
+
+@pytest.mark.parametrize("impl", ["c", "np"])
+@pytest.mark.parametrize("rule", [LIFE, LIFE_M0], ids=["M1", "M0"])
+@pytest.mark.parametrize("name", sorted(PATTERNS))
+def test_life_patterns(name, rule, impl):
+    pat, period, di, dj = PATTERNS[name]
+    g0 = place(pat)
+    run = oracle.run if impl == "c" else oracle.np_run
+    g = run(g0, rule, period)
+    assert np.array_equal(g, np.roll(np.roll(g0, di, axis=0), dj, axis=1))
+    # not a fixed point unless the pattern is a still life
+    if period > 1:
+        assert not np.array_equal(run(g0, rule, 1), g0)
+    # the population is unchanged after one full period
+    assert int(g.sum()) == int(pat.sum())
+
+
+def test_glider_hits_dead_boundary_without_wrapping():
+    pat = PATTERNS["glider"][0]
+    g0 = place(pat, 20, 20, at=(12, 12))
+    g = oracle.run(g0, LIFE, 40)
+    # a periodic boundary would carry the glider to the top-left; the dead halo never does
+    assert g[:10, :10].sum() == 0
+    # the glider meets the corner and turns into a block (a still life) at the edge
+    assert np.array_equal(oracle.run(g, LIFE, 1), g)
+    assert g.sum() == 4 and g[18:20, 18:20].sum() == 4
+
+
+def _brute_grid(r, patterns):
+    """Tile every pattern (integers whose (2r+1)^2 bits are the cells) as an adjacent
+    block; the centre of each block then sees exactly its own block."""
+    d = 2 * r + 1
+    nb_i, nb_j = patterns.shape
+    g = np.zeros((nb_i * d, nb_j * d), dtype=np.uint8)
+    for di in range(d):
+        for dj in range(d):
+            g[di::d, dj::d] = ((patterns >> (d * di + dj)) & 1).astype(np.uint8)
+    return g
+
+
+def _expected_centre(rule, pop, centre):
+    """Transition written from the rule notation: count = popcount minus the centre if M0."""
+    R, C, M, S1, S2, B1, B2 = rule.as_tuple()
+    cnt = pop - (centre if M == 0 else 0)
+    born = (B1 <= cnt) & (cnt <= B2)
+    keep = (S1 <= cnt) & (cnt <= S2)
+    return np.where(centre == 1, keep, born).astype(np.uint8)
+
+
+BRUTE_RULES_R1 = [LIFE, LIFE_M0, inputs.Rule(1, 0, 1, 0, 9, 0, 0), inputs.Rule(1, 0, 0, 5, 2, 0, 8),
+                  inputs.Rule(1, 0, 1, 2, 6, 1, 4)]
+
+
+@pytest.mark.parametrize("impl", ["c", "np"])
+@pytest.mark.parametrize("rule", BRUTE_RULES_R1, ids=lambda r: r.text())
+def test_bruteforce_all_3x3_neighbourhoods(rule, impl):
+    p = np.arange(512, dtype=np.int64).reshape(32, 16)
+    g = _brute_grid(1, p)
+    nxt = (oracle.step if impl == "c" else oracle.np_step)(g, rule)
+    pop = np.bitwise_count(p.astype(np.uint64)).astype(np.int64)
+    centre = (p >> 4) & 1
+    assert np.array_equal(nxt[1::3, 1::3], _expected_centre(rule, pop, centre))
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("rule", [inputs.Rule(2, 0, 1, 7, 13, 8, 11), inputs.Rule(2, 2, 0, 0, 24, 0, 6)],
+                         ids=lambda r: r.text())
+def test_bruteforce_all_5x5_neighbourhoods(rule):
+    # all 2**25 patterns as a 4096 x 8192 array of 5x5 blocks (a 20480 x 40960 grid)
+    p = np.arange(1 << 25, dtype=np.int64).reshape(4096, 8192)
+    g = _brute_grid(2, p)
+    nxt = oracle.step(g, rule)
+    del g
+    pop = np.bitwise_count(p.astype(np.uint64)).astype(np.int64)
+    centre = (p >> 12) & 1
+    assert np.array_equal(nxt[2::5, 2::5], _expected_centre(rule, pop, centre))
+
+
+def test_bruteforce_decay_states():
+    # r = 1, C = 4: every centre state 0..3 with every neighbourhood of states {0, 1, 2}
+    C = 4
+    rule = inputs.Rule(1, C, 0, 2, 3, 3, 3)
+    pats = []
+    for centre in range(C):
+        for code in range(3 ** 8):
+            nb, x = [], code
+            for _ in range(8):
+                nb.append(x % 3)
+                x //= 3
+            cells = nb[:4] + [centre] + nb[4:]
+            pats.append(cells)
+    pats = np.array(pats, dtype=np.uint8)  # (4 * 6561, 9)
+    n = len(pats)
+    nb_j = 81
+    nb_i = n // nb_j
+    g = np.zeros((nb_i * 3, nb_j * 3), dtype=np.uint8)
+    blocks = pats.reshape(nb_i, nb_j, 3, 3).transpose(0, 2, 1, 3).reshape(nb_i * 3, nb_j * 3)
+    g[:] = blocks
+    for impl in (oracle.step, oracle.np_step):
+        nxt = impl(g, rule)[1::3, 1::3].reshape(-1)
+        centre = pats[:, 4].astype(np.int64)
+        alive_nb = (pats == 1).sum(axis=1) - (centre == 1)
+        exp = np.empty(n, dtype=np.uint8)
+        for k in range(n):
+            c, a = int(centre[k]), int(alive_nb[k])
+            if c == 0:
+                exp[k] = 1 if 3 <= a <= 3 else 0
+            elif c == 1:
+                exp[k] = 1 if 2 <= a <= 3 else 2
+            else:
+                exp[k] = c + 1 if c + 1 < C else 0
+        assert np.array_equal(nxt, exp)
+
+
+@pytest.mark.parametrize("r", [1, 2, 5, 16])
+def test_count_single_cell_is_a_box(r):
+    H, W = 70, 53
+    for (i, j) in [(35, 26), (0, 0), (3, W - 2), (H - 1, 10)]:
+        g = np.zeros((H, W), dtype=np.uint8)
+        g[i, j] = 1
+        exp = np.zeros((H, W), dtype=np.int32)
+        exp[max(0, i - r):i + r + 1, max(0, j - r):j + r + 1] = 1
+        assert np.array_equal(oracle.count(g, r), exp)
+        assert np.array_equal(oracle.np_count(g, r), exp)
+
+
+@pytest.mark.parametrize("r", [1, 3, 7, 16])
+@pytest.mark.parametrize("shape", [(1, 1), (5, 40), (37, 29), (64, 64)])
+def test_count_all_alive_closed_form(r, shape):
+    H, W = shape
+    g = np.ones((H, W), dtype=np.uint8)
+    i = np.arange(H)[:, None]
+    j = np.arange(W)[None, :]
+    exp = (np.minimum(i, r) + np.minimum(H - 1 - i, r) + 1) * (np.minimum(j, r) + np.minimum(W - 1 - j, r) + 1)
+    assert np.array_equal(oracle.count(g, r), exp)
+    assert np.array_equal(oracle.np_count(g, r), exp)
+
+
+@pytest.mark.parametrize("r", [1, 4, 9, 16])
+def test_count_matches_scipy_convolution(r):
+    from scipy.signal import convolve2d
+    rng = np.random.default_rng(r)
+    g = rng.integers(0, 3, size=(61, 83)).astype(np.uint8)  # states 0, 1, 2: only 1 counts
+    ref = convolve2d((g == 1).astype(np.int64), np.ones((2 * r + 1, 2 * r + 1), dtype=np.int64),
+                     mode="same", boundary="fill", fillvalue=0)
+    assert np.array_equal(oracle.count(g, r), ref)
+
+
+@pytest.mark.parametrize("r", [1, 2, 5, 16])
+def test_count_is_the_band_product_of_eq2_eq3(r):
+    """Eq. 2-3: H = Lambda Pi, R = Pi H with Pi[a][b] = 1 iff |a - b| <= r (band truncated
+    at the grid edge, i.e. dead ghost halo)."""
+    rng = np.random.default_rng(100 + r)
+    Hh, Ww = 45, 70
+    lam = (rng.random((Hh, Ww)) < 0.5).astype(np.int64)
+    pi_w = (np.abs(np.arange(Ww)[:, None] - np.arange(Ww)[None, :]) <= r).astype(np.int64)
+    pi_h = (np.abs(np.arange(Hh)[:, None] - np.arange(Hh)[None, :]) <= r).astype(np.int64)
+    Hmat = lam @ pi_w
+    Rmat = pi_h @ Hmat
+    assert np.array_equal(oracle.count(lam.astype(np.uint8), r), Rmat)
+
+
+def _fragment_form(lam, r, p=16):
+    """Eq. F^H / F^R with 16 x 16 fragments and band fragments pi1, pi2, pi3, all three
+    vertical terms taken from H (the printed F^R shows Lambda in two terms; the
+    algorithm listing and the overview figure use H)."""
+    n = lam.shape[0]
+    assert n % p == 0
+    pad = np.zeros((n + 2 * p, n + 2 * p), dtype=np.int64)
+    pad[p:p + n, p:p + n] = lam
+    big = np.abs(np.arange(3 * p)[:, None] - np.arange(3 * p)[None, :]) <= r
+    pi1 = big[0:p, p:2 * p].astype(np.int64)      # band block (row j-1, col j)
+    pi2 = big[p:2 * p, p:2 * p].astype(np.int64)  # diagonal block
+    pi3 = big[2 * p:3 * p, p:2 * p].astype(np.int64)
+    nf = n // p + 2
+    F = lambda M, i, j: M[i * p:(i + 1) * p, j * p:(j + 1) * p]
+    Hm = np.zeros_like(pad)
+    for i in range(nf):
+        for j in range(1, nf - 1):
+            Hm[i * p:(i + 1) * p, j * p:(j + 1) * p] = F(pad, i, j - 1) @ pi1 + F(pad, i, j) @ pi2 + F(pad, i, j + 1) @ pi3
+    Rm = np.zeros_like(pad)
+    for i in range(1, nf - 1):
+        for j in range(1, nf - 1):
+            Rm[i * p:(i + 1) * p, j * p:(j + 1) * p] = pi3 @ F(Hm, i - 1, j) + pi2 @ F(Hm, i, j) + pi1 @ F(Hm, i + 1, j)
+    return Rm[p:p + n, p:p + n], (pi1, pi2, pi3)
+
+
+@pytest.mark.parametrize("r", [1, 8, 16])
+def test_count_matches_fragment_equations(r):
+    rng = np.random.default_rng(7 + r)
+    lam = (rng.random((48, 48)) < 0.5).astype(np.uint8)
+    Rm, (pi1, pi2, pi3) = _fragment_form(lam.astype(np.int64), r)
+    assert np.array_equal(pi3, pi1.T)
+    assert np.array_equal(Rm, oracle.count(lam, r))
+
+
+@pytest.mark.parametrize("rule", [LIFE, inputs.Rule(3, 0, 0, 12, 22, 13, 16), inputs.Rule(2, 5, 1, 6, 11, 6, 8)],
+                         ids=lambda r: r.text())
+def test_step_commutes_with_d4_symmetries(rule):
+    g = inputs.state_grid(57, 57, rule.C, seed=11)
+    s = oracle.step(g, rule)
+    for k in range(4):
+        assert np.array_equal(oracle.step(np.rot90(g, k), rule), np.rot90(s, k))
+    assert np.array_equal(oracle.step(g.T, rule), s.T)
+    assert np.array_equal(oracle.step(g[::-1], rule), s[::-1])
+
+
+@pytest.mark.parametrize("r,S,B", [(1, (2, 3), (3, 3)), (5, (34, 58), (34, 45)), (9, (100, 200), (0, 120))])
+def test_m0_equals_m1_with_survival_shifted(r, S, B):
+    g = inputs.bernoulli_grid(80, 67, 0.5, seed=r)
+    m0 = inputs.Rule(r, 0, 0, S[0], S[1], B[0], B[1])
+    m1 = inputs.Rule(r, 0, 1, S[0] + 1, S[1] + 1, B[0], B[1])
+    assert np.array_equal(oracle.run(g, m0, 6), oracle.run(g, m1, 6))
+
+
+@pytest.mark.parametrize("C", [3, 4, 8])
+def test_decay_countdown(C):
+    # an isolated alive cell always has count 1 (itself, M1); S excludes it, B never fires
+    rule = inputs.Rule(2, C, 1, 5, 9, 5, 9)
+    g = np.zeros((15, 15), dtype=np.uint8)
+    g[7, 7] = 1
+    seen = [int(g[7, 7])]
+    for _ in range(C + 1):
+        g = oracle.step(g, rule)
+        assert g.sum() == g[7, 7]  # nothing else is ever born
+        seen.append(int(g[7, 7]))
+    assert seen == [1] + list(range(2, C)) + [0, 0, 0]
+
+
+def test_decaying_cells_are_not_counted():
+    # a block of decaying cells must not let a dead cell be born with B = [1, 25]
+    rule = inputs.Rule(2, 5, 1, 0, 0, 1, 25)
+    g = np.zeros((12, 12), dtype=np.uint8)
+    g[4:7, 4:7] = 2
+    nxt = oracle.step(g, rule)
+    assert np.all(nxt[4:7, 4:7] == 3)
+    assert nxt.sum() == 9 * 3
+
+
+def test_birth_at_zero_fills_the_interior_only():
+    rule = inputs.Rule(3, 0, 1, 0, 0, 0, 0)  # born iff no alive cell in the box
+    g = np.zeros((21, 34), dtype=np.uint8)
+    assert np.all(oracle.step(g, rule) == 1)
+    assert np.all(oracle.np_step(g, rule) == 1)
+
+
+def test_resume_equals_single_run():
+    g = inputs.bernoulli_grid(64, 96, 0.5, seed=9)
+    rule = inputs.Rule(4, 6, 0, 20, 36, 21, 27)
+    assert np.array_equal(oracle.run(oracle.run(g, rule, 3), rule, 4), oracle.run(g, rule, 7))
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_c_and_numpy_oracles_agree(seed):
+    rng = np.random.default_rng(seed)
+    r = int(rng.integers(1, 17))
+    n = (2 * r + 1) ** 2
+    C = int(rng.choice([0, 2, 3, 7]))
+    s1, s2 = sorted(rng.integers(0, n + 1, size=2))
+    b1, b2 = sorted(rng.integers(0, n + 1, size=2))
+    rule = inputs.Rule(r, C, int(rng.integers(0, 2)), int(s1), int(s2), int(b1), int(b2))
+    H, W = int(rng.integers(1, 90)), int(rng.integers(1, 90))
+    g = inputs.state_grid(H, W, C, seed=seed)
+    assert np.array_equal(oracle.run(g, rule, 3), oracle.np_run(g, rule, 3))
+
+
+def test_table4_rules_parse_and_agree():
+    with open(os.path.join(GOLDEN, "table4_rules.txt")) as f:
+        rows = [ln.split() for ln in f if ln.strip() and not ln.startswith("#")]
+    assert len(rows) == 16
+    for k, (txt, dens) in enumerate(rows):
+        rule = inputs.parse_rule(txt)
+        assert rule.R == k + 1 and rule.N == "M"
+        g = inputs.bernoulli_grid(40, 40, float(dens), seed=k)
+        assert np.array_equal(oracle.run(g, rule, 2), oracle.np_run(g, rule, 2))
+
+
+def test_cone_run_matches_full_run():
+    rule = inputs.Rule(3, 0, 1, 12, 22, 13, 16)
+    H, W = 90, 120
+    full = inputs.bernoulli_grid(H, W, 0.5, seed=3)
+    ref = oracle.run(full, rule, 5)
+    fn = lambda rows, cols: inputs.bernoulli_grid(H, W, 0.5, seed=3, rows=rows, cols=cols)
+    for (i, j) in [(0, 0), (45, 60), (89, 119), (10, 100)]:
+        got = oracle.cone_run(fn, H, W, rule, 5, i, j, radius=2)
+        assert np.array_equal(got, ref[max(0, i - 2):i + 3, max(0, j - 2):j + 3])
