@@ -1,0 +1,182 @@
+"""Benchmark: Larger-than-Life cell-updates/s on one MI355X, CAT int8-MFMA vs the LDS direct stencil.
+
+A bench step is one full run of the workload: ``ltl_step(100)`` on the Bosco-type rule
+R5 C0 M1 S34..58 B34..45 N_M over a 4096 x 4096 uint8 grid (Bernoulli(0.5), seed 2, dead
+ghost halo), inputs resident in HBM. Prints one JSON line.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--sweep] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "cell-updates/s vs radius r=1..16, CAT int8-MFMA vs direct stencil, bit-exact"
+INT8_PEAK_TOPS = 5000.0  # MI355X dense int8 MFMA
+HBM_PEAK_GBS = 8000.0
+OPS_PER_CELL = 256       # two 16x16x64 int8 MFMAs per 256 cells, 2 ops per multiply-add
+
+
+def timed_runs(sim, n_per_run, runs, torch):
+    stream = sim.stream
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(runs):
+        sim.step(n_per_run)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return ev0.elapsed_time(ev1) / 1e3, wall
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--sweep", action="store_true", help="also time the radius sweep r=1..16 on 16384^2")
+    ap.add_argument("--sweep-side", type=int, default=16384)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--tuning", type=str, default="", help="T,tile_rows,tile_cols,waves")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2406_17284_amd import inputs, ltl
+
+    torch.cuda.set_device(0)
+    w = inputs.WORKLOADS["bosco4096"]
+    g0_np = inputs.bernoulli_grid(w.H, w.W, w.p, w.seed)
+    g0 = torch.from_numpy(g0_np).cuda()
+    cells = w.H * w.W
+
+    # ---- CAT int8
+    sim = ltl.Simulation(g0, w.rule, "cat_i8")
+    if args.tuning:
+        T, th, tw, wv = (int(x) for x in args.tuning.split(","))
+        sim.set_tuning(steps_per_launch=T, tile_rows=th, tile_cols=tw, waves=wv)
+    elif not args.no_autotune:
+        sim.autotune(probe_steps=20)
+    tuning = sim.tuning()
+    for _ in range(args.warmup):
+        sim.step(w.steps)
+    secs, wall = timed_runs(sim, w.steps, args.steps, torch)
+    value = cells * w.steps * args.steps / secs
+    launches_per_run = math.ceil(w.steps / tuning["steps_per_launch"])
+    avg_launch_s = secs / (args.steps * launches_per_run)
+    ops_per_launch = OPS_PER_CELL * cells * w.steps / launches_per_run
+    achieved_tops = ops_per_launch / avg_launch_s / 1e12
+    sim.close()
+
+    # ---- direct stencil, same workload
+    simd = ltl.Simulation(g0, w.rule, "direct")
+    simd.step(w.steps)
+    dsteps = max(1, min(args.steps, 3))
+    dsecs, _ = timed_runs(simd, w.steps, dsteps, torch)
+    direct_value = cells * w.steps * dsteps / dsecs
+    simd.close()
+
+    # ---- parity at the workload's own length: CAT vs direct on the GPU (and the oracle below)
+    a = ltl.Simulation(g0, w.rule, "cat_i8")
+    a.set_tuning(**{k: tuning[k] for k in ("steps_per_launch", "tile_rows", "tile_cols", "waves")})
+    a.step(w.steps)
+    b = ltl.Simulation(g0, w.rule, "direct")
+    b.step(w.steps)
+    cat_final = a.read().cpu().numpy()
+    direct_final = b.read().cpu().numpy()
+    a.close()
+    b.close()
+    parity = {"cat_vs_direct_equal": bool(np.array_equal(cat_final, direct_final))}
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": secs / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "i8",
+        "data": "synthetic",
+        "config": {
+            "workload": "bosco4096: R5 C0 M1 S34..58 B34..45 N_M, 4096x4096 uint8, Bernoulli(0.5) seed 2, "
+                        "dead ghost halo, 100 LTL steps per bench step",
+            "method": "cat_i8",
+            "tuning": tuning,
+            "direct_stencil_cell_updates_per_s": direct_value,
+            "cat_over_direct": value / direct_value,
+            "wall_s": wall,
+        },
+        "roofline": {
+            "bound": "mfma",
+            "achieved": achieved_tops,
+            "peak": INT8_PEAK_TOPS,
+            "unit": "TFLOP/s",
+            "frac": achieved_tops / INT8_PEAK_TOPS,
+            "traffic": None,
+            "kernel": "cat_step_i8",
+            "ops_per_cell_update": OPS_PER_CELL,
+            "avg_launch_us": avg_launch_s * 1e6,
+            "launches_per_bench_step": launches_per_run,
+        },
+        "parity": parity,
+    }
+
+    if args.sweep:
+        sweep = {}
+        side = args.sweep_side
+        gs = inputs.bernoulli_grid_torch(side, side, 0.5, 3, device="cuda")
+        for r in range(1, 17):
+            rule = inputs.sweep_rule(r)
+            row = {}
+            for method in ("cat_i8", "direct"):
+                s = ltl.Simulation(gs, rule, method)
+                if method == "cat_i8" and not args.no_autotune:
+                    s.autotune(probe_steps=10)
+                s.step(50)
+                secs_r, _ = timed_runs(s, 50, 1, torch)
+                row[method] = side * side * 50 / secs_r
+                s.close()
+            sweep[str(r)] = row
+        out["sweep"] = {"workload": f"{side}x{side}, r=1..16 sweep rules, Bernoulli(0.5) seed 3, 50 steps",
+                        "cell_updates_per_s": sweep}
+
+    if not args.no_cpu:
+        import oracle
+
+        threads = oracle.set_threads(0)
+        t0 = time.perf_counter()
+        one = oracle.run(g0_np, w.rule, 1)
+        t1 = time.perf_counter() - t0
+        n_cpu = int(max(1, min(w.steps - 1, 15.0 // max(t1, 1e-3))))
+        t0 = time.perf_counter()
+        res = oracle.run(one, w.rule, n_cpu)
+        tc = time.perf_counter() - t0
+        sample = f"bosco4096 grid, steps 2..{n_cpu + 1} of 100 ({n_cpu} steps, {t1 + tc:.1f} s total)"
+        if n_cpu + 1 == w.steps:
+            parity["cat_vs_oracle_equal"] = bool(np.array_equal(res, cat_final))
+        out["cpu_baseline"] = {"value": cells * n_cpu / tc, "unit": "cell-updates/s", "cores": threads,
+                               "kind": "oracle", "sample": sample}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

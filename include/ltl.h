@@ -1,0 +1,142 @@
+/*
+ * ltl.h -- C ABI of libltl: Larger-than-Life stepping on one MI355X (gfx950).
+ *
+ * The library advances cellular automata of the Larger-than-Life family,
+ * R_r C_c M_m S_{s1..s2} B_{b1..b2} N_M (paper: "Chosen CA tests", rule notation),
+ * on a uint8 grid with a dead ghost halo. The Moore neighbourhood count of every
+ * cell is the band-matrix reduction of "Formulation of CAT" (Eq. 2-3: H = Lambda Pi,
+ * R = Pi H, Pi the band of ones of half-width r), computed per grid tile on int8
+ * MFMA with int32 accumulation (exact for r <= 16), followed in the same kernel by
+ * the birth / survival / decay transition (Algorithm 1, per-thread rule after the
+ * reductions). The ping-pong update of "Pseudocode of CAT's Kernel" is kept: two
+ * caller-owned buffers swap roles every step.
+ *
+ * Conventions for every function below:
+ *  - All device pointers are HIP device memory on the current device. The caller
+ *    (for instance PyTorch) allocates and frees them; the library never frees them.
+ *  - Work is enqueued asynchronously on the stream given at creation; synchronize
+ *    that stream before reading results on the host or freeing the buffers.
+ *  - Return value: LTL_OK (0) or a negative LTL_ERR_* code; ltl_last_error() then
+ *    holds a message (thread-local, valid until the next call on the thread).
+ *  - Handles are not thread-safe: one thread uses one handle at a time.
+ */
+#ifndef LTL_H
+#define LTL_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    LTL_OK = 0,
+    LTL_ERR_ARG = -1,         /* null pointer, size < 1, pitch < width, bad tuning value */
+    LTL_ERR_RULE = -2,        /* R outside 1..16, C == 1 or > 255, M not 0/1, threshold < 0 or > (2R+1)^2 */
+    LTL_ERR_UNSUPPORTED = -3, /* neighbourhood other than Moore ('M') */
+    LTL_ERR_INEXACT = -4,     /* FP8 method with 2R+1 > 16: counts would not be exact in e4m3 */
+    LTL_ERR_SIZE = -5,        /* buffer smaller than ltl_buffer_bytes() */
+    LTL_ERR_HIP = -6,         /* HIP runtime error (message in ltl_last_error) */
+    LTL_ERR_STATE = -7        /* an initial cell holds a state >= max(C, 2) */
+};
+
+/* An LTL rule (paper, "Chosen CA tests"). N is the character 'M' (77) for Moore.
+ * C = 0 or 2: two states. C >= 3: states 2..C-1 are decay states (a surviving-range
+ * miss sends an alive cell to 2, decay advances by one per step and wraps to 0;
+ * decaying cells are neither alive nor born). M = 1 counts the centre cell itself.
+ * S and B are inclusive ranges of the count; s1 > s2 (or b1 > b2) is an empty range. */
+typedef struct {
+    int32_t R, C, M, S1, S2, B1, B2, N;
+} ltl_rule_t;
+
+/* How the neighbourhood count is computed; all give bit-identical grids. */
+typedef enum {
+    LTL_CAT_I8 = 0,  /* band products on int8 MFMA (v_mfma_i32_16x16x64_i8), int32 accumulate */
+    LTL_CAT_F16 = 1, /* band products on fp16 MFMA, fp32 accumulate (exact: counts <= 1089 < 2^11) */
+    LTL_CAT_F8 = 2,  /* band products on fp8-e4m3 MFMA, fp32 accumulate; only 2R+1 <= 16 */
+    LTL_DIRECT = 3   /* comparison method: LDS tile + direct (2R+1)^2 sum per cell */
+} ltl_method_t;
+
+/* Launch shape. Zero fields mean "library default". The result never depends on it. */
+typedef struct {
+    int32_t steps_per_launch; /* T >= 1 time steps fused in one kernel launch (temporal blocking) */
+    int32_t tile_rows;        /* output rows per workgroup: multiple of 16, 16..512 */
+    int32_t tile_cols;        /* output columns per workgroup: multiple of 32, 32..512 */
+    int32_t waves;            /* 64-lane waves per workgroup: 1..16 */
+    int32_t use_graph;        /* 1: replay multi-launch loops from a cached hipGraph */
+} ltl_tuning_t;
+
+typedef struct ltl_sim ltl_sim_t;
+typedef struct ltl_batch ltl_batch_t;
+
+/* Bytes of EACH of the two ping-pong buffers for an H x W grid (row pitch
+ * ltl_pitch(W), H rows). Returns LTL_ERR_ARG for H < 1 or W < 1. */
+int32_t ltl_buffer_bytes(int32_t H, int32_t W, size_t *bytes);
+
+/* Row pitch in bytes of the library's grid layout: W rounded up to 64. */
+int32_t ltl_pitch(int32_t W, int32_t *pitch);
+
+/* Create a simulation of an H x W grid.
+ *  rule       host pointer, copied.
+ *  method     an ltl_method_t.
+ *  buf_a/b    two device buffers of buf_bytes >= ltl_buffer_bytes(H, W) each, 256-byte aligned;
+ *             the library owns their contents until ltl_destroy.
+ *  init       device pointer to H rows of W uint8 states, row pitch init_pitch >= W bytes;
+ *             read before ltl_create returns. Every state must be < max(C, 2) (else LTL_ERR_STATE).
+ *  stream     HIP stream for all work of this handle (0 = null stream).
+ * ltl_create synchronizes `stream` once (state validation); later calls do not. */
+int32_t ltl_create(ltl_sim_t **out, int32_t H, int32_t W, const ltl_rule_t *rule, int32_t method,
+                   void *buf_a, void *buf_b, size_t buf_bytes, const void *init, size_t init_pitch,
+                   hipStream_t stream);
+
+/* Enqueue n_steps >= 0 synchronous steps. ltl_step(a); ltl_step(b) equals ltl_step(a + b)
+ * cell for cell. */
+int32_t ltl_step(ltl_sim_t *sim, int32_t n_steps);
+
+/* Enqueue a copy of the current H x W states into device memory dst (row pitch dst_pitch >= W). */
+int32_t ltl_read(ltl_sim_t *sim, void *dst, size_t dst_pitch);
+
+/* Device buffer holding the current state in the library layout (H rows of *pitch bytes;
+ * columns W..pitch-1 are always 0), and the number of steps taken so far. */
+int32_t ltl_current(ltl_sim_t *sim, void **buf, size_t *pitch, int64_t *steps_done);
+
+/* Current launch shape, and replacing it (validated; LTL_ERR_ARG on an invalid field). */
+int32_t ltl_get_tuning(ltl_sim_t *sim, ltl_tuning_t *tuning);
+int32_t ltl_set_tuning(ltl_sim_t *sim, const ltl_tuning_t *tuning);
+
+/* Time candidate launch shapes on this simulation (probe_steps steps each, on a device
+ * copy of the current state so the simulation itself does not advance), keep the
+ * fastest and return it in *best (may be NULL). Synchronizes the stream. */
+int32_t ltl_autotune(ltl_sim_t *sim, int32_t probe_steps, ltl_tuning_t *best);
+
+/* Release the handle (graphs, descriptors). Does not free the caller's buffers and does
+ * not synchronize; the caller synchronizes the stream first. NULL is accepted. */
+int32_t ltl_destroy(ltl_sim_t *sim);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char *ltl_last_error(void);
+
+/* ----------------------------------------------------------------------------------
+ * Batched simulation: `count` independent automata of any sizes and rules advance
+ * together, one persistent kernel launch per step over a cost-sorted (instance, tile)
+ * work list; multi-step loops are replayed from a hipGraph.
+ *  H, W, rules    host arrays of `count` entries (copied).
+ *  arena_a/b      two device buffers of >= ltl_batch_buffer_bytes() each; instance i
+ *                 occupies H[i] rows of ltl_pitch(W[i]) bytes at a library-chosen offset.
+ *  init           host array of `count` device pointers, instance i has row pitch init_pitch[i].
+ * Methods: LTL_CAT_I8 or LTL_DIRECT. */
+int32_t ltl_batch_buffer_bytes(int32_t count, const int32_t *H, const int32_t *W, size_t *bytes);
+int32_t ltl_batch_create(ltl_batch_t **out, int32_t count, const int32_t *H, const int32_t *W,
+                         const ltl_rule_t *rules, int32_t method, void *arena_a, void *arena_b,
+                         size_t bytes, const void *const *init, const size_t *init_pitch,
+                         hipStream_t stream);
+int32_t ltl_batch_step(ltl_batch_t *batch, int32_t n_steps);
+int32_t ltl_batch_read(ltl_batch_t *batch, int32_t index, void *dst, size_t dst_pitch);
+int32_t ltl_batch_destroy(ltl_batch_t *batch);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LTL_H */

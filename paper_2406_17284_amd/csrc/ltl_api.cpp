@@ -1,0 +1,530 @@
+// Host side of libltl: argument and rule validation, launch planning (tile shape, steps per
+// launch), the ping-pong driver with hipGraph replay of multi-launch loops, and the
+// autotuner. Every step of the automaton itself runs in the kernels of this library.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <new>
+#include <string>
+#include <tuple>
+#include <utility>
+#include <vector>
+
+#include "ltl.h"
+#include "ltl_internal.h"
+
+using namespace ltl;
+
+namespace {
+
+thread_local std::string g_err;
+
+int32_t fail(int32_t code, const std::string &msg) {
+    g_err = msg;
+    return code;
+}
+
+int32_t hip_fail(hipError_t e, const char *what) {
+    return fail(LTL_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr, what)                          \
+    do {                                             \
+        hipError_t e_ = (expr);                      \
+        if (e_ != hipSuccess) return hip_fail(e_, what); \
+    } while (0)
+
+int32_t validate_rule(const ltl_rule_t *r, int method) {
+    if (!r) return fail(LTL_ERR_ARG, "rule is NULL");
+    if (r->N != 'M') return fail(LTL_ERR_UNSUPPORTED, "only the Moore neighbourhood (N = 'M') is supported");
+    if (r->R < 1 || r->R > 16) return fail(LTL_ERR_RULE, "radius R must be in 1..16");
+    if (r->C < 0 || r->C == 1 || r->C > 255) return fail(LTL_ERR_RULE, "C must be 0 or in 2..255");
+    if (r->M != 0 && r->M != 1) return fail(LTL_ERR_RULE, "M must be 0 or 1");
+    const int nmax = (2 * r->R + 1) * (2 * r->R + 1);
+    const int th[4] = {r->S1, r->S2, r->B1, r->B2};
+    for (int v : th)
+        if (v < 0 || v > nmax) return fail(LTL_ERR_RULE, "S and B thresholds must be in 0..(2R+1)^2");
+    if (method < LTL_CAT_I8 || method > LTL_DIRECT) return fail(LTL_ERR_ARG, "unknown method");
+    if (method == LTL_CAT_F8 && 2 * r->R + 1 > 16)
+        return fail(LTL_ERR_INEXACT, "FP8 (e4m3) counts are exact only for 2R+1 <= 16");
+    if (method == LTL_CAT_F16 || method == LTL_CAT_F8)
+        return fail(LTL_ERR_UNSUPPORTED, "fp16/fp8 MFMA methods are not built yet");
+    return LTL_OK;
+}
+
+int epi_of(const ltl_rule_t &r) {
+    if (r.C >= 3) return EPI_DECAY;
+    int nmax = (2 * r.R + 1) * (2 * r.R + 1);
+    return nmax <= 126 ? EPI_BYTE : EPI_HALF;
+}
+
+// Thresholds on the box count n (centre included) and the SWAR constants of the two-state
+// epilogues. An alive centre with M = 0 sees n - 1, so its survival range moves up by one.
+RuleConsts make_consts(const ltl_rule_t &r, int epi) {
+    RuleConsts c;
+    std::memset(&c, 0, sizeof(c));
+    c.C = r.C >= 3 ? r.C : 2;
+    c.M = r.M;
+    c.s1 = r.S1; c.s2 = r.S2; c.b1 = r.B1; c.b2 = r.B2;
+    const int nmax = (2 * r.R + 1) * (2 * r.R + 1);
+    const int shift = (r.M == 0) ? 1 : 0;
+    auto norm = [&](int lo, int hi, int cap, int &olo, int &ohi) {
+        if (lo > hi || lo > nmax || hi < 0) { olo = cap; ohi = 0; return; }  // empty range
+        olo = std::max(lo, 0);
+        ohi = std::min(hi, nmax);
+    };
+    int ls, hs, lb, hb;
+    if (epi == EPI_BYTE) {
+        norm(r.S1 + shift, r.S2 + shift, 127, ls, hs);
+        norm(r.B1, r.B2, 127, lb, hb);
+        c.klo_s = (uint32_t)(0x80 - ls) * 0x01010101u;
+        c.khi_s = (uint32_t)(0x80 + hs) * 0x01010101u;
+        c.klo_b = (uint32_t)(0x80 - lb) * 0x01010101u;
+        c.khi_b = (uint32_t)(0x80 + hb) * 0x01010101u;
+    } else if (epi == EPI_HALF) {
+        norm(r.S1 + shift, r.S2 + shift, 2047, ls, hs);
+        norm(r.B1, r.B2, 2047, lb, hb);
+        c.klo_s = (uint32_t)(0x8000 - ls) * 0x00010001u;
+        c.khi_s = (uint32_t)(0x8000 + hs) * 0x00010001u;
+        c.klo_b = (uint32_t)(0x8000 - lb) * 0x00010001u;
+        c.khi_b = (uint32_t)(0x8000 + hb) * 0x00010001u;
+    }
+    return c;
+}
+
+int pitch_of(int W) { return roundup(W, 64); }
+
+size_t max_lds_bytes() {
+    static size_t v = 0;
+    if (v == 0) {
+        int dev = 0, x = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&x, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && x > 0)
+            v = (size_t)x;
+        else
+            v = 65536;
+    }
+    return v;
+}
+
+}  // namespace
+
+struct ltl_sim {
+    int32_t H = 0, W = 0, pitch = 0;
+    ltl_rule_t rule{};
+    int method = 0;
+    int epi = 0;
+    RuleConsts rc{};
+    uint8_t *buf[2] = {nullptr, nullptr};
+    int cur = 0;
+    int64_t steps_done = 0;
+    hipStream_t stream = nullptr;
+    ltl_tuning_t tuning{};
+    uint32_t *dflag = nullptr;
+    std::map<std::pair<int32_t, int>, hipGraphExec_t> graphs;
+};
+
+namespace {
+
+ltl_tuning_t default_tuning(const ltl_sim &s) {
+    ltl_tuning_t t;
+    t.steps_per_launch = 1;
+    t.tile_rows = 64;
+    t.tile_cols = 64;
+    t.waves = 4;
+    t.use_graph = 1;
+    (void)s;
+    return t;
+}
+
+CatParams cat_params(const ltl_sim &s, const ltl_tuning_t &t, int T, const uint8_t *src, uint8_t *dst) {
+    CatParams p;
+    p.src = src;
+    p.dst = dst;
+    p.H = s.H;
+    p.W = s.W;
+    p.pitch = s.pitch;
+    p.r = s.rule.R;
+    p.T = T;
+    p.TH = t.tile_rows;
+    p.TW = t.tile_cols;
+    p.L = cat_margin(p.r, T);
+    int elem_bytes = (s.method == LTL_CAT_F16) ? 2 : 1;
+    p.PS = cat_lds_pitch(p.TW, p.L, elem_bytes);
+    p.lds_rows = p.TH + 2 * p.L;
+    p.rc = s.rc;
+    return p;
+}
+
+DirectParams direct_params(const ltl_sim &s, const uint8_t *src, uint8_t *dst) {
+    DirectParams p;
+    p.src = src;
+    p.dst = dst;
+    p.H = s.H;
+    p.W = s.W;
+    p.pitch = s.pitch;
+    p.r = s.rule.R;
+    p.TH = 32;
+    p.TW = 64;
+    p.LP = 64 + 2 * p.r;
+    p.rc = s.rc;
+    return p;
+}
+
+int elem_of(int method) {
+    return method == LTL_CAT_F16 ? ELEM_F16 : method == LTL_CAT_F8 ? ELEM_F8 : ELEM_I8;
+}
+
+int32_t check_tuning(const ltl_sim &s, const ltl_tuning_t &t) {
+    if (t.steps_per_launch < 1 || t.steps_per_launch > 64) return fail(LTL_ERR_ARG, "steps_per_launch must be in 1..64");
+    if (t.tile_rows < 16 || t.tile_rows > 512 || t.tile_rows % 16) return fail(LTL_ERR_ARG, "tile_rows must be a multiple of 16 in 16..512");
+    if (t.tile_cols < 32 || t.tile_cols > 512 || t.tile_cols % 32) return fail(LTL_ERR_ARG, "tile_cols must be a multiple of 32 in 32..512");
+    if (t.waves < 1 || t.waves > 16) return fail(LTL_ERR_ARG, "waves must be in 1..16");
+    if (s.method != LTL_DIRECT) {
+        CatParams p = cat_params(s, t, t.steps_per_launch, nullptr, nullptr);
+        size_t lds = cat_lds_bytes(p, elem_of(s.method), s.epi);
+        if (lds > max_lds_bytes()) return fail(LTL_ERR_ARG, "launch shape needs " + std::to_string(lds) + " bytes of LDS");
+    } else if (t.steps_per_launch != 1) {
+        return fail(LTL_ERR_ARG, "the direct method takes one step per launch");
+    }
+    return LTL_OK;
+}
+
+// Launch shape and argument block of launch number k (steps_in_launch steps) starting
+// from buffer `from`.
+struct PlannedLaunch {
+    KernelLaunch k;
+    CatParams cp;
+    DirectParams dp;
+    bool direct;
+};
+
+PlannedLaunch plan(const ltl_sim &s, int steps_in_launch, int from) {
+    PlannedLaunch pl;
+    const uint8_t *src = s.buf[from];
+    uint8_t *dst = s.buf[from ^ 1];
+    pl.direct = (s.method == LTL_DIRECT);
+    if (pl.direct) {
+        pl.dp = direct_params(s, src, dst);
+        pl.k = direct_launch_shape(pl.dp);
+    } else {
+        pl.cp = cat_params(s, s.tuning, steps_in_launch, src, dst);
+        pl.k = cat_launch_shape(pl.cp, elem_of(s.method), s.epi, s.tuning.waves);
+    }
+    return pl;
+}
+
+std::vector<int> launch_sizes(const ltl_sim &s, int n) {
+    std::vector<int> v;
+    int T = (s.method == LTL_DIRECT) ? 1 : s.tuning.steps_per_launch;
+    while (n > 0) {
+        int t = std::min(T, n);
+        v.push_back(t);
+        n -= t;
+    }
+    return v;
+}
+
+hipError_t enqueue_one(ltl_sim &s, const PlannedLaunch &pl) {
+    if (pl.k.lds > 65536) {
+        hipError_t e = hipFuncSetAttribute(pl.k.func, hipFuncAttributeMaxDynamicSharedMemorySize, (int)pl.k.lds);
+        if (e != hipSuccess) return e;
+    }
+    void *args[1];
+    args[0] = pl.direct ? (void *)&pl.dp : (void *)&pl.cp;
+    return hipLaunchKernel(pl.k.func, pl.k.grid, pl.k.block, args, pl.k.lds, s.stream);
+}
+
+void clear_graphs(ltl_sim &s) {
+    for (auto &kv : s.graphs) (void)hipGraphExecDestroy(kv.second);
+    s.graphs.clear();
+}
+
+int32_t build_graph(ltl_sim &s, int n, int from, hipGraphExec_t *out) {
+    hipGraph_t g = nullptr;
+    HIP_TRY(hipGraphCreate(&g, 0), "hipGraphCreate");
+    hipGraphNode_t prev = nullptr;
+    int b = from;
+    std::vector<int> sizes = launch_sizes(s, n);
+    for (int t : sizes) {
+        PlannedLaunch pl = plan(s, t, b);
+        if (pl.k.lds > 65536) {
+            hipError_t e = hipFuncSetAttribute(pl.k.func, hipFuncAttributeMaxDynamicSharedMemorySize, (int)pl.k.lds);
+            if (e != hipSuccess) { (void)hipGraphDestroy(g); return hip_fail(e, "hipFuncSetAttribute"); }
+        }
+        hipKernelNodeParams kp;
+        std::memset(&kp, 0, sizeof(kp));
+        void *args[1];
+        args[0] = pl.direct ? (void *)&pl.dp : (void *)&pl.cp;
+        kp.func = const_cast<void *>(pl.k.func);
+        kp.gridDim = pl.k.grid;
+        kp.blockDim = pl.k.block;
+        kp.sharedMemBytes = (unsigned)pl.k.lds;
+        kp.kernelParams = args;
+        kp.extra = nullptr;
+        hipGraphNode_t node;
+        hipError_t e = hipGraphAddKernelNode(&node, g, prev ? &prev : nullptr, prev ? 1 : 0, &kp);
+        if (e != hipSuccess) { (void)hipGraphDestroy(g); return hip_fail(e, "hipGraphAddKernelNode"); }
+        prev = node;
+        b ^= 1;
+    }
+    hipGraphExec_t ex = nullptr;
+    hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+    *out = ex;
+    return LTL_OK;
+}
+
+int32_t do_steps(ltl_sim &s, int32_t n) {
+    if (n == 0) return LTL_OK;
+    std::vector<int> sizes = launch_sizes(s, n);
+    if (s.tuning.use_graph && sizes.size() > 1) {
+        auto key = std::make_pair(n, s.cur);
+        auto it = s.graphs.find(key);
+        hipGraphExec_t ex = nullptr;
+        if (it == s.graphs.end()) {
+            if (s.graphs.size() >= 32) clear_graphs(s);
+            int32_t rc = build_graph(s, n, s.cur, &ex);
+            if (rc != LTL_OK) return rc;
+            s.graphs[key] = ex;
+        } else {
+            ex = it->second;
+        }
+        HIP_TRY(hipGraphLaunch(ex, s.stream), "hipGraphLaunch");
+        s.cur ^= (int)(sizes.size() & 1);
+    } else {
+        for (int t : sizes) {
+            PlannedLaunch pl = plan(s, t, s.cur);
+            HIP_TRY(enqueue_one(s, pl), "kernel launch");
+            s.cur ^= 1;
+        }
+    }
+    s.steps_done += n;
+    return LTL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *ltl_last_error(void) { return g_err.c_str(); }
+
+int32_t ltl_pitch(int32_t W, int32_t *pitch) {
+    if (!pitch || W < 1) return fail(LTL_ERR_ARG, "W must be >= 1 and pitch non-NULL");
+    *pitch = pitch_of(W);
+    return LTL_OK;
+}
+
+int32_t ltl_buffer_bytes(int32_t H, int32_t W, size_t *bytes) {
+    if (!bytes || H < 1 || W < 1) return fail(LTL_ERR_ARG, "H and W must be >= 1 and bytes non-NULL");
+    *bytes = (size_t)H * (size_t)pitch_of(W);
+    return LTL_OK;
+}
+
+int32_t ltl_create(ltl_sim_t **out, int32_t H, int32_t W, const ltl_rule_t *rule, int32_t method,
+                   void *buf_a, void *buf_b, size_t buf_bytes, const void *init, size_t init_pitch,
+                   hipStream_t stream) {
+    if (!out) return fail(LTL_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    if (H < 1 || W < 1) return fail(LTL_ERR_ARG, "H and W must be >= 1");
+    if (!buf_a || !buf_b || !init) return fail(LTL_ERR_ARG, "NULL buffer");
+    if (buf_a == buf_b) return fail(LTL_ERR_ARG, "the two buffers must differ");
+    if (init_pitch < (size_t)W) return fail(LTL_ERR_ARG, "init_pitch < W");
+    if (((uintptr_t)buf_a & 255) || ((uintptr_t)buf_b & 255)) return fail(LTL_ERR_ARG, "buffers must be 256-byte aligned");
+    int32_t rc = validate_rule(rule, method);
+    if (rc != LTL_OK) return rc;
+    size_t need = (size_t)H * (size_t)pitch_of(W);
+    if (buf_bytes < need) return fail(LTL_ERR_SIZE, "buffers need " + std::to_string(need) + " bytes each");
+
+    ltl_sim *s = new (std::nothrow) ltl_sim();
+    if (!s) return fail(LTL_ERR_ARG, "out of host memory");
+    s->H = H;
+    s->W = W;
+    s->pitch = pitch_of(W);
+    s->rule = *rule;
+    s->method = method;
+    s->epi = epi_of(*rule);
+    s->rc = make_consts(*rule, s->epi);
+    s->buf[0] = (uint8_t *)buf_a;
+    s->buf[1] = (uint8_t *)buf_b;
+    s->stream = stream;
+    s->tuning = default_tuning(*s);
+
+    auto bail = [&](int32_t code) {
+        if (s->dflag) (void)hipFree(s->dflag);
+        delete s;
+        return code;
+    };
+    hipError_t e;
+    if ((e = hipMalloc(&s->dflag, sizeof(uint32_t))) != hipSuccess) { s->dflag = nullptr; return bail(hip_fail(e, "hipMalloc")); }
+    if ((e = hipMemsetAsync(s->dflag, 0, sizeof(uint32_t), stream)) != hipSuccess) return bail(hip_fail(e, "hipMemsetAsync"));
+    if ((e = launch_validate((const uint8_t *)init, H, W, init_pitch, s->rc.C, s->dflag, stream)) != hipSuccess)
+        return bail(hip_fail(e, "validate launch"));
+    uint32_t bad = 0;
+    if ((e = hipMemcpyAsync(&bad, s->dflag, sizeof(bad), hipMemcpyDeviceToHost, stream)) != hipSuccess) return bail(hip_fail(e, "hipMemcpyAsync"));
+    if ((e = hipStreamSynchronize(stream)) != hipSuccess) return bail(hip_fail(e, "hipStreamSynchronize"));
+    if (bad) return bail(fail(LTL_ERR_STATE, "initial grid holds a state >= max(C, 2)"));
+    for (int b = 0; b < 2; ++b)
+        if ((e = hipMemsetAsync(s->buf[b], 0, need, stream)) != hipSuccess) return bail(hip_fail(e, "hipMemsetAsync"));
+    if ((e = hipMemcpy2DAsync(s->buf[0], s->pitch, init, init_pitch, W, H, hipMemcpyDeviceToDevice, stream)) != hipSuccess)
+        return bail(hip_fail(e, "hipMemcpy2DAsync"));
+    *out = s;
+    return LTL_OK;
+}
+
+int32_t ltl_step(ltl_sim_t *sim, int32_t n_steps) {
+    if (!sim) return fail(LTL_ERR_ARG, "sim is NULL");
+    if (n_steps < 0) return fail(LTL_ERR_ARG, "n_steps must be >= 0");
+    return do_steps(*sim, n_steps);
+}
+
+int32_t ltl_read(ltl_sim_t *sim, void *dst, size_t dst_pitch) {
+    if (!sim || !dst) return fail(LTL_ERR_ARG, "NULL argument");
+    if (dst_pitch < (size_t)sim->W) return fail(LTL_ERR_ARG, "dst_pitch < W");
+    HIP_TRY(hipMemcpy2DAsync(dst, dst_pitch, sim->buf[sim->cur], sim->pitch, sim->W, sim->H,
+                             hipMemcpyDeviceToDevice, sim->stream), "hipMemcpy2DAsync");
+    return LTL_OK;
+}
+
+int32_t ltl_current(ltl_sim_t *sim, void **buf, size_t *pitch, int64_t *steps_done) {
+    if (!sim) return fail(LTL_ERR_ARG, "sim is NULL");
+    if (buf) *buf = sim->buf[sim->cur];
+    if (pitch) *pitch = (size_t)sim->pitch;
+    if (steps_done) *steps_done = sim->steps_done;
+    return LTL_OK;
+}
+
+int32_t ltl_get_tuning(ltl_sim_t *sim, ltl_tuning_t *tuning) {
+    if (!sim || !tuning) return fail(LTL_ERR_ARG, "NULL argument");
+    *tuning = sim->tuning;
+    return LTL_OK;
+}
+
+int32_t ltl_set_tuning(ltl_sim_t *sim, const ltl_tuning_t *tuning) {
+    if (!sim || !tuning) return fail(LTL_ERR_ARG, "NULL argument");
+    ltl_tuning_t t = *tuning;
+    ltl_tuning_t d = default_tuning(*sim);
+    if (t.steps_per_launch == 0) t.steps_per_launch = d.steps_per_launch;
+    if (t.tile_rows == 0) t.tile_rows = d.tile_rows;
+    if (t.tile_cols == 0) t.tile_cols = d.tile_cols;
+    if (t.waves == 0) t.waves = d.waves;
+    t.use_graph = t.use_graph ? 1 : 0;
+    int32_t rc = check_tuning(*sim, t);
+    if (rc != LTL_OK) return rc;
+    clear_graphs(*sim);
+    sim->tuning = t;
+    return LTL_OK;
+}
+
+int32_t ltl_autotune(ltl_sim_t *sim, int32_t probe_steps, ltl_tuning_t *best) {
+    if (!sim) return fail(LTL_ERR_ARG, "sim is NULL");
+    if (probe_steps < 1) return fail(LTL_ERR_ARG, "probe_steps must be >= 1");
+    ltl_sim &s = *sim;
+    if (s.method == LTL_DIRECT) {
+        if (best) *best = s.tuning;
+        return LTL_OK;
+    }
+    size_t bytes = (size_t)s.H * s.pitch;
+    uint8_t *scratch[2] = {nullptr, nullptr};
+    for (int b = 0; b < 2; ++b) {
+        hipError_t e = hipMalloc(&scratch[b], bytes);
+        if (e != hipSuccess) {
+            if (scratch[0]) (void)hipFree(scratch[0]);
+            return hip_fail(e, "hipMalloc (autotune scratch)");
+        }
+    }
+    ltl_sim probe;
+    probe.H = s.H; probe.W = s.W; probe.pitch = s.pitch; probe.rule = s.rule; probe.method = s.method;
+    probe.epi = s.epi; probe.rc = s.rc; probe.buf[0] = scratch[0]; probe.buf[1] = scratch[1];
+    probe.stream = s.stream;
+    hipEvent_t ev0, ev1;
+    (void)hipEventCreate(&ev0);
+    (void)hipEventCreate(&ev1);
+    const int Ts[] = {1, 2, 3, 4, 5, 6, 8};
+    const int tiles[][2] = {{64, 64}, {128, 64}, {64, 128}, {128, 128}, {256, 64}, {256, 128}, {128, 256}, {192, 128}};
+    const int wavess[] = {4, 8};
+    float best_ms = 1e30f;
+    ltl_tuning_t best_t = s.tuning;
+    int32_t rc = LTL_OK;
+    for (int T : Ts) {
+        if (T > probe_steps) continue;
+        for (auto &tl : tiles) {
+            for (int wv : wavess) {
+                ltl_tuning_t t;
+                t.steps_per_launch = T; t.tile_rows = tl[0]; t.tile_cols = tl[1]; t.waves = wv; t.use_graph = 1;
+                std::string saved = g_err;
+                if (check_tuning(s, t) != LTL_OK) { g_err = saved; continue; }
+                clear_graphs(probe);
+                probe.tuning = t;
+                (void)hipMemcpyAsync(scratch[0], s.buf[s.cur], bytes, hipMemcpyDeviceToDevice, s.stream);
+                probe.cur = 0;
+                if ((rc = do_steps(probe, probe_steps)) != LTL_OK) goto done;   // warm-up + graph build
+                (void)hipEventRecord(ev0, s.stream);
+                if ((rc = do_steps(probe, probe_steps)) != LTL_OK) goto done;
+                (void)hipEventRecord(ev1, s.stream);
+                if (hipEventSynchronize(ev1) != hipSuccess) { rc = fail(LTL_ERR_HIP, "autotune sync"); goto done; }
+                float ms = 0;
+                (void)hipEventElapsedTime(&ms, ev0, ev1);
+                if (ms < best_ms) { best_ms = ms; best_t = t; }
+            }
+        }
+    }
+done:
+    clear_graphs(probe);
+    (void)hipStreamSynchronize(s.stream);
+    (void)hipEventDestroy(ev0);
+    (void)hipEventDestroy(ev1);
+    (void)hipFree(scratch[0]);
+    (void)hipFree(scratch[1]);
+    if (rc != LTL_OK) return rc;
+    clear_graphs(s);
+    s.tuning = best_t;
+    if (best) *best = best_t;
+    return LTL_OK;
+}
+
+int32_t ltl_destroy(ltl_sim_t *sim) {
+    if (!sim) return LTL_OK;
+    clear_graphs(*sim);
+    if (sim->dflag) (void)hipFree(sim->dflag);
+    delete sim;
+    return LTL_OK;
+}
+
+// ---------------------------------------------------------------------- batched API
+int32_t ltl_batch_buffer_bytes(int32_t count, const int32_t *H, const int32_t *W, size_t *bytes) {
+    (void)count; (void)H; (void)W; (void)bytes;
+    return fail(LTL_ERR_UNSUPPORTED, "batched simulation not built yet");
+}
+
+int32_t ltl_batch_create(ltl_batch_t **out, int32_t count, const int32_t *H, const int32_t *W,
+                         const ltl_rule_t *rules, int32_t method, void *arena_a, void *arena_b,
+                         size_t bytes, const void *const *init, const size_t *init_pitch,
+                         hipStream_t stream) {
+    (void)out; (void)count; (void)H; (void)W; (void)rules; (void)method; (void)arena_a; (void)arena_b;
+    (void)bytes; (void)init; (void)init_pitch; (void)stream;
+    return fail(LTL_ERR_UNSUPPORTED, "batched simulation not built yet");
+}
+
+int32_t ltl_batch_step(ltl_batch_t *batch, int32_t n_steps) {
+    (void)batch; (void)n_steps;
+    return fail(LTL_ERR_UNSUPPORTED, "batched simulation not built yet");
+}
+
+int32_t ltl_batch_read(ltl_batch_t *batch, int32_t index, void *dst, size_t dst_pitch) {
+    (void)batch; (void)index; (void)dst; (void)dst_pitch;
+    return fail(LTL_ERR_UNSUPPORTED, "batched simulation not built yet");
+}
+
+int32_t ltl_batch_destroy(ltl_batch_t *batch) {
+    (void)batch;
+    return LTL_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,84 @@
+// Internal interface between the host library (ltl_api.cpp) and the kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ltl {
+
+// Epilogue flavour, chosen on the host from the rule:
+//  EPI_BYTE  two states, every count fits in 7 bits ((2r+1)^2 <= 126): 4 cells per dword SWAR
+//  EPI_HALF  two states, counts up to 1089: 2 cells per dword SWAR on 16-bit lanes
+//  EPI_DECAY C >= 3 states: per-cell transition with decay
+enum Epi { EPI_BYTE = 0, EPI_HALF = 1, EPI_DECAY = 2 };
+
+// Element type of the band-product operands.
+enum Elem { ELEM_I8 = 0, ELEM_F16 = 1, ELEM_F8 = 2 };
+
+// Rule constants prepared on the host (thresholds on the box count n that includes
+// the centre: for an alive centre with M = 0 the survival range is shifted by one).
+struct RuleConsts {
+    int32_t C;             // number of states (2 for C in {0, 2})
+    int32_t M;             // 1: centre counted
+    int32_t s1, s2, b1, b2;  // raw rule thresholds (per-cell decay epilogue and direct kernel)
+    // SWAR constants. BYTE: per byte 0x80 - lo and 0x80 + hi. HALF: per 16 bits 0x8000 - lo, 0x8000 + hi.
+    uint32_t klo_s, klo_b, khi_s, khi_b;
+};
+
+struct CatParams {
+    const uint8_t *src;
+    uint8_t *dst;
+    int32_t H, W, pitch;  // grid rows, columns, row pitch (bytes)
+    int32_t r;            // radius 1..16
+    int32_t T;            // steps in this launch
+    int32_t TH, TW;       // output tile (multiples of 16 / 32)
+    int32_t L;            // LDS margin around the output tile: roundup16(r (T-1)) + 16
+    int32_t PS;           // LDS row pitch (bytes per element row)
+    int32_t lds_rows;     // TH + 2L
+    RuleConsts rc;
+};
+
+struct DirectParams {
+    const uint8_t *src;
+    uint8_t *dst;
+    int32_t H, W, pitch;
+    int32_t r;
+    int32_t TH, TW;       // output tile of the direct kernel
+    int32_t LP;           // LDS row pitch
+    RuleConsts rc;
+};
+
+// Per-kernel geometry helpers shared by the host planner.
+inline int roundup(int x, int m) { return (x + m - 1) / m * m; }
+
+inline int cat_margin(int r, int T) { return roundup(r * (T - 1), 16) + 16; }
+
+inline int cat_lds_pitch(int TW, int L, int elem_bytes) {
+    // bytes per LDS row; kept = 16 (mod 32) bytes so the 16 rows of a 16-byte-per-lane
+    // operand read fall into distinct bank groups
+    int p = roundup((TW + 2 * L) * elem_bytes, 16);
+    if ((p & 31) == 0) p += 16;
+    return p;
+}
+
+inline int cat_tiles_in_lds(int T, int epi) {
+    int per_step = (epi == EPI_DECAY) ? 2 : 1;  // alive tile (+ state tile for decay)
+    return per_step * (T > 1 ? 2 : 1);
+}
+
+// Launchers (return the HIP status of the launch).
+hipError_t launch_cat(const CatParams &p, int elem, int epi, int waves, hipStream_t s);
+hipError_t launch_direct(const DirectParams &p, hipStream_t s);
+hipError_t launch_validate(const uint8_t *src, int H, int W, size_t pitch, int states,
+                           uint32_t *flag, hipStream_t s);
+
+// Kernel symbol and launch shape, for building graph nodes.
+struct KernelLaunch {
+    const void *func;
+    dim3 grid, block;
+    size_t lds;
+};
+KernelLaunch cat_launch_shape(const CatParams &p, int elem, int epi, int waves);
+KernelLaunch direct_launch_shape(const DirectParams &p);
+size_t cat_lds_bytes(const CatParams &p, int elem, int epi);
+
+}  // namespace ltl

@@ -1,0 +1,289 @@
+"""ctypes binding of ``libltl.so`` (declared in ``include/ltl.h``).
+
+Functions keep the C names and only marshal arguments; every step of the automaton
+runs in the library's HIP kernels. PyTorch supplies device memory and streams.
+There is no fallback: if the library is missing or fails to load, the call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libltl.so")
+
+LTL_OK = 0
+LTL_ERR_ARG = -1
+LTL_ERR_RULE = -2
+LTL_ERR_UNSUPPORTED = -3
+LTL_ERR_INEXACT = -4
+LTL_ERR_SIZE = -5
+LTL_ERR_HIP = -6
+LTL_ERR_STATE = -7
+
+LTL_CAT_I8 = 0
+LTL_CAT_F16 = 1
+LTL_CAT_F8 = 2
+LTL_DIRECT = 3
+METHODS = {"cat_i8": LTL_CAT_I8, "cat_f16": LTL_CAT_F16, "cat_f8": LTL_CAT_F8, "direct": LTL_DIRECT}
+
+# every symbol the header declares
+EXPORTS = [
+    "ltl_buffer_bytes", "ltl_pitch", "ltl_create", "ltl_step", "ltl_read", "ltl_current",
+    "ltl_get_tuning", "ltl_set_tuning", "ltl_autotune", "ltl_destroy", "ltl_last_error",
+    "ltl_batch_buffer_bytes", "ltl_batch_create", "ltl_batch_step", "ltl_batch_read",
+    "ltl_batch_destroy",
+]
+
+
+class ltl_rule_t(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int32) for n in ("R", "C", "M", "S1", "S2", "B1", "B2", "N")]
+
+
+class ltl_tuning_t(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int32) for n in ("steps_per_launch", "tile_rows", "tile_cols", "waves", "use_graph")]
+
+    def as_dict(self):
+        return {n: int(getattr(self, n)) for n, _ in self._fields_}
+
+
+class LtlError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"ltl error {code}: {msg}")
+        self.code = code
+
+
+_lib: Optional[ctypes.CDLL] = None
+
+
+def load(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load the HIP library (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with `python -m paper_2406_17284_amd.build`")
+    lib = ctypes.CDLL(path)
+    P, I32, SZ = ctypes.c_void_p, ctypes.c_int32, ctypes.c_size_t
+    PSZ = ctypes.POINTER(ctypes.c_size_t)
+    sig = {
+        "ltl_buffer_bytes": ([I32, I32, PSZ], I32),
+        "ltl_pitch": ([I32, ctypes.POINTER(ctypes.c_int32)], I32),
+        "ltl_create": ([ctypes.POINTER(P), I32, I32, ctypes.POINTER(ltl_rule_t), I32, P, P, SZ, P, SZ, P], I32),
+        "ltl_step": ([P, I32], I32),
+        "ltl_read": ([P, P, SZ], I32),
+        "ltl_current": ([P, ctypes.POINTER(P), PSZ, ctypes.POINTER(ctypes.c_int64)], I32),
+        "ltl_get_tuning": ([P, ctypes.POINTER(ltl_tuning_t)], I32),
+        "ltl_set_tuning": ([P, ctypes.POINTER(ltl_tuning_t)], I32),
+        "ltl_autotune": ([P, I32, ctypes.POINTER(ltl_tuning_t)], I32),
+        "ltl_destroy": ([P], I32),
+        "ltl_last_error": ([], ctypes.c_char_p),
+        "ltl_batch_buffer_bytes": ([I32, P, P, PSZ], I32),
+        "ltl_batch_create": ([ctypes.POINTER(P), I32, P, P, P, I32, P, P, SZ, P, P, P], I32),
+        "ltl_batch_step": ([P, I32], I32),
+        "ltl_batch_read": ([P, I32, P, SZ], I32),
+        "ltl_batch_destroy": ([P], I32),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = lib
+    return lib
+
+
+def last_error() -> str:
+    return load().ltl_last_error().decode()
+
+
+def _check(rc: int) -> int:
+    if rc != LTL_OK:
+        raise LtlError(rc, last_error())
+    return rc
+
+
+def make_rule(rule) -> ltl_rule_t:
+    """ltl_rule_t from an ``inputs.Rule`` or a (R, C, M, S1, S2, B1, B2[, N]) tuple."""
+    if hasattr(rule, "as_tuple"):
+        vals = list(rule.as_tuple()) + [ord(rule.N)]
+    else:
+        vals = list(rule)
+        if len(vals) == 7:
+            vals.append(ord("M"))
+        elif isinstance(vals[7], str):
+            vals[7] = ord(vals[7])
+    return ltl_rule_t(*[int(v) for v in vals])
+
+
+def _stream_handle(stream) -> int:
+    if stream is None:
+        return 0
+    if isinstance(stream, int):
+        return stream
+    return int(stream.cuda_stream)
+
+
+# ----------------------------------------------------------------- C-named calls
+def ltl_buffer_bytes(H: int, W: int) -> int:
+    out = ctypes.c_size_t(0)
+    _check(load().ltl_buffer_bytes(H, W, ctypes.byref(out)))
+    return out.value
+
+
+def ltl_pitch(W: int) -> int:
+    out = ctypes.c_int32(0)
+    _check(load().ltl_pitch(W, ctypes.byref(out)))
+    return out.value
+
+
+def ltl_create(H: int, W: int, rule, method: int, buf_a: int, buf_b: int, buf_bytes: int,
+               init: int, init_pitch: int, stream=None) -> int:
+    h = ctypes.c_void_p(0)
+    r = make_rule(rule)
+    _check(load().ltl_create(ctypes.byref(h), H, W, ctypes.byref(r), int(method), ctypes.c_void_p(buf_a),
+                             ctypes.c_void_p(buf_b), buf_bytes, ctypes.c_void_p(init), init_pitch,
+                             ctypes.c_void_p(_stream_handle(stream))))
+    return h.value
+
+
+def ltl_step(sim: int, n_steps: int) -> None:
+    _check(load().ltl_step(ctypes.c_void_p(sim), int(n_steps)))
+
+
+def ltl_read(sim: int, dst: int, dst_pitch: int) -> None:
+    _check(load().ltl_read(ctypes.c_void_p(sim), ctypes.c_void_p(dst), dst_pitch))
+
+
+def ltl_current(sim: int):
+    buf = ctypes.c_void_p(0)
+    pitch = ctypes.c_size_t(0)
+    steps = ctypes.c_int64(0)
+    _check(load().ltl_current(ctypes.c_void_p(sim), ctypes.byref(buf), ctypes.byref(pitch), ctypes.byref(steps)))
+    return buf.value, pitch.value, steps.value
+
+
+def ltl_get_tuning(sim: int) -> ltl_tuning_t:
+    t = ltl_tuning_t()
+    _check(load().ltl_get_tuning(ctypes.c_void_p(sim), ctypes.byref(t)))
+    return t
+
+
+def ltl_set_tuning(sim: int, steps_per_launch=0, tile_rows=0, tile_cols=0, waves=0, use_graph=1) -> None:
+    t = ltl_tuning_t(steps_per_launch, tile_rows, tile_cols, waves, use_graph)
+    _check(load().ltl_set_tuning(ctypes.c_void_p(sim), ctypes.byref(t)))
+
+
+def ltl_autotune(sim: int, probe_steps: int) -> ltl_tuning_t:
+    t = ltl_tuning_t()
+    _check(load().ltl_autotune(ctypes.c_void_p(sim), int(probe_steps), ctypes.byref(t)))
+    return t
+
+
+def ltl_destroy(sim: int) -> None:
+    _check(load().ltl_destroy(ctypes.c_void_p(sim)))
+
+
+def ltl_batch_buffer_bytes(H: Sequence[int], W: Sequence[int]) -> int:
+    n = len(H)
+    ha = (ctypes.c_int32 * n)(*H)
+    wa = (ctypes.c_int32 * n)(*W)
+    out = ctypes.c_size_t(0)
+    _check(load().ltl_batch_buffer_bytes(n, ha, wa, ctypes.byref(out)))
+    return out.value
+
+
+def ltl_batch_create(H: Sequence[int], W: Sequence[int], rules, method: int, arena_a: int, arena_b: int,
+                     nbytes: int, inits: Sequence[int], init_pitches: Sequence[int], stream=None) -> int:
+    n = len(H)
+    ha = (ctypes.c_int32 * n)(*H)
+    wa = (ctypes.c_int32 * n)(*W)
+    ra = (ltl_rule_t * n)(*[make_rule(r) for r in rules])
+    ia = (ctypes.c_void_p * n)(*inits)
+    pa = (ctypes.c_size_t * n)(*init_pitches)
+    h = ctypes.c_void_p(0)
+    _check(load().ltl_batch_create(ctypes.byref(h), n, ha, wa, ra, int(method), ctypes.c_void_p(arena_a),
+                                   ctypes.c_void_p(arena_b), nbytes, ia, pa,
+                                   ctypes.c_void_p(_stream_handle(stream))))
+    return h.value
+
+
+def ltl_batch_step(batch: int, n_steps: int) -> None:
+    _check(load().ltl_batch_step(ctypes.c_void_p(batch), int(n_steps)))
+
+
+def ltl_batch_read(batch: int, index: int, dst: int, dst_pitch: int) -> None:
+    _check(load().ltl_batch_read(ctypes.c_void_p(batch), int(index), ctypes.c_void_p(dst), dst_pitch))
+
+
+def ltl_batch_destroy(batch: int) -> None:
+    _check(load().ltl_batch_destroy(ctypes.c_void_p(batch)))
+
+
+# ------------------------------------------------------------ torch-owned memory
+class Simulation:
+    """One automaton whose two ping-pong buffers are torch uint8 tensors on the GPU."""
+
+    def __init__(self, init, rule, method="cat_i8", stream=None, tuning: Optional[dict] = None):
+        import torch
+
+        if isinstance(method, str):
+            method = METHODS[method]
+        if init.device.type != "cuda" or init.dtype != torch.uint8 or init.dim() != 2:
+            raise ValueError("init must be a 2-D uint8 CUDA tensor")
+        init = init.contiguous()
+        self.H, self.W = int(init.shape[0]), int(init.shape[1])
+        self.stream = stream if stream is not None else torch.cuda.current_stream(init.device)
+        nbytes = ltl_buffer_bytes(self.H, self.W)
+        # 256-byte aligned: torch's caching allocator hands out 512-byte aligned blocks
+        self.bufs = [torch.empty(nbytes, dtype=torch.uint8, device=init.device) for _ in range(2)]
+        self.handle = ltl_create(self.H, self.W, rule, method, self.bufs[0].data_ptr(), self.bufs[1].data_ptr(),
+                                 nbytes, init.data_ptr(), init.stride(0), self.stream)
+        self.device = init.device
+        if tuning:
+            ltl_set_tuning(self.handle, **tuning)
+
+    def step(self, n: int = 1) -> "Simulation":
+        ltl_step(self.handle, n)
+        return self
+
+    def read(self, out=None):
+        import torch
+
+        if out is None:
+            out = torch.empty((self.H, self.W), dtype=torch.uint8, device=self.device)
+        ltl_read(self.handle, out.data_ptr(), out.stride(0))
+        return out
+
+    def current_padded(self):
+        """The library-layout buffer holding the current state (H rows x pitch)."""
+        ptr, pitch, _ = ltl_current(self.handle)
+        idx = 0 if ptr == self.bufs[0].data_ptr() else 1
+        return self.bufs[idx][: self.H * pitch].view(self.H, pitch)
+
+    @property
+    def steps_done(self) -> int:
+        return ltl_current(self.handle)[2]
+
+    def tuning(self) -> dict:
+        return ltl_get_tuning(self.handle).as_dict()
+
+    def set_tuning(self, **kw) -> None:
+        ltl_set_tuning(self.handle, **kw)
+
+    def autotune(self, probe_steps: int = 8) -> dict:
+        return ltl_autotune(self.handle, probe_steps).as_dict()
+
+    def close(self) -> None:
+        if self.handle:
+            import torch
+
+            torch.cuda.synchronize(self.device)
+            ltl_destroy(self.handle)
+            self.handle = 0
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,78 @@
+"""C-ABI contract checks that need no GPU: the library loads, exports every function
+declared in include/ltl.h, and rejects bad arguments before touching the device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2406_17284_amd import ltl
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "ltl.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(ltl_\w+)\s*\(", src, flags=re.M)))
+
+
+def test_library_exports_every_declared_function():
+    lib = ltl.load()
+    names = declared_functions()
+    assert len(names) >= 16
+    assert sorted(ltl.EXPORTS) == names
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_pitch_and_buffer_bytes():
+    assert ltl.ltl_pitch(1) == 64
+    assert ltl.ltl_pitch(64) == 64
+    assert ltl.ltl_pitch(65) == 128
+    assert ltl.ltl_buffer_bytes(3, 100) == 3 * 128
+    for bad in [(0, 5), (5, 0), (-1, 3)]:
+        with pytest.raises(ltl.LtlError) as e:
+            ltl.ltl_buffer_bytes(*bad)
+        assert e.value.code == ltl.LTL_ERR_ARG
+
+
+def _create(H=8, W=8, rule=(1, 0, 1, 3, 4, 3, 3), method=ltl.LTL_CAT_I8, a=256, b=512, nbytes=1 << 20, init=1024,
+            pitch=8):
+    return ltl.ltl_create(H, W, rule, method, a, b, nbytes, init, pitch)
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(H=0), ltl.LTL_ERR_ARG),
+    (dict(a=0), ltl.LTL_ERR_ARG),
+    (dict(init=0), ltl.LTL_ERR_ARG),
+    (dict(a=256, b=256), ltl.LTL_ERR_ARG),
+    (dict(pitch=4), ltl.LTL_ERR_ARG),
+    (dict(a=100), ltl.LTL_ERR_ARG),
+    (dict(rule=(0, 0, 1, 3, 4, 3, 3)), ltl.LTL_ERR_RULE),
+    (dict(rule=(17, 0, 1, 3, 4, 3, 3)), ltl.LTL_ERR_RULE),
+    (dict(rule=(1, 1, 1, 3, 4, 3, 3)), ltl.LTL_ERR_RULE),
+    (dict(rule=(1, 256, 1, 3, 4, 3, 3)), ltl.LTL_ERR_RULE),
+    (dict(rule=(1, 0, 2, 3, 4, 3, 3)), ltl.LTL_ERR_RULE),
+    (dict(rule=(1, 0, 1, -1, 4, 3, 3)), ltl.LTL_ERR_RULE),
+    (dict(rule=(1, 0, 1, 3, 10, 3, 3)), ltl.LTL_ERR_RULE),
+    (dict(rule=(2, 0, 1, 3, 4, 3, 3, "N")), ltl.LTL_ERR_UNSUPPORTED),
+    (dict(rule=(8, 0, 1, 3, 4, 3, 3), method=ltl.LTL_CAT_F8), ltl.LTL_ERR_INEXACT),
+    (dict(method=7), ltl.LTL_ERR_ARG),
+    (dict(nbytes=63), ltl.LTL_ERR_SIZE),
+])
+def test_create_rejects_bad_arguments(kw, code):
+    with pytest.raises(ltl.LtlError) as e:
+        _create(**kw)
+    assert e.value.code == code
+    assert ltl.last_error()
+
+
+def test_null_handles():
+    lib = ltl.load()
+    assert lib.ltl_step(None, 1) == ltl.LTL_ERR_ARG
+    assert lib.ltl_read(None, None, 0) == ltl.LTL_ERR_ARG
+    assert lib.ltl_destroy(None) == ltl.LTL_OK
+    assert lib.ltl_batch_destroy(None) == ltl.LTL_OK
+    t = ltl.ltl_tuning_t()
+    assert lib.ltl_get_tuning(None, ctypes.byref(t)) == ltl.LTL_ERR_ARG

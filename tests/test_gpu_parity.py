@@ -1,0 +1,167 @@
+"""GPU parity: the HIP library against the CPU oracle, cell for cell.
+
+Counts are integers computed exactly (int8 MFMA with int32 accumulation), so the bar is
+bit-exact equality of every cell after every step checked.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2406_17284_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def ltl():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2406_17284_amd import ltl as mod
+    mod.load()
+    return mod
+
+
+def gpu_grid(a: np.ndarray):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def run_and_compare_each_step(ltl, g0, rule, method, steps, tuning=None):
+    sim = ltl.Simulation(gpu_grid(g0), rule, method, tuning=tuning)
+    ref = g0.copy()
+    for t in range(steps):
+        sim.step(1)
+        ref = oracle.step(ref, rule)
+        got = sim.read().cpu().numpy()
+        if not np.array_equal(got, ref):
+            bad = np.argwhere(got != ref)
+            raise AssertionError(f"{method} {rule.text()} tuning={tuning}: step {t + 1} differs at "
+                                 f"{len(bad)} cells, first {bad[:5].tolist()}")
+    sim.close()
+    return ref
+
+
+def run_and_compare(ltl, g0, rule, method, steps, tuning=None, chunks=None):
+    sim = ltl.Simulation(gpu_grid(g0), rule, method, tuning=tuning)
+    for n in (chunks or [steps]):
+        sim.step(n)
+    got = sim.read().cpu().numpy()
+    pad = sim.current_padded().cpu().numpy()
+    sim.close()
+    ref = oracle.run(g0, rule, steps)
+    if not np.array_equal(got, ref):
+        bad = np.argwhere(got != ref)
+        raise AssertionError(f"{method} {rule.text()} tuning={tuning}: after {steps} steps {len(bad)} cells "
+                             f"differ, first {bad[:5].tolist()}")
+    # padding columns of the library layout stay dead
+    assert not pad[:, g0.shape[1]:].any()
+
+
+METHODS = ["cat_i8", "direct"]
+
+SMALL_RULES = [
+    inputs.LIFE,
+    inputs.Rule(1, 2, 0, 2, 3, 3, 3),
+    inputs.Rule(2, 0, 1, 7, 13, 8, 11),
+    inputs.Rule(3, 0, 0, 15, 23, 14, 17),
+    inputs.BOSCO_M1,
+    inputs.Rule(5, 0, 0, 35, 59, 34, 45),
+    inputs.Rule(6, 0, 1, 42, 76, 45, 57),
+    inputs.Rule(8, 2, 0, 163, 223, 74, 252),
+    inputs.Rule(11, 0, 1, 132, 238, 142, 179),
+    inputs.Rule(16, 0, 0, 170, 296, 170, 300),
+    inputs.Rule(16, 0, 1, 272, 490, 294, 370),
+    inputs.Rule(3, 4, 1, 12, 22, 13, 16),
+    inputs.Rule(16, 8, 0, 300, 500, 330, 420),
+    inputs.Rule(2, 0, 1, 0, 3, 0, 2),      # birth at count 0: the dead halo must not be born
+    inputs.Rule(4, 0, 1, 30, 10, 21, 27),  # empty survival range
+]
+
+
+@pytest.mark.parametrize("method", METHODS)
+@pytest.mark.parametrize("rule", SMALL_RULES, ids=lambda r: r.text())
+def test_every_step_small_ragged(ltl, method, rule):
+    g0 = inputs.bernoulli_grid(83, 151, 0.5, seed=rule.R * 7 + rule.C)
+    run_and_compare_each_step(ltl, g0, rule, method, 6)
+
+
+@pytest.mark.parametrize("shape", [(1, 1), (1, 40), (37, 1), (16, 32), (17, 33), (255, 257), (300, 65)])
+@pytest.mark.parametrize("method", METHODS)
+def test_shapes(ltl, shape, method):
+    rule = inputs.Rule(3, 0, 1, 12, 22, 13, 16)
+    g0 = inputs.bernoulli_grid(shape[0], shape[1], 0.5, seed=shape[0] * 1000 + shape[1])
+    run_and_compare(ltl, g0, rule, method, 5)
+
+
+@pytest.mark.parametrize("T", [1, 2, 3, 4, 7])
+@pytest.mark.parametrize("r", [1, 2, 5, 6, 9, 16])
+def test_temporal_blocking(ltl, T, r):
+    rule = inputs.sweep_rule(r)
+    g0 = inputs.bernoulli_grid(200, 333, 0.5, seed=100 + r)
+    tuning = dict(steps_per_launch=T, tile_rows=64, tile_cols=64, waves=4)
+    margin = -(-r * (T - 1) // 16) * 16 + 16
+    lds = 2 * (64 + 2 * margin) * (64 + 2 * margin + 16)
+    if lds > 160 * 1024:
+        # the launch shape does not fit the 160 KB LDS: the library must refuse it
+        with pytest.raises(ltl.LtlError) as e:
+            run_and_compare(ltl, g0, rule, "cat_i8", 9, tuning=tuning)
+        assert e.value.code == ltl.LTL_ERR_ARG and "LDS" in str(e.value)
+        return
+    run_and_compare(ltl, g0, rule, "cat_i8", 9, tuning=tuning)
+
+
+@pytest.mark.parametrize("tile", [(16, 32, 1), (32, 64, 2), (64, 64, 4), (128, 128, 8), (48, 96, 3), (256, 128, 16)])
+def test_tile_shapes(ltl, tile):
+    rule = inputs.Rule(7, 0, 1, 56, 101, 60, 76)
+    g0 = inputs.bernoulli_grid(301, 299, 0.5, seed=5)
+    for T in (1, 3):
+        tuning = dict(steps_per_launch=T, tile_rows=tile[0], tile_cols=tile[1], waves=tile[2])
+        run_and_compare(ltl, g0, rule, "cat_i8", 7, tuning=tuning)
+
+
+def test_decay_multistep(ltl):
+    rule = inputs.Rule(5, 6, 0, 30, 54, 32, 41)
+    g0 = inputs.state_grid(190, 230, 6, seed=12)
+    for T in (1, 2, 4):
+        run_and_compare(ltl, g0, rule, "cat_i8", 8, tuning=dict(steps_per_launch=T))
+    run_and_compare(ltl, g0, rule, "direct", 8)
+
+
+def test_resume_and_graph_chunks(ltl):
+    rule = inputs.BOSCO_M1
+    g0 = inputs.bernoulli_grid(260, 270, 0.5, seed=77)
+    tuning = dict(steps_per_launch=3, tile_rows=64, tile_cols=64, waves=4)
+    run_and_compare(ltl, g0, rule, "cat_i8", 17, tuning=tuning, chunks=[0, 5, 1, 11, 0])
+    run_and_compare(ltl, g0, rule, "cat_i8", 17, tuning=dict(tuning, use_graph=0), chunks=[5, 12])
+
+
+def test_life_256_every_step(ltl):
+    w = inputs.WORKLOADS["life256"]
+    g0 = inputs.bernoulli_grid(w.H, w.W, w.p, w.seed)
+    for method in METHODS:
+        run_and_compare_each_step(ltl, g0, w.rule, method, w.steps)
+
+
+def test_life_patterns_on_gpu(ltl):
+    # a glider crossing tile borders keeps its shape and velocity
+    g0 = np.zeros((100, 100), dtype=np.uint8)
+    g0[1:4, 1:4] = np.array([[0, 1, 0], [0, 0, 1], [1, 1, 1]], dtype=np.uint8)
+    sim = ltl.Simulation(gpu_grid(g0), inputs.LIFE, "cat_i8", tuning=dict(steps_per_launch=4, tile_rows=32, tile_cols=32))
+    sim.step(80)
+    got = sim.read().cpu().numpy()
+    sim.close()
+    assert np.array_equal(got, np.roll(np.roll(g0, 20, 0), 20, 1))
+
+
+def test_bosco_4096_full(ltl):
+    w = inputs.WORKLOADS["bosco4096"]
+    g0 = inputs.bernoulli_grid(w.H, w.W, w.p, w.seed)
+    oracle.set_threads(0)
+    ref = oracle.run(g0, w.rule, w.steps)
+    for method in ("cat_i8", "direct"):
+        sim = ltl.Simulation(gpu_grid(g0), w.rule, method)
+        sim.step(w.steps)
+        got = sim.read().cpu().numpy()
+        sim.close()
+        assert np.array_equal(got, ref), method
