@@ -35,9 +35,15 @@
 namespace ltl {
 
 typedef int32_t v4i __attribute__((ext_vector_type(4)));
+// global-memory dword (explicit address space: global_store_*, not flat_* which would also
+// count against the LDS wait counter)
+typedef __attribute__((address_space(1))) uint32_t gdword;
 
+// Low bytes of the four int32 lanes of d packed into one dword (three byte permutes).
 __device__ __forceinline__ uint32_t pack_bytes(v4i d) {
-    return (uint32_t)d[0] | ((uint32_t)d[1] << 8) | ((uint32_t)d[2] << 16) | ((uint32_t)d[3] << 24);
+    uint32_t lo = __builtin_amdgcn_perm((uint32_t)d[1], (uint32_t)d[0], 0x0c0c0400u);  // d0.b0, d1.b0
+    uint32_t hi = __builtin_amdgcn_perm((uint32_t)d[3], (uint32_t)d[2], 0x0c0c0400u);  // d2.b0, d3.b0
+    return __builtin_amdgcn_perm(hi, lo, 0x05040100u);
 }
 
 __device__ __forceinline__ uint32_t bfi(uint32_t mask, uint32_t a, uint32_t b) {
@@ -53,33 +59,37 @@ __device__ __forceinline__ uint32_t col_mask(int gc, int W) {
     return m;
 }
 
-// Next states of 4 adjacent cells from their box counts (centre included) and states.
+// Next states of 4 adjacent cells from their box counts n (centre included) and states s.
+// `m` is the validity mask of the 4 cells (0xFF per byte inside the grid); cells outside get 0.
 // Returns the state dword; *alive receives the alive-indicator dword (state == 1).
+//
+// Two-state rules test lo(s) <= n <= hi(s) on 8-bit (BYTE) or 16-bit (HALF) SWAR lanes:
+// a = 0x80 + n - lo has its top bit set iff n >= lo, b = 0x80 + hi - n iff n <= hi, and the
+// per-lane offsets come from the centre state in one 3-input bitwise op each.
 template <int EPI>
-__device__ __forceinline__ uint32_t transition4(v4i n, uint32_t s, const RuleConsts &rc, uint32_t *alive) {
+__device__ __forceinline__ uint32_t transition4(v4i n, uint32_t s, uint32_t m, const RuleConsts &rc,
+                                                uint32_t *alive) {
     if constexpr (EPI == EPI_BYTE) {
-        // counts <= 126: per byte a = 0x80 + n - lo has bit 7 iff n >= lo,
-        // b = 0x80 + hi - n has bit 7 iff n <= hi; lo/hi picked per byte by the centre state
         uint32_t N = pack_bytes(n);
-        uint32_t sm = (0x80808080u - s) ^ 0x80808080u;  // 0xFF where s == 1
-        uint32_t a = N + bfi(sm, rc.klo_s, rc.klo_b);
-        uint32_t b = bfi(sm, rc.khi_s, rc.khi_b) - N;
-        uint32_t x = ((a & b) >> 7) & 0x01010101u;
+        uint32_t sm = 0x80808080u - s;                 // 0x80 per dead lane, 0x7F per alive lane
+        uint32_t a = N + (rc.Klo ^ (sm & rc.Dlo));
+        uint32_t b = (rc.Khi ^ (sm & rc.Dhi)) - N;
+        uint32_t x = (a & b & (m & 0x80808080u)) >> 7;
         *alive = x;
         return x;
     } else if constexpr (EPI == EPI_HALF) {
-        // the same test on 16-bit lanes, two cells per dword
         uint32_t p01 = (uint32_t)n[0] | ((uint32_t)n[1] << 16);
         uint32_t p23 = (uint32_t)n[2] | ((uint32_t)n[3] << 16);
-        uint32_t s01 = (s & 0xFFu) | ((s & 0xFF00u) << 8);
-        uint32_t s23 = ((s >> 16) & 0xFFu) | ((s >> 8) & 0xFF0000u);
-        uint32_t m01 = (0x80008000u - s01) ^ 0x80008000u;
-        uint32_t m23 = (0x80008000u - s23) ^ 0x80008000u;
-        uint32_t x01 = (p01 + bfi(m01, rc.klo_s, rc.klo_b)) & (bfi(m01, rc.khi_s, rc.khi_b) - p01);
-        uint32_t x23 = (p23 + bfi(m23, rc.klo_s, rc.klo_b)) & (bfi(m23, rc.khi_s, rc.khi_b) - p23);
+        uint32_t s01 = __builtin_amdgcn_perm(0u, s, 0x0c010c00u);  // bytes 0, 1 -> 16-bit lanes
+        uint32_t s23 = __builtin_amdgcn_perm(0u, s, 0x0c030c02u);
+        uint32_t m01 = __builtin_amdgcn_perm(0u, m, 0x010c000cu);  // mask bytes 0, 1 -> lane top bytes
+        uint32_t m23 = __builtin_amdgcn_perm(0u, m, 0x030c020cu);
+        uint32_t sm01 = 0x80008000u - s01;
+        uint32_t sm23 = 0x80008000u - s23;
+        uint32_t x01 = (p01 + (rc.Klo ^ (sm01 & rc.Dlo))) & ((rc.Khi ^ (sm01 & rc.Dhi)) - p01) & (m01 & 0x80008000u);
+        uint32_t x23 = (p23 + (rc.Klo ^ (sm23 & rc.Dlo))) & ((rc.Khi ^ (sm23 & rc.Dhi)) - p23) & (m23 & 0x80008000u);
         // bits 15 and 31 of x01, x23 -> bit 7 of bytes 0..3, then down to bit 0
-        uint32_t y = __builtin_amdgcn_perm(x23, x01, 0x07050301u);
-        uint32_t x = (y >> 7) & 0x01010101u;
+        uint32_t x = __builtin_amdgcn_perm(x23, x01, 0x07050301u) >> 7;
         *alive = x;
         return x;
     } else {
@@ -100,8 +110,8 @@ __device__ __forceinline__ uint32_t transition4(v4i n, uint32_t s, const RuleCon
             out |= (uint32_t)nx << (8 * v);
             al |= (uint32_t)(nx == 1) << (8 * v);
         }
-        *alive = al;
-        return out;
+        *alive = al & m;
+        return out & m;
     }
 }
 
@@ -153,176 +163,212 @@ __device__ __forceinline__ v4i band_v(int r, int phase, int lane) {
     return b;
 }
 
+// Geometry of one step: strips of 32 columns, each cut into `nseg` row segments of at most
+// CAT_MAXC 16-row blocks. Every segment is one wave's work item; a step needs
+// items <= waves (the host planner checks this for every step of a launch).
+struct StepGeom {
+    int E, nstrips, nrb, nseg, seglen;
+};
+
+__device__ __forceinline__ StepGeom step_geom(const CatParams &p, int t) {
+    StepGeom g;
+    g.E = (p.r * (p.T - t) + 15) & ~15;
+    g.nstrips = (p.TW + 2 * g.E) >> 5;
+    g.nrb = (p.TH + 2 * g.E) >> 4;
+    g.nseg = (g.nrb + CAT_MAXC - 1) / CAT_MAXC;
+    g.seglen = (g.nrb + g.nseg - 1) / g.nseg;
+    return g;
+}
+
+// H of one item and one 16-column half: the packed dword of H block rb0 - 1 + k in element
+// k (k = 0 .. count + 1 <= 15) of a 16-register tuple. Output block M needs k = M, M+1, M+2;
+// MFMA #2 reads the even-aligned 4-register window starting at M (M even: the blocks sit in
+// slots 0, 1, 2) or at M - 1 (M odd: slots 1, 2, 3), so the band operand has two phases and
+// every output block costs one MFMA, with no register copies.
+typedef int32_t v16i __attribute__((ext_vector_type(16)));
+
+template <int K>
+__device__ __forceinline__ v4i window4(const v16i &h) {
+    return __builtin_shufflevector(h, h, K, K + 1, K + 2, K + 3);
+}
+
+// Phase A of one item: H (horizontal band sums) of blocks rb0 - 1 .. rb0 + count for both
+// 16-column halves of the strip, packed to bytes, in registers.
+__device__ __forceinline__ void phase_a(const uint8_t *At, uint32_t a_off, uint32_t PS, int rb0, int count,
+                                        const v4i &bh0, const v4i &bh1, v16i &Ha, v16i &Hb) {
+    const v4i zero = {0, 0, 0, 0};
+#define CAT_HBLOCK(K)                                                                              \
+    if ((K) < count + 2) {                                                                         \
+        v4i a = *reinterpret_cast<const v4i *>(At + (a_off + (uint32_t)(16 * (rb0 - 1 + (K))) * PS)); \
+        v4i da = __builtin_amdgcn_mfma_i32_16x16x64_i8(a, bh0, zero, 0, 0, 0);                     \
+        v4i db = __builtin_amdgcn_mfma_i32_16x16x64_i8(a, bh1, zero, 0, 0, 0);                     \
+        Ha[(K)] = (int32_t)pack_bytes(da);                                                         \
+        Hb[(K)] = (int32_t)pack_bytes(db);                                                         \
+    }
+    CAT_HBLOCK(0) CAT_HBLOCK(1) CAT_HBLOCK(2) CAT_HBLOCK(3) CAT_HBLOCK(4) CAT_HBLOCK(5)
+    CAT_HBLOCK(6) CAT_HBLOCK(7) CAT_HBLOCK(8) CAT_HBLOCK(9) CAT_HBLOCK(10) CAT_HBLOCK(11)
+    CAT_HBLOCK(12) CAT_HBLOCK(13) CAT_HBLOCK(14) CAT_HBLOCK(15)
+#undef CAT_HBLOCK
+}
+
+// Phase B of one item: vertical band products, transition, store (in place in LDS for an
+// intermediate step, to the output grid on the last step of the launch).
+template <int EPI, bool MASKED, bool LAST>
+__device__ __forceinline__ void phase_b(const CatParams &p, uint8_t *At, uint8_t *Qt, uint32_t c_off, int rb0,
+                                        int count, int gr0, uint32_t goff0, int gca, uint32_t cma, uint32_t cmb,
+                                        const v4i &bve, const v4i &bvo, const v16i &Ha, const v16i &Hb) {
+    const v4i zero = {0, 0, 0, 0};
+    const uint32_t PS = (uint32_t)p.PS;
+    const uint8_t *Sc = (EPI == EPI_DECAY) ? Qt : At;
+#define CAT_OBLOCK(M)                                                                              \
+    if ((M) < count) {                                                                             \
+        constexpr int W0 = ((M) & 1) ? (M) - 1 : (M);                                              \
+        const v4i &bv = ((M) & 1) ? bvo : bve;                                                     \
+        const v4i ca = __builtin_amdgcn_mfma_i32_16x16x64_i8(window4<W0>(Ha), bv, zero, 0, 0, 0);  \
+        const v4i cb = __builtin_amdgcn_mfma_i32_16x16x64_i8(window4<W0>(Hb), bv, zero, 0, 0, 0);  \
+        const uint32_t co = c_off + (uint32_t)(16 * (rb0 + (M))) * PS;                             \
+        const uint32_t sa = *reinterpret_cast<const uint32_t *>(Sc + co);                          \
+        const uint32_t sb = *reinterpret_cast<const uint32_t *>(Sc + co + 16);                     \
+        const int grow = gr0 + 16 * (M);                                                           \
+        uint32_t rowm = 0xFFFFFFFFu;                                                               \
+        if (MASKED) rowm = ((unsigned)grow < (unsigned)p.H) ? 0xFFFFFFFFu : 0u;                    \
+        uint32_t ala, alb;                                                                         \
+        const uint32_t na = transition4<EPI>(ca, sa, rowm & cma, p.rc, &ala);                      \
+        const uint32_t nb = transition4<EPI>(cb, sb, rowm & cmb, p.rc, &alb);                      \
+        if constexpr (LAST) {                                                                      \
+            const uint32_t go = goff0 + (uint32_t)(16 * (M)) * (uint32_t)p.pitch;                  \
+            if (!MASKED || rowm) {                                                                 \
+                if (!MASKED || (unsigned)gca < (unsigned)p.pitch) *(gdword *)(p.dst + go) = na;    \
+                if (!MASKED || (unsigned)(gca + 16) < (unsigned)p.pitch) *(gdword *)(p.dst + go + 16) = nb; \
+            }                                                                                      \
+        } else if constexpr (EPI == EPI_DECAY) {                                                   \
+            *reinterpret_cast<uint32_t *>(Qt + co) = na;                                           \
+            *reinterpret_cast<uint32_t *>(Qt + co + 16) = nb;                                      \
+            *reinterpret_cast<uint32_t *>(At + co) = ala;                                          \
+            *reinterpret_cast<uint32_t *>(At + co + 16) = alb;                                     \
+        } else {                                                                                   \
+            *reinterpret_cast<uint32_t *>(At + co) = na;                                           \
+            *reinterpret_cast<uint32_t *>(At + co + 16) = nb;                                      \
+        }                                                                                          \
+    }
+    CAT_OBLOCK(0) CAT_OBLOCK(1) CAT_OBLOCK(2) CAT_OBLOCK(3) CAT_OBLOCK(4) CAT_OBLOCK(5)
+    CAT_OBLOCK(6) CAT_OBLOCK(7) CAT_OBLOCK(8) CAT_OBLOCK(9) CAT_OBLOCK(10) CAT_OBLOCK(11)
+    CAT_OBLOCK(12) CAT_OBLOCK(13)
+#undef CAT_OBLOCK
+}
+
+template <int EPI, bool MASKED>
+__device__ __forceinline__ void cat_steps(const CatParams &p, uint8_t *At, uint8_t *Qt, int gi0, int gj0, int wave,
+                                          int nwaves, int lane) {
+    const int li = lane & 15, lg = lane >> 4;
+    const v4i bh0 = band_h(p.r, 0, lane);
+    const v4i bh1 = band_h(p.r, 1, lane);
+    const v4i bve = band_v(p.r, 0, lane);   // window slots 0, 1, 2 = blocks m-1, m, m+1
+    const v4i bvo = band_v(p.r, 1, lane);   // window slots 1, 2, 3 = blocks m-1, m, m+1
+    const uint32_t PS = (uint32_t)p.PS;
+    const int L = p.L;
+    (void)nwaves;
+    for (int t = 1; t <= p.T; ++t) {
+        const bool last = (t == p.T);
+        const StepGeom g = step_geom(p, t);
+        const int items = g.nstrips * g.nseg;
+        int j0 = 0, rb0 = 0, count = 0;
+        if (wave < items) {
+            const int strip = wave % g.nstrips;
+            const int seg = wave / g.nstrips;
+            const int mb_lo = seg * g.seglen;
+            const int mb_hi = min(g.nrb, mb_lo + g.seglen);
+            j0 = -g.E + 32 * strip;
+            rb0 = -(g.E >> 4) + mb_lo;
+            count = max(0, mb_hi - mb_lo);
+        }
+        v16i Ha, Hb;
+        // LDS offsets of this lane's A chunk (row li of a block, 16 bytes at column
+        // j0 - 16 + 16 lg) and centre dword (row li, column j0 + 4 lg), block row 0
+        const uint32_t a_off = (uint32_t)((L + li) * (int)PS + (L + j0 - 16 + 16 * lg));
+        const uint32_t c_off = (uint32_t)((L + li) * (int)PS + (L + j0 + 4 * lg));
+        if (count > 0) phase_a(At, a_off, PS, rb0, count, bh0, bh1, Ha, Hb);
+        if (!last) __syncthreads();   // every read of the old states precedes any in-place write
+        if (count > 0) {
+            const int gca = gj0 + j0 + 4 * lg;
+            uint32_t cma = 0xFFFFFFFFu, cmb = 0xFFFFFFFFu;
+            if constexpr (MASKED) {
+                cma = col_mask(gca, p.W);
+                cmb = col_mask(gca + 16, p.W);
+            }
+            const int gr0 = gi0 + 16 * rb0 + li;
+            const uint32_t goff0 = (uint32_t)(gr0 * p.pitch + gca);
+            if (last)
+                phase_b<EPI, MASKED, true>(p, At, Qt, c_off, rb0, count, gr0, goff0, gca, cma, cmb, bve, bvo, Ha, Hb);
+            else
+                phase_b<EPI, MASKED, false>(p, At, Qt, c_off, rb0, count, gr0, goff0, gca, cma, cmb, bve, bvo, Ha, Hb);
+        }
+        if (!last) __syncthreads();   // new states complete before the next step reads them
+    }
+}
+
 template <int EPI>
 __global__ void __launch_bounds__(1024) cat_step_i8(CatParams p) {
     extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
     const int tid = threadIdx.x;
     const int lane = tid & 63;
-    const int wave = tid >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform: keeps item code scalar
     const int nwaves = blockDim.x >> 6;
-    const int li = lane & 15, lg = lane >> 4;
     const int PS = p.PS;
     const int L = p.L;
-    const size_t tile_bytes = (size_t)p.lds_rows * PS;
-    const bool multi = p.T > 1;
-    // LDS tiles: alive maps A[0..1] and, for decay, state maps Q[0..1]
-    uint8_t *A0 = lds;
-    uint8_t *A1 = multi ? lds + tile_bytes : lds;
-    uint8_t *Q0 = lds + (multi ? 2 : 1) * tile_bytes;
-    uint8_t *Q1 = multi ? Q0 + tile_bytes : Q0;
+    const uint32_t tile_bytes = (uint32_t)p.lds_rows * (uint32_t)PS;
+    // LDS: alive map A, and for decay rules the state map Q; both updated in place
+    uint8_t *At = lds;
+    uint8_t *Qt = lds + tile_bytes;
 
     const int gi0 = blockIdx.y * p.TH;
     const int gj0 = blockIdx.x * p.TW;
 
-    // ---- load the tile + margin (16-byte vectors, zero outside the grid)
+    // ---- load tile + margin with 16-byte vectors (zero outside the grid), 8 loads in flight
     {
         const int vpr = (p.TW + 2 * L) >> 4;
-        const int nvec = p.lds_rows * vpr;
-        for (int v = tid; v < nvec; v += blockDim.x) {
-            int lr = v / vpr;
-            int lc = (v - lr * vpr) << 4;
-            int gr = gi0 - L + lr;
-            int gc = gj0 - L + lc;
-            uint4 x = make_uint4(0, 0, 0, 0);
-            if ((unsigned)gr < (unsigned)p.H && (unsigned)gc < (unsigned)p.pitch)
-                x = *reinterpret_cast<const uint4 *>(p.src + (size_t)gr * p.pitch + gc);
-            size_t off = (size_t)lr * PS + lc;
-            if constexpr (EPI == EPI_DECAY) {
-                uint4 a = make_uint4(alive_of(x.x), alive_of(x.y), alive_of(x.z), alive_of(x.w));
-                *reinterpret_cast<uint4 *>(A0 + off) = a;
-                *reinterpret_cast<uint4 *>(Q0 + off) = x;
-                if (multi) {
-                    *reinterpret_cast<uint4 *>(A1 + off) = a;
-                    *reinterpret_cast<uint4 *>(Q1 + off) = x;
+        const int nvec = (p.TH + 2 * L) * vpr;
+        const int nthr = blockDim.x;
+        for (int v0 = tid; v0 < nvec; v0 += 8 * nthr) {
+            uint4 x[8];
+            uint32_t off[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                int v = v0 + k * nthr;
+                x[k] = make_uint4(0, 0, 0, 0);
+                off[k] = 0xFFFFFFFFu;
+                if (v < nvec) {
+                    int lr = v / vpr;
+                    int lc = (v - lr * vpr) << 4;
+                    int gr = gi0 - L + lr;
+                    int gc = gj0 - L + lc;
+                    off[k] = (uint32_t)(lr * PS + lc);
+                    if ((unsigned)gr < (unsigned)p.H && (unsigned)gc < (unsigned)p.pitch)
+                        x[k] = *reinterpret_cast<const uint4 *>(p.src + (size_t)gr * p.pitch + gc);
                 }
-            } else {
-                *reinterpret_cast<uint4 *>(A0 + off) = x;
-                if (multi) *reinterpret_cast<uint4 *>(A1 + off) = x;
+            }
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                if (off[k] == 0xFFFFFFFFu) continue;
+                if constexpr (EPI == EPI_DECAY) {
+                    uint4 a = make_uint4(alive_of(x[k].x), alive_of(x[k].y), alive_of(x[k].z), alive_of(x[k].w));
+                    *reinterpret_cast<uint4 *>(At + off[k]) = a;
+                    *reinterpret_cast<uint4 *>(Qt + off[k]) = x[k];
+                } else {
+                    *reinterpret_cast<uint4 *>(At + off[k]) = x[k];
+                }
             }
         }
     }
-
-    const v4i bh0 = band_h(p.r, 0, lane);
-    const v4i bh1 = band_h(p.r, 1, lane);
-    const v4i bv0 = band_v(p.r, 0, lane);
-    const v4i bv1 = band_v(p.r, 1, lane);
-    const v4i bv2 = band_v(p.r, 2, lane);
-    const v4i bv3 = band_v(p.r, 3, lane);
-    const v4i zero = {0, 0, 0, 0};
     __syncthreads();
 
-    int cur = 0;
-    for (int t = 1; t <= p.T; ++t) {
-        const bool last = (t == p.T);
-        const int E = (p.r * (p.T - t) + 15) & ~15;
-        const int nstrips = (p.TW + 2 * E) >> 5;
-        const int nrb = (p.TH + 2 * E) >> 4;
-        const int nseg = (nwaves + nstrips - 1) / nstrips;
-        const int seglen = (nrb + nseg - 1) / nseg;
-        const int items = nstrips * nseg;
-        const uint8_t *Ac = cur ? A1 : A0;
-        uint8_t *An = cur ? A0 : A1;
-        const uint8_t *Qc = cur ? Q1 : Q0;
-        uint8_t *Qn = cur ? Q0 : Q1;
-
-        for (int it = wave; it < items; it += nwaves) {
-            const int strip = it % nstrips;
-            const int seg = it / nstrips;
-            const int mb_lo = seg * seglen;
-            const int mb_hi = min(nrb, mb_lo + seglen);
-            if (mb_lo >= mb_hi) continue;
-            const int j0 = -E + 32 * strip;           // strip's first column, tile-relative
-            const int rb0 = -(E >> 4) + mb_lo;        // first output row block, tile-relative
-            const int count = mb_hi - mb_lo;
-
-            // column masks of this lane's 4 output cells in the two halves
-            const int gca = gj0 + j0 + 4 * lg;
-            const int gcb = gca + 16;
-            const uint32_t cma = col_mask(gca, p.W);
-            const uint32_t cmb = col_mask(gcb, p.W);
-
-            // LDS address of this lane's 16-byte A chunk for H block b:
-            // row 16 b + li, columns j0 - 16 + 16 lg .. + 16
-            const uint8_t *abase = Ac + (size_t)(L + li) * PS + (L + j0 - 16 + 16 * lg);
-            auto h_block = [&](int b, uint32_t &ha, uint32_t &hb) {
-                v4i a = *reinterpret_cast<const v4i *>(abase + (ptrdiff_t)(16 * b) * PS);
-                v4i da = __builtin_amdgcn_mfma_i32_16x16x64_i8(a, bh0, zero, 0, 0, 0);
-                v4i db = __builtin_amdgcn_mfma_i32_16x16x64_i8(a, bh1, zero, 0, 0, 0);
-                ha = pack_bytes(da);
-                hb = pack_bytes(db);
-            };
-
-            // ring: slot d holds H block rb0 - 1 + d (mod 4)
-            v4i ra = zero, rbv = zero;
-            {
-                uint32_t x, y;
-                h_block(rb0 - 1, x, y);
-                ra[0] = (int32_t)x; rbv[0] = (int32_t)y;
-                h_block(rb0, x, y);
-                ra[1] = (int32_t)x; rbv[1] = (int32_t)y;
-            }
-
-            auto out_block = [&](int m, v4i ca, v4i cb) {
-                // tile-relative row of this lane's cells; columns j0 + 4 lg (+16)
-                const int rr = 16 * m + li;
-                const int gr = gi0 + rr;
-                const uint32_t rowm = ((unsigned)gr < (unsigned)p.H) ? 0xFFFFFFFFu : 0u;
-                const size_t loff = (size_t)(L + rr) * PS + (L + j0 + 4 * lg);
-                uint32_t sa, sb;
-                if constexpr (EPI == EPI_DECAY) {
-                    sa = *reinterpret_cast<const uint32_t *>(Qc + loff);
-                    sb = *reinterpret_cast<const uint32_t *>(Qc + loff + 16);
-                } else {
-                    sa = *reinterpret_cast<const uint32_t *>(Ac + loff);
-                    sb = *reinterpret_cast<const uint32_t *>(Ac + loff + 16);
-                }
-                uint32_t ala, alb;
-                uint32_t na = transition4<EPI>(ca, sa, p.rc, &ala) & (rowm & cma);
-                uint32_t nb = transition4<EPI>(cb, sb, p.rc, &alb) & (rowm & cmb);
-                if (last) {
-                    if (rowm) {
-                        uint8_t *drow = p.dst + (size_t)gr * p.pitch;
-                        if ((unsigned)gca < (unsigned)p.pitch) *reinterpret_cast<uint32_t *>(drow + gca) = na;
-                        if ((unsigned)gcb < (unsigned)p.pitch) *reinterpret_cast<uint32_t *>(drow + gcb) = nb;
-                    }
-                } else {
-                    if constexpr (EPI == EPI_DECAY) {
-                        *reinterpret_cast<uint32_t *>(Qn + loff) = na;
-                        *reinterpret_cast<uint32_t *>(Qn + loff + 16) = nb;
-                        *reinterpret_cast<uint32_t *>(An + loff) = ala & (rowm & cma);
-                        *reinterpret_cast<uint32_t *>(An + loff + 16) = alb & (rowm & cmb);
-                    } else {
-                        *reinterpret_cast<uint32_t *>(An + loff) = na;
-                        *reinterpret_cast<uint32_t *>(An + loff + 16) = nb;
-                    }
-                }
-            };
-
-            // one output row block: H block m + 1 into ring slot (q + 2) & 3, then MFMA #2
-            // with the band phase q & 3, then the transition
-#define CAT_STEP(Q)                                                                   \
-    if (q + (Q) < count) {                                                            \
-        const int m = rb0 + q + (Q);                                                  \
-        uint32_t x, y;                                                                \
-        h_block(m + 1, x, y);                                                         \
-        ra[((Q) + 2) & 3] = (int32_t)x;                                               \
-        rbv[((Q) + 2) & 3] = (int32_t)y;                                              \
-        const v4i bv = ((Q) & 3) == 0 ? bv0 : ((Q) & 3) == 1 ? bv1 : ((Q) & 3) == 2 ? bv2 : bv3; \
-        v4i ca = __builtin_amdgcn_mfma_i32_16x16x64_i8(ra, bv, zero, 0, 0, 0);       \
-        v4i cb = __builtin_amdgcn_mfma_i32_16x16x64_i8(rbv, bv, zero, 0, 0, 0);      \
-        out_block(m, ca, cb);                                                         \
-    }
-            for (int q = 0; q < count; q += 4) {
-                CAT_STEP(0)
-                CAT_STEP(1)
-                CAT_STEP(2)
-                CAT_STEP(3)
-            }
-#undef CAT_STEP
-        }
-        if (!last) __syncthreads();
-        cur ^= 1;
-    }
+    // no masking needed when every cell this workgroup computes lies inside the grid
+    const int E1 = L - 16;
+    const bool interior = gi0 - E1 >= 0 && gi0 + p.TH + E1 <= p.H && gj0 - E1 >= 0 && gj0 + p.TW + E1 <= p.W;
+    if (interior)
+        cat_steps<EPI, false>(p, At, Qt, gi0, gj0, wave, nwaves, lane);
+    else
+        cat_steps<EPI, true>(p, At, Qt, gi0, gj0, wave, nwaves, lane);
 }
 
 size_t cat_lds_bytes(const CatParams &p, int elem, int epi) {

@@ -79,21 +79,30 @@ RuleConsts make_consts(const ltl_rule_t &r, int epi) {
         ohi = std::min(hi, nmax);
     };
     int ls, hs, lb, hb;
+    uint32_t rep, top, klo_s, klo_b, khi_s, khi_b;
     if (epi == EPI_BYTE) {
         norm(r.S1 + shift, r.S2 + shift, 127, ls, hs);
         norm(r.B1, r.B2, 127, lb, hb);
-        c.klo_s = (uint32_t)(0x80 - ls) * 0x01010101u;
-        c.khi_s = (uint32_t)(0x80 + hs) * 0x01010101u;
-        c.klo_b = (uint32_t)(0x80 - lb) * 0x01010101u;
-        c.khi_b = (uint32_t)(0x80 + hb) * 0x01010101u;
+        rep = 0x01010101u;
+        top = 0x80u;
     } else if (epi == EPI_HALF) {
         norm(r.S1 + shift, r.S2 + shift, 2047, ls, hs);
         norm(r.B1, r.B2, 2047, lb, hb);
-        c.klo_s = (uint32_t)(0x8000 - ls) * 0x00010001u;
-        c.khi_s = (uint32_t)(0x8000 + hs) * 0x00010001u;
-        c.klo_b = (uint32_t)(0x8000 - lb) * 0x00010001u;
-        c.khi_b = (uint32_t)(0x8000 + hb) * 0x00010001u;
+        rep = 0x00010001u;
+        top = 0x8000u;
+    } else {
+        return c;
     }
+    klo_s = (top - (uint32_t)ls) * rep;
+    klo_b = (top - (uint32_t)lb) * rep;
+    khi_s = (top + (uint32_t)hs) * rep;
+    khi_b = (top + (uint32_t)hb) * rep;
+    // select x_s where the lane mask m = sm ^ (top * rep) is all ones (alive centre), x_b where it
+    // is zero:  x_b ^ (m & (x_s ^ x_b))  =  [x_b ^ (top*rep & D)] ^ (sm & D),  D = x_s ^ x_b
+    c.Dlo = klo_s ^ klo_b;
+    c.Klo = klo_b ^ ((top * rep) & c.Dlo);
+    c.Dhi = khi_s ^ khi_b;
+    c.Khi = khi_b ^ ((top * rep) & c.Dhi);
     return c;
 }
 
@@ -137,8 +146,10 @@ ltl_tuning_t default_tuning(const ltl_sim &s) {
     t.tile_rows = 64;
     t.tile_cols = 64;
     t.waves = 4;
+    // grow the wave count until the widest step fits (one strip segment per wave)
+    while (t.waves < 16 && !cat_shape_fits(s.rule.R, t.steps_per_launch, t.tile_rows, t.tile_cols, t.waves))
+        t.waves *= 2;
     t.use_graph = 1;
-    (void)s;
     return t;
 }
 
@@ -189,6 +200,8 @@ int32_t check_tuning(const ltl_sim &s, const ltl_tuning_t &t) {
         CatParams p = cat_params(s, t, t.steps_per_launch, nullptr, nullptr);
         size_t lds = cat_lds_bytes(p, elem_of(s.method), s.epi);
         if (lds > max_lds_bytes()) return fail(LTL_ERR_ARG, "launch shape needs " + std::to_string(lds) + " bytes of LDS");
+        if (!cat_shape_fits(s.rule.R, t.steps_per_launch, t.tile_rows, t.tile_cols, t.waves))
+            return fail(LTL_ERR_ARG, "launch shape has more strip segments than waves in some step");
     } else if (t.steps_per_launch != 1) {
         return fail(LTL_ERR_ARG, "the direct method takes one step per launch");
     }
@@ -406,6 +419,11 @@ int32_t ltl_get_tuning(ltl_sim_t *sim, ltl_tuning_t *tuning) {
     return LTL_OK;
 }
 
+static bool s_fits(const ltl_sim &s, const ltl_tuning_t &t) {
+    return s.method != LTL_DIRECT &&
+           !cat_shape_fits(s.rule.R, t.steps_per_launch, t.tile_rows, t.tile_cols, t.waves);
+}
+
 int32_t ltl_set_tuning(ltl_sim_t *sim, const ltl_tuning_t *tuning) {
     if (!sim || !tuning) return fail(LTL_ERR_ARG, "NULL argument");
     ltl_tuning_t t = *tuning;
@@ -413,7 +431,10 @@ int32_t ltl_set_tuning(ltl_sim_t *sim, const ltl_tuning_t *tuning) {
     if (t.steps_per_launch == 0) t.steps_per_launch = d.steps_per_launch;
     if (t.tile_rows == 0) t.tile_rows = d.tile_rows;
     if (t.tile_cols == 0) t.tile_cols = d.tile_cols;
-    if (t.waves == 0) t.waves = d.waves;
+    if (t.waves == 0) {  // smallest wave count (power of two) whose every step fits
+        t.waves = 1;
+        while (t.waves < 16 && s_fits(*sim, t)) t.waves *= 2;
+    }
     t.use_graph = t.use_graph ? 1 : 0;
     int32_t rc = check_tuning(*sim, t);
     if (rc != LTL_OK) return rc;
@@ -447,8 +468,9 @@ int32_t ltl_autotune(ltl_sim_t *sim, int32_t probe_steps, ltl_tuning_t *best) {
     (void)hipEventCreate(&ev0);
     (void)hipEventCreate(&ev1);
     const int Ts[] = {1, 2, 3, 4, 5, 6, 8};
-    const int tiles[][2] = {{64, 64}, {128, 64}, {64, 128}, {128, 128}, {256, 64}, {256, 128}, {128, 256}, {192, 128}};
-    const int wavess[] = {4, 8};
+    const int tiles[][2] = {{64, 64}, {96, 96}, {128, 128}, {128, 192}, {160, 160}, {192, 128},
+                            {192, 224}, {128, 224}, {224, 224}, {64, 128}};
+    const int wavess[] = {0, 8, 16};  // 0: fewest waves that fit every step
     float best_ms = 1e30f;
     ltl_tuning_t best_t = s.tuning;
     int32_t rc = LTL_OK;
@@ -458,6 +480,10 @@ int32_t ltl_autotune(ltl_sim_t *sim, int32_t probe_steps, ltl_tuning_t *best) {
             for (int wv : wavess) {
                 ltl_tuning_t t;
                 t.steps_per_launch = T; t.tile_rows = tl[0]; t.tile_cols = tl[1]; t.waves = wv; t.use_graph = 1;
+                if (wv == 0) {
+                    t.waves = 1;
+                    while (t.waves < 16 && s_fits(s, t)) t.waves *= 2;
+                }
                 std::string saved = g_err;
                 if (check_tuning(s, t) != LTL_OK) { g_err = saved; continue; }
                 clear_graphs(probe);

@@ -20,8 +20,13 @@ struct RuleConsts {
     int32_t C;             // number of states (2 for C in {0, 2})
     int32_t M;             // 1: centre counted
     int32_t s1, s2, b1, b2;  // raw rule thresholds (per-cell decay epilogue and direct kernel)
-    // SWAR constants. BYTE: per byte 0x80 - lo and 0x80 + hi. HALF: per 16 bits 0x8000 - lo, 0x8000 + hi.
-    uint32_t klo_s, klo_b, khi_s, khi_b;
+    // SWAR constants of the two-state epilogues, per lane of 8 bits (BYTE) or 16 bits (HALF):
+    // with sm = 0x80 - s per lane (0x80 dead, 0x7F alive), the per-lane offsets
+    //   klo = Klo ^ (sm & Dlo)   equal 0x80 - lo(s)
+    //   khi = Khi ^ (sm & Dhi)   equal 0x80 + hi(s)
+    // (0x8000-based for HALF), lo/hi being the birth range for s = 0 and the survival range
+    // for s = 1.
+    uint32_t Klo, Dlo, Khi, Dhi;
 };
 
 struct CatParams {
@@ -60,9 +65,27 @@ inline int cat_lds_pitch(int TW, int L, int elem_bytes) {
     return p;
 }
 
+// The tile is updated in place: one alive map, plus a state map for decay rules.
 inline int cat_tiles_in_lds(int T, int epi) {
-    int per_step = (epi == EPI_DECAY) ? 2 : 1;  // alive tile (+ state tile for decay)
-    return per_step * (T > 1 ? 2 : 1);
+    (void)T;
+    return (epi == EPI_DECAY) ? 2 : 1;
+}
+
+// Longest 16-row run of output blocks one wave handles in one step.
+#define CAT_MAXC 14
+
+// Whether a launch shape can run: in every step of a T-step launch the strips x segments
+// must not outnumber the waves (each wave keeps one item's H blocks in registers across the
+// barrier that separates the reads of the old states from the in-place writes).
+inline bool cat_shape_fits(int r, int T, int TH, int TW, int waves) {
+    for (int t = 1; t <= T; ++t) {
+        int E = roundup(r * (T - t), 16);
+        int nstrips = (TW + 2 * E) / 32;
+        int nrb = (TH + 2 * E) / 16;
+        int nseg = (nrb + CAT_MAXC - 1) / CAT_MAXC;
+        if (nstrips * nseg > waves) return false;
+    }
+    return true;
 }
 
 // Launchers (return the HIP status of the launch).

@@ -99,9 +99,9 @@ def test_shapes(ltl, shape, method):
 def test_temporal_blocking(ltl, T, r):
     rule = inputs.sweep_rule(r)
     g0 = inputs.bernoulli_grid(200, 333, 0.5, seed=100 + r)
-    tuning = dict(steps_per_launch=T, tile_rows=64, tile_cols=64, waves=4)
+    tuning = dict(steps_per_launch=T, tile_rows=64, tile_cols=64, waves=0)
     margin = -(-r * (T - 1) // 16) * 16 + 16
-    lds = 2 * (64 + 2 * margin) * (64 + 2 * margin + 16)
+    lds = (64 + 2 * margin) * (64 + 2 * margin + 16)
     if lds > 160 * 1024:
         # the launch shape does not fit the 160 KB LDS: the library must refuse it
         with pytest.raises(ltl.LtlError) as e:
@@ -111,13 +111,24 @@ def test_temporal_blocking(ltl, T, r):
     run_and_compare(ltl, g0, rule, "cat_i8", 9, tuning=tuning)
 
 
-@pytest.mark.parametrize("tile", [(16, 32, 1), (32, 64, 2), (64, 64, 4), (128, 128, 8), (48, 96, 3), (256, 128, 16)])
+@pytest.mark.parametrize("tile", [(16, 32), (32, 64), (64, 64), (128, 128), (48, 96), (256, 128), (128, 256), (80, 224)])
 def test_tile_shapes(ltl, tile):
     rule = inputs.Rule(7, 0, 1, 56, 101, 60, 76)
     g0 = inputs.bernoulli_grid(301, 299, 0.5, seed=5)
     for T in (1, 3):
-        tuning = dict(steps_per_launch=T, tile_rows=tile[0], tile_cols=tile[1], waves=tile[2])
+        tuning = dict(steps_per_launch=T, tile_rows=tile[0], tile_cols=tile[1], waves=0)
         run_and_compare(ltl, g0, rule, "cat_i8", 7, tuning=tuning)
+
+
+def test_wave_count_must_cover_the_strips(ltl):
+    g0 = inputs.bernoulli_grid(64, 64, 0.5, seed=1)
+    sim = ltl.Simulation(gpu_grid(g0), inputs.Rule(7, 0, 1, 56, 101, 60, 76), "cat_i8")
+    with pytest.raises(ltl.LtlError) as e:
+        sim.set_tuning(steps_per_launch=3, tile_rows=64, tile_cols=128, waves=2)
+    assert e.value.code == ltl.LTL_ERR_ARG
+    sim.set_tuning(steps_per_launch=3, tile_rows=64, tile_cols=128, waves=0)
+    assert sim.tuning()["waves"] == 8
+    sim.close()
 
 
 def test_decay_multistep(ltl):
@@ -131,7 +142,7 @@ def test_decay_multistep(ltl):
 def test_resume_and_graph_chunks(ltl):
     rule = inputs.BOSCO_M1
     g0 = inputs.bernoulli_grid(260, 270, 0.5, seed=77)
-    tuning = dict(steps_per_launch=3, tile_rows=64, tile_cols=64, waves=4)
+    tuning = dict(steps_per_launch=3, tile_rows=64, tile_cols=64, waves=0)
     run_and_compare(ltl, g0, rule, "cat_i8", 17, tuning=tuning, chunks=[0, 5, 1, 11, 0])
     run_and_compare(ltl, g0, rule, "cat_i8", 17, tuning=dict(tuning, use_graph=0), chunks=[5, 12])
 
