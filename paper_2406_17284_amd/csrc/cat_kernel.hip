@@ -122,47 +122,6 @@ __device__ __forceinline__ uint32_t alive_of(uint32_t s) {
     return (~y & 0x80808080u) >> 7;
 }
 
-// Band operands. Lane (n = lane % 16, g = lane / 16); byte e of dword d is K slot 16 g + 4 d + e.
-//  MFMA #1, half h (output columns 16 h .. 16 h + 15 of a 32-column strip whose 64-column
-//  window starts 16 columns left of the strip): weight 1 iff |k - 16 - 16 h - n| <= r.
-__device__ __forceinline__ v4i band_h(int r, int half, int lane) {
-    int n = lane & 15, g = lane >> 4;
-    v4i b;
-#pragma unroll
-    for (int d = 0; d < 4; ++d) {
-        uint32_t w = 0;
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            int k = 16 * g + 4 * d + e;
-            int dist = k - 16 - 16 * half - n;
-            w |= (uint32_t)((dist >= -r && dist <= r) ? 1 : 0) << (8 * e);
-        }
-        b[d] = (int32_t)w;
-    }
-    return b;
-}
-
-//  MFMA #2, ring phase p: dword d of every lane holds the H block whose distance to the
-//  output block is delta = ((d - p) & 3) - 1 (in units of 16 rows); byte e of that dword is
-//  H row 16 delta + 4 g + e relative to the output block. Weight 1 iff |row - n| <= r.
-__device__ __forceinline__ v4i band_v(int r, int phase, int lane) {
-    int n = lane & 15, g = lane >> 4;
-    v4i b;
-#pragma unroll
-    for (int d = 0; d < 4; ++d) {
-        int delta = ((d - phase) & 3) - 1;
-        uint32_t w = 0;
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            int row = 16 * delta + 4 * g + e;
-            int dist = row - n;
-            w |= (uint32_t)((dist >= -r && dist <= r) ? 1 : 0) << (8 * e);
-        }
-        b[d] = (int32_t)w;
-    }
-    return b;
-}
-
 // Geometry of one step: strips of 32 columns, each cut into `nseg` row segments of at most
 // CAT_MAXC 16-row blocks. Every segment is one wave's work item; a step needs
 // items <= waves (the host planner checks this for every step of a launch).
@@ -193,26 +152,41 @@ __device__ __forceinline__ v4i window4(const v16i &h) {
 }
 
 // Phase A of one item: H (horizontal band sums) of blocks rb0 - 1 .. rb0 + count for both
-// 16-column halves of the strip, packed to bytes, in registers.
+// 16-column halves of the strip, packed to bytes, in registers. Software-pipelined in pairs of
+// blocks: the A chunks of the next pair are read from LDS before the MFMAs of this pair run.
 __device__ __forceinline__ void phase_a(const uint8_t *At, uint32_t a_off, uint32_t PS, int rb0, int count,
                                         const v4i &bh0, const v4i &bh1, v16i &Ha, v16i &Hb) {
     const v4i zero = {0, 0, 0, 0};
-#define CAT_HBLOCK(K)                                                                              \
-    if ((K) < count + 2) {                                                                         \
-        v4i a = *reinterpret_cast<const v4i *>(At + (a_off + (uint32_t)(16 * (rb0 - 1 + (K))) * PS)); \
-        v4i da = __builtin_amdgcn_mfma_i32_16x16x64_i8(a, bh0, zero, 0, 0, 0);                     \
-        v4i db = __builtin_amdgcn_mfma_i32_16x16x64_i8(a, bh1, zero, 0, 0, 0);                     \
+    const int nh = count + 2;
+    v4i a[4];
+#define CAT_LDA(K) a[(K) & 3] = *reinterpret_cast<const v4i *>(At + (a_off + (uint32_t)(16 * (rb0 - 1 + (K))) * PS));
+#define CAT_HB(K)                                                                                  \
+    {                                                                                              \
+        v4i da = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[(K) & 3], bh0, zero, 0, 0, 0);            \
+        v4i db = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[(K) & 3], bh1, zero, 0, 0, 0);            \
         Ha[(K)] = (int32_t)pack_bytes(da);                                                         \
         Hb[(K)] = (int32_t)pack_bytes(db);                                                         \
     }
-    CAT_HBLOCK(0) CAT_HBLOCK(1) CAT_HBLOCK(2) CAT_HBLOCK(3) CAT_HBLOCK(4) CAT_HBLOCK(5)
-    CAT_HBLOCK(6) CAT_HBLOCK(7) CAT_HBLOCK(8) CAT_HBLOCK(9) CAT_HBLOCK(10) CAT_HBLOCK(11)
-    CAT_HBLOCK(12) CAT_HBLOCK(13) CAT_HBLOCK(14) CAT_HBLOCK(15)
-#undef CAT_HBLOCK
+#define CAT_APAIR(P)                                                                               \
+    if (2 * (P) < nh) {                                                                            \
+        if (2 * (P) + 2 < nh) {                                                                    \
+            CAT_LDA(2 * (P) + 2)                                                                   \
+            if (2 * (P) + 3 < nh) CAT_LDA(2 * (P) + 3)                                             \
+        }                                                                                          \
+        CAT_HB(2 * (P))                                                                            \
+        if (2 * (P) + 1 < nh) CAT_HB(2 * (P) + 1)                                                  \
+    }
+    CAT_LDA(0) CAT_LDA(1)
+    CAT_APAIR(0) CAT_APAIR(1) CAT_APAIR(2) CAT_APAIR(3) CAT_APAIR(4) CAT_APAIR(5) CAT_APAIR(6) CAT_APAIR(7)
+#undef CAT_APAIR
+#undef CAT_HB
+#undef CAT_LDA
 }
 
 // Phase B of one item: vertical band products, transition, store (in place in LDS for an
-// intermediate step, to the output grid on the last step of the launch).
+// intermediate step, to the output grid on the last step of the launch). Software-pipelined in
+// pairs of output blocks: the MFMAs and centre-state reads of the next pair are issued before
+// the VALU transition of this pair, so their latencies overlap it.
 template <int EPI, bool MASKED, bool LAST>
 __device__ __forceinline__ void phase_b(const CatParams &p, uint8_t *At, uint8_t *Qt, uint32_t c_off, int rb0,
                                         int count, int gr0, uint32_t goff0, int gca, uint32_t cma, uint32_t cmb,
@@ -220,21 +194,29 @@ __device__ __forceinline__ void phase_b(const CatParams &p, uint8_t *At, uint8_t
     const v4i zero = {0, 0, 0, 0};
     const uint32_t PS = (uint32_t)p.PS;
     const uint8_t *Sc = (EPI == EPI_DECAY) ? Qt : At;
-#define CAT_OBLOCK(M)                                                                              \
-    if ((M) < count) {                                                                             \
+    v4i ca[4], cb[4];
+    uint32_t sa[4], sb[4];
+    // counts and centre states of block M (slot M & 3)
+#define CAT_ISSUE(M)                                                                               \
+    {                                                                                              \
         constexpr int W0 = ((M) & 1) ? (M) - 1 : (M);                                              \
         const v4i &bv = ((M) & 1) ? bvo : bve;                                                     \
-        const v4i ca = __builtin_amdgcn_mfma_i32_16x16x64_i8(window4<W0>(Ha), bv, zero, 0, 0, 0);  \
-        const v4i cb = __builtin_amdgcn_mfma_i32_16x16x64_i8(window4<W0>(Hb), bv, zero, 0, 0, 0);  \
+        ca[(M) & 3] = __builtin_amdgcn_mfma_i32_16x16x64_i8(window4<W0>(Ha), bv, zero, 0, 0, 0);   \
+        cb[(M) & 3] = __builtin_amdgcn_mfma_i32_16x16x64_i8(window4<W0>(Hb), bv, zero, 0, 0, 0);   \
         const uint32_t co = c_off + (uint32_t)(16 * (rb0 + (M))) * PS;                             \
-        const uint32_t sa = *reinterpret_cast<const uint32_t *>(Sc + co);                          \
-        const uint32_t sb = *reinterpret_cast<const uint32_t *>(Sc + co + 16);                     \
+        sa[(M) & 3] = *reinterpret_cast<const uint32_t *>(Sc + co);                                \
+        sb[(M) & 3] = *reinterpret_cast<const uint32_t *>(Sc + co + 16);                           \
+    }
+    // transition and store of block M
+#define CAT_FINISH(M)                                                                              \
+    {                                                                                              \
+        const uint32_t co = c_off + (uint32_t)(16 * (rb0 + (M))) * PS;                             \
         const int grow = gr0 + 16 * (M);                                                           \
         uint32_t rowm = 0xFFFFFFFFu;                                                               \
         if (MASKED) rowm = ((unsigned)grow < (unsigned)p.H) ? 0xFFFFFFFFu : 0u;                    \
         uint32_t ala, alb;                                                                         \
-        const uint32_t na = transition4<EPI>(ca, sa, rowm & cma, p.rc, &ala);                      \
-        const uint32_t nb = transition4<EPI>(cb, sb, rowm & cmb, p.rc, &alb);                      \
+        const uint32_t na = transition4<EPI>(ca[(M) & 3], sa[(M) & 3], rowm & cma, p.rc, &ala);    \
+        const uint32_t nb = transition4<EPI>(cb[(M) & 3], sb[(M) & 3], rowm & cmb, p.rc, &alb);    \
         if constexpr (LAST) {                                                                      \
             const uint32_t go = goff0 + (uint32_t)(16 * (M)) * (uint32_t)p.pitch;                  \
             if (!MASKED || rowm) {                                                                 \
@@ -251,23 +233,30 @@ __device__ __forceinline__ void phase_b(const CatParams &p, uint8_t *At, uint8_t
             *reinterpret_cast<uint32_t *>(At + co + 16) = nb;                                      \
         }                                                                                          \
     }
-    CAT_OBLOCK(0) CAT_OBLOCK(1) CAT_OBLOCK(2) CAT_OBLOCK(3) CAT_OBLOCK(4) CAT_OBLOCK(5)
-    CAT_OBLOCK(6) CAT_OBLOCK(7) CAT_OBLOCK(8) CAT_OBLOCK(9) CAT_OBLOCK(10) CAT_OBLOCK(11)
-    CAT_OBLOCK(12) CAT_OBLOCK(13)
-#undef CAT_OBLOCK
+    // pair P = blocks 2P, 2P + 1; block `count` (one past the item) may be issued: its window
+    // and centre row are inside the tile and nothing is stored for it
+#define CAT_BPAIR(P, NEXT)                                                                         \
+    if (2 * (P) < count) {                                                                         \
+        if (NEXT && 2 * (P) + 2 < count) { CAT_ISSUE(2 * (P) + 2) CAT_ISSUE(2 * (P) + 3) }         \
+        CAT_FINISH(2 * (P))                                                                        \
+        if (2 * (P) + 1 < count) CAT_FINISH(2 * (P) + 1)                                           \
+    }
+    CAT_ISSUE(0) CAT_ISSUE(1)
+    CAT_BPAIR(0, 1) CAT_BPAIR(1, 1) CAT_BPAIR(2, 1) CAT_BPAIR(3, 1) CAT_BPAIR(4, 1) CAT_BPAIR(5, 1)
+    CAT_BPAIR(6, 0)
+#undef CAT_BPAIR
+#undef CAT_FINISH
+#undef CAT_ISSUE
 }
 
+// T steps of one tile, in place in LDS (the last step writes the output grid).
+// bve: window slots 0, 1, 2 = blocks m-1, m, m+1; bvo: slots 1, 2, 3.
 template <int EPI, bool MASKED>
 __device__ __forceinline__ void cat_steps(const CatParams &p, uint8_t *At, uint8_t *Qt, int gi0, int gj0, int wave,
-                                          int nwaves, int lane) {
+                                          int lane, const v4i &bh0, const v4i &bh1, const v4i &bve, const v4i &bvo) {
     const int li = lane & 15, lg = lane >> 4;
-    const v4i bh0 = band_h(p.r, 0, lane);
-    const v4i bh1 = band_h(p.r, 1, lane);
-    const v4i bve = band_v(p.r, 0, lane);   // window slots 0, 1, 2 = blocks m-1, m, m+1
-    const v4i bvo = band_v(p.r, 1, lane);   // window slots 1, 2, 3 = blocks m-1, m, m+1
     const uint32_t PS = (uint32_t)p.PS;
     const int L = p.L;
-    (void)nwaves;
     for (int t = 1; t <= p.T; ++t) {
         const bool last = (t == p.T);
         const StepGeom g = step_geom(p, t);
@@ -307,84 +296,119 @@ __device__ __forceinline__ void cat_steps(const CatParams &p, uint8_t *At, uint8
     }
 }
 
+// Stream the (TH + 2L) x PS window of tile `tile` into the LDS buffer `buf` with direct
+// global->LDS loads: wave w moves KiB chunks w, w + nwaves, ...; lane l of a chunk carries
+// the 16 bytes at buffer offset 1024 c + 16 l. Cells outside the grid come from the zero page.
+__device__ __forceinline__ void issue_tile_load(const CatParams &p, int gi0, int gj0, uint8_t *buf, int wave,
+                                                int nwaves, int lane, float inv_ps) {
+    const int rows = p.TH + 2 * p.L;
+    const int nchunks = p.lds_tile >> 10;
+    for (int c = wave; c < nchunks; c += nwaves) {
+        const int o = (c << 10) + (lane << 4);
+        int lr = (int)((float)o * inv_ps);
+        int lc = o - lr * p.PS;
+        if (lc < 0) { lr -= 1; lc += p.PS; }
+        if (lc >= p.PS) { lr += 1; lc -= p.PS; }
+        const int gr = gi0 - p.L + lr;
+        const int gc = gj0 - p.L + lc;
+        const uint8_t *g = p.zero;
+        if (lr < rows && (unsigned)gr < (unsigned)p.H && (unsigned)gc < (unsigned)p.pitch)
+            g = p.src + (size_t)gr * p.pitch + gc;
+        // The load is issued from inline assembly: the compiler cannot see which LDS bytes an
+        // LDS-DMA writes, so for its own builtin it would make every later LDS access wait for
+        // all outstanding vector-memory operations. The caller waits (vmcnt(0) + barrier) before
+        // the buffer is read.
+        const uint32_t lds_addr = (uint32_t)(uintptr_t)(buf + (c << 10));
+        asm volatile("s_mov_b32 m0, %0\n\tglobal_load_lds_dwordx4 %1, off"
+                     :
+                     : "s"(__builtin_amdgcn_readfirstlane(lds_addr)), "v"(g)
+                     : "memory", "m0");
+    }
+}
+
+// One workgroup per tile (workgroups of one XCD take consecutive tiles, so the halos of
+// neighbouring tiles meet in that XCD's L2): load the window with direct LDS loads, then T
+// steps in place.
 template <int EPI>
-__global__ void __launch_bounds__(1024) cat_step_i8(CatParams p) {
-    extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) cat_step_i8(CatParams p) {
+    extern __shared__ __attribute__((aligned(1024))) uint8_t lds[];
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform: keeps item code scalar
     const int nwaves = blockDim.x >> 6;
-    const int PS = p.PS;
-    const int L = p.L;
-    const uint32_t tile_bytes = (uint32_t)p.lds_rows * (uint32_t)PS;
-    // LDS: alive map A, and for decay rules the state map Q; both updated in place
-    uint8_t *At = lds;
-    uint8_t *Qt = lds + tile_bytes;
+    const uint32_t tile_bytes = (uint32_t)p.lds_tile;
 
-    const int gi0 = blockIdx.y * p.TH;
-    const int gj0 = blockIdx.x * p.TW;
+    const int ntiles = p.ntx * p.nty;
+    const int nb = gridDim.x;
+    const int bid = blockIdx.x;
+    const int tile = (nb & 7) ? bid : (bid & 7) * (nb >> 3) + (bid >> 3);
+    if (tile >= ntiles) return;
+    const int gi0 = (tile / p.ntx) * p.TH;
+    const int gj0 = (tile % p.ntx) * p.TW;
 
-    // ---- load tile + margin with 16-byte vectors (zero outside the grid), 8 loads in flight
-    {
-        const int vpr = (p.TW + 2 * L) >> 4;
-        const int nvec = (p.TH + 2 * L) * vpr;
-        const int nthr = blockDim.x;
-        for (int v0 = tid; v0 < nvec; v0 += 8 * nthr) {
-            uint4 x[8];
-            uint32_t off[8];
-#pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                int v = v0 + k * nthr;
-                x[k] = make_uint4(0, 0, 0, 0);
-                off[k] = 0xFFFFFFFFu;
-                if (v < nvec) {
-                    int lr = v / vpr;
-                    int lc = (v - lr * vpr) << 4;
-                    int gr = gi0 - L + lr;
-                    int gc = gj0 - L + lc;
-                    off[k] = (uint32_t)(lr * PS + lc);
-                    if ((unsigned)gr < (unsigned)p.H && (unsigned)gc < (unsigned)p.pitch)
-                        x[k] = *reinterpret_cast<const uint4 *>(p.src + (size_t)gr * p.pitch + gc);
-                }
-            }
-#pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                if (off[k] == 0xFFFFFFFFu) continue;
-                if constexpr (EPI == EPI_DECAY) {
-                    uint4 a = make_uint4(alive_of(x[k].x), alive_of(x[k].y), alive_of(x[k].z), alive_of(x[k].w));
-                    *reinterpret_cast<uint4 *>(At + off[k]) = a;
-                    *reinterpret_cast<uint4 *>(Qt + off[k]) = x[k];
-                } else {
-                    *reinterpret_cast<uint4 *>(At + off[k]) = x[k];
-                }
-            }
-        }
-    }
+    issue_tile_load(p, gi0, gj0, lds, wave, nwaves, lane, 1.0f / (float)p.PS);
+    const v4i *bt = reinterpret_cast<const v4i *>(p.bands);
+    const v4i bh0 = bt[0 * 64 + lane], bh1 = bt[1 * 64 + lane];
+    const v4i bve = bt[2 * 64 + lane], bvo = bt[3 * 64 + lane];
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();
 
-    // no masking needed when every cell this workgroup computes lies inside the grid
-    const int E1 = L - 16;
+    uint8_t *At = lds;
+    uint8_t *Qt = lds;
+    if constexpr (EPI == EPI_DECAY) {
+        // the window holds states; derive the alive map the band products read
+        uint8_t *Alive = lds + tile_bytes;
+        const int nvec = (p.TH + 2 * p.L) * p.PS >> 4;
+        for (int v = tid; v < nvec; v += blockDim.x) {
+            uint4 q = *reinterpret_cast<const uint4 *>(Qt + (v << 4));
+            *reinterpret_cast<uint4 *>(Alive + (v << 4)) =
+                make_uint4(alive_of(q.x), alive_of(q.y), alive_of(q.z), alive_of(q.w));
+        }
+        __syncthreads();
+        At = Alive;
+    }
+    // no masking needed when every cell this tile computes lies inside the grid
+    const int E1 = p.L - 16;
     const bool interior = gi0 - E1 >= 0 && gi0 + p.TH + E1 <= p.H && gj0 - E1 >= 0 && gj0 + p.TW + E1 <= p.W;
     if (interior)
-        cat_steps<EPI, false>(p, At, Qt, gi0, gj0, wave, nwaves, lane);
+        cat_steps<EPI, false>(p, At, Qt, gi0, gj0, wave, lane, bh0, bh1, bve, bvo);
     else
-        cat_steps<EPI, true>(p, At, Qt, gi0, gj0, wave, nwaves, lane);
+        cat_steps<EPI, true>(p, At, Qt, gi0, gj0, wave, lane, bh0, bh1, bve, bvo);
 }
 
 size_t cat_lds_bytes(const CatParams &p, int elem, int epi) {
     (void)elem;
-    return (size_t)cat_tiles_in_lds(p.T, epi) * p.lds_rows * p.PS;
+    return (size_t)cat_tiles_in_lds(p.T, epi) * (size_t)p.lds_tile;
+}
+
+static const void *cat_func(int epi) {
+    if (epi == EPI_BYTE) return (const void *)&cat_step_i8<EPI_BYTE>;
+    if (epi == EPI_HALF) return (const void *)&cat_step_i8<EPI_HALF>;
+    return (const void *)&cat_step_i8<EPI_DECAY>;
+}
+
+int cat_occupancy(const CatParams &p, int elem, int epi, int waves) {
+    const void *f = cat_func(epi);
+    size_t lds = cat_lds_bytes(p, elem, epi);
+    if (lds > 65536 && hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+        return 0;
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, 64 * waves, lds) != hipSuccess) return 0;
+    return nb;
 }
 
 KernelLaunch cat_launch_shape(const CatParams &p, int elem, int epi, int waves) {
     KernelLaunch k;
-    (void)elem;
-    if (epi == EPI_BYTE) k.func = (const void *)&cat_step_i8<EPI_BYTE>;
-    else if (epi == EPI_HALF) k.func = (const void *)&cat_step_i8<EPI_HALF>;
-    else k.func = (const void *)&cat_step_i8<EPI_DECAY>;
-    k.grid = dim3((p.W + p.TW - 1) / p.TW, (p.H + p.TH - 1) / p.TH, 1);
-    k.block = dim3(64 * waves, 1, 1);
+    k.func = cat_func(epi);
     k.lds = cat_lds_bytes(p, elem, epi);
+    int dev = 0, ncu = 256;
+    if (hipGetDevice(&dev) == hipSuccess) {
+        int x = 0;
+        if (hipDeviceGetAttribute(&x, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && x > 0) ncu = x;
+    }
+    (void)ncu;
+    k.grid = dim3((unsigned)((long)p.ntx * p.nty), 1, 1);
+    k.block = dim3(64 * waves, 1, 1);
     return k;
 }
 

@@ -135,10 +135,27 @@ struct ltl_sim {
     hipStream_t stream = nullptr;
     ltl_tuning_t tuning{};
     uint32_t *dflag = nullptr;
+    uint8_t *dconst = nullptr;   // band tables for r = 1..16, then a zero page
     std::map<std::pair<int32_t, int>, hipGraphExec_t> graphs;
 };
 
 namespace {
+
+// Device constants shared by the CAT launches of a handle: the band operands of every
+// radius (band_table layout, 4 KiB each) followed by a 4 KiB zero page.
+constexpr size_t kBandBytes = LTL_BAND_TABLE_INTS * sizeof(int32_t);
+constexpr size_t kConstBytes = 16 * kBandBytes + 4096;
+
+std::vector<uint8_t> host_constants() {
+    std::vector<uint8_t> h(kConstBytes, 0);
+    for (int r = 1; r <= 16; ++r) {
+        int32_t *t = reinterpret_cast<int32_t *>(h.data() + (r - 1) * kBandBytes);
+        for (int which = 0; which < LTL_BAND_OPERANDS; ++which)
+            for (int lane = 0; lane < 64; ++lane)
+                for (int d = 0; d < 4; ++d) t[(which * 64 + lane) * 4 + d] = band_dword(r, which, lane, d);
+    }
+    return h;
+}
 
 ltl_tuning_t default_tuning(const ltl_sim &s) {
     ltl_tuning_t t;
@@ -147,7 +164,7 @@ ltl_tuning_t default_tuning(const ltl_sim &s) {
     t.tile_cols = 64;
     t.waves = 4;
     // grow the wave count until the widest step fits (one strip segment per wave)
-    while (t.waves < 16 && !cat_shape_fits(s.rule.R, t.steps_per_launch, t.tile_rows, t.tile_cols, t.waves))
+    while (t.waves < 8 && !cat_shape_fits(s.rule.R, t.steps_per_launch, t.tile_rows, t.tile_cols, t.waves))
         t.waves *= 2;
     t.use_graph = 1;
     return t;
@@ -168,6 +185,11 @@ CatParams cat_params(const ltl_sim &s, const ltl_tuning_t &t, int T, const uint8
     int elem_bytes = (s.method == LTL_CAT_F16) ? 2 : 1;
     p.PS = cat_lds_pitch(p.TW, p.L, elem_bytes);
     p.lds_rows = p.TH + 2 * p.L;
+    p.lds_tile = roundup(p.lds_rows * p.PS, 1024);
+    p.ntx = (s.W + p.TW - 1) / p.TW;
+    p.nty = (s.H + p.TH - 1) / p.TH;
+    p.bands = reinterpret_cast<const int32_t *>(s.dconst + (size_t)(p.r - 1) * kBandBytes);
+    p.zero = s.dconst + 16 * kBandBytes;
     p.rc = s.rc;
     return p;
 }
@@ -195,11 +217,13 @@ int32_t check_tuning(const ltl_sim &s, const ltl_tuning_t &t) {
     if (t.steps_per_launch < 1 || t.steps_per_launch > 64) return fail(LTL_ERR_ARG, "steps_per_launch must be in 1..64");
     if (t.tile_rows < 16 || t.tile_rows > 512 || t.tile_rows % 16) return fail(LTL_ERR_ARG, "tile_rows must be a multiple of 16 in 16..512");
     if (t.tile_cols < 32 || t.tile_cols > 512 || t.tile_cols % 32) return fail(LTL_ERR_ARG, "tile_cols must be a multiple of 32 in 32..512");
-    if (t.waves < 1 || t.waves > 16) return fail(LTL_ERR_ARG, "waves must be in 1..16");
+    if (t.waves < 1 || t.waves > (s.method == LTL_DIRECT ? 16 : 8)) return fail(LTL_ERR_ARG, "waves must be in 1..8");
     if (s.method != LTL_DIRECT) {
         CatParams p = cat_params(s, t, t.steps_per_launch, nullptr, nullptr);
         size_t lds = cat_lds_bytes(p, elem_of(s.method), s.epi);
         if (lds > max_lds_bytes()) return fail(LTL_ERR_ARG, "launch shape needs " + std::to_string(lds) + " bytes of LDS");
+        if (s.dconst && cat_occupancy(p, elem_of(s.method), s.epi, t.waves) < 1)
+            return fail(LTL_ERR_ARG, "launch shape does not fit on a compute unit (registers or LDS)");
         if (!cat_shape_fits(s.rule.R, t.steps_per_launch, t.tile_rows, t.tile_cols, t.waves))
             return fail(LTL_ERR_ARG, "launch shape has more strip segments than waves in some step");
     } else if (t.steps_per_launch != 1) {
@@ -371,11 +395,19 @@ int32_t ltl_create(ltl_sim_t **out, int32_t H, int32_t W, const ltl_rule_t *rule
 
     auto bail = [&](int32_t code) {
         if (s->dflag) (void)hipFree(s->dflag);
+        if (s->dconst) (void)hipFree(s->dconst);
         delete s;
         return code;
     };
     hipError_t e;
     if ((e = hipMalloc(&s->dflag, sizeof(uint32_t))) != hipSuccess) { s->dflag = nullptr; return bail(hip_fail(e, "hipMalloc")); }
+    if ((e = hipMalloc(&s->dconst, kConstBytes)) != hipSuccess) { s->dconst = nullptr; return bail(hip_fail(e, "hipMalloc")); }
+    {
+        std::vector<uint8_t> hc = host_constants();
+        if ((e = hipMemcpyAsync(s->dconst, hc.data(), kConstBytes, hipMemcpyHostToDevice, stream)) != hipSuccess)
+            return bail(hip_fail(e, "hipMemcpyAsync"));
+        if ((e = hipStreamSynchronize(stream)) != hipSuccess) return bail(hip_fail(e, "hipStreamSynchronize"));
+    }
     if ((e = hipMemsetAsync(s->dflag, 0, sizeof(uint32_t), stream)) != hipSuccess) return bail(hip_fail(e, "hipMemsetAsync"));
     if ((e = launch_validate((const uint8_t *)init, H, W, init_pitch, s->rc.C, s->dflag, stream)) != hipSuccess)
         return bail(hip_fail(e, "validate launch"));
@@ -433,7 +465,7 @@ int32_t ltl_set_tuning(ltl_sim_t *sim, const ltl_tuning_t *tuning) {
     if (t.tile_cols == 0) t.tile_cols = d.tile_cols;
     if (t.waves == 0) {  // smallest wave count (power of two) whose every step fits
         t.waves = 1;
-        while (t.waves < 16 && s_fits(*sim, t)) t.waves *= 2;
+        while (t.waves < 8 && s_fits(*sim, t)) t.waves *= 2;
     }
     t.use_graph = t.use_graph ? 1 : 0;
     int32_t rc = check_tuning(*sim, t);
@@ -463,6 +495,7 @@ int32_t ltl_autotune(ltl_sim_t *sim, int32_t probe_steps, ltl_tuning_t *best) {
     ltl_sim probe;
     probe.H = s.H; probe.W = s.W; probe.pitch = s.pitch; probe.rule = s.rule; probe.method = s.method;
     probe.epi = s.epi; probe.rc = s.rc; probe.buf[0] = scratch[0]; probe.buf[1] = scratch[1];
+    probe.dconst = s.dconst;
     probe.stream = s.stream;
     hipEvent_t ev0, ev1;
     (void)hipEventCreate(&ev0);
@@ -482,7 +515,7 @@ int32_t ltl_autotune(ltl_sim_t *sim, int32_t probe_steps, ltl_tuning_t *best) {
                 t.steps_per_launch = T; t.tile_rows = tl[0]; t.tile_cols = tl[1]; t.waves = wv; t.use_graph = 1;
                 if (wv == 0) {
                     t.waves = 1;
-                    while (t.waves < 16 && s_fits(s, t)) t.waves *= 2;
+                    while (t.waves < 8 && s_fits(s, t)) t.waves *= 2;
                 }
                 std::string saved = g_err;
                 if (check_tuning(s, t) != LTL_OK) { g_err = saved; continue; }
@@ -519,6 +552,7 @@ int32_t ltl_destroy(ltl_sim_t *sim) {
     if (!sim) return LTL_OK;
     clear_graphs(*sim);
     if (sim->dflag) (void)hipFree(sim->dflag);
+    if (sim->dconst) (void)hipFree(sim->dconst);
     delete sim;
     return LTL_OK;
 }

@@ -32,15 +32,43 @@ struct RuleConsts {
 struct CatParams {
     const uint8_t *src;
     uint8_t *dst;
-    int32_t H, W, pitch;  // grid rows, columns, row pitch (bytes)
-    int32_t r;            // radius 1..16
-    int32_t T;            // steps in this launch
-    int32_t TH, TW;       // output tile (multiples of 16 / 32)
-    int32_t L;            // LDS margin around the output tile: roundup16(r (T-1)) + 16
-    int32_t PS;           // LDS row pitch (bytes per element row)
-    int32_t lds_rows;     // TH + 2L
+    const int32_t *bands;    // band operands for radius r: [4][64 lanes][4 dwords] (band_table layout)
+    const uint8_t *zero;     // >= 16 zero bytes in device memory (source of out-of-grid loads)
+    int32_t H, W, pitch;     // grid rows, columns, row pitch (bytes)
+    int32_t r;               // radius 1..16
+    int32_t T;               // steps in this launch
+    int32_t TH, TW;          // output tile (multiples of 16 / 32)
+    int32_t L;               // LDS margin around the output tile: roundup16(r (T-1)) + 16
+    int32_t PS;              // LDS row pitch = TW + 2L + 16 (rows stored densely)
+    int32_t lds_rows;        // TH + 2L
+    int32_t lds_tile;        // bytes of one LDS tile buffer: lds_rows * PS rounded up to 1 KiB
+    int32_t ntx, nty;        // tiles across / down the grid
     RuleConsts rc;
 };
+
+// Band operands (one v4i per lane, 16 bytes, K slot 16 g + 4 d + e = byte e of dword d of lane
+// group g = lane / 16; n = lane % 16 is the output index):
+//  0, 1: MFMA #1 for the two 16-column halves of a 32-column strip whose 64-column window
+//        starts 16 columns left of the strip: weight 1 iff |k - 16 - 16 h - n| <= r;
+//  2, 3: MFMA #2, dword d holding the H block at distance ((d - p) & 3) - 1 (in 16-row
+//        blocks) from the output block, p = 0, 1: weight 1 iff |16 delta + 4 g + e - n| <= r.
+#define LTL_BAND_OPERANDS 4
+#define LTL_BAND_TABLE_INTS (LTL_BAND_OPERANDS * 64 * 4)   // per radius
+__host__ __device__ inline int32_t band_dword(int r, int which, int lane, int d) {
+    int n = lane & 15, g = lane >> 4;
+    uint32_t w = 0;
+    for (int e = 0; e < 4; ++e) {
+        int dist;
+        if (which < 2) {
+            dist = 16 * g + 4 * d + e - 16 - 16 * which - n;
+        } else {
+            int delta = ((d - (which - 2)) & 3) - 1;
+            dist = 16 * delta + 4 * g + e - n;
+        }
+        w |= (uint32_t)((dist >= -r && dist <= r) ? 1 : 0) << (8 * e);
+    }
+    return (int32_t)w;
+}
 
 struct DirectParams {
     const uint8_t *src;
@@ -58,14 +86,15 @@ inline int roundup(int x, int m) { return (x + m - 1) / m * m; }
 inline int cat_margin(int r, int T) { return roundup(r * (T - 1), 16) + 16; }
 
 inline int cat_lds_pitch(int TW, int L, int elem_bytes) {
-    // bytes per LDS row; kept = 16 (mod 32) bytes so the 16 rows of a 16-byte-per-lane
-    // operand read fall into distinct bank groups
-    int p = roundup((TW + 2 * L) * elem_bytes, 16);
-    if ((p & 31) == 0) p += 16;
-    return p;
+    // bytes per LDS row: the loaded window is TW + 2L columns (a multiple of 32) plus 16 more,
+    // so the pitch is = 16 (mod 32) and the 16 rows of a 16-byte-per-lane operand read fall
+    // into distinct bank groups; rows are stored densely so 1 KiB of consecutive LDS maps to
+    // consecutive window bytes (one direct global->LDS load per wave)
+    return (TW + 2 * L) * elem_bytes + 16;
 }
 
-// The tile is updated in place: one alive map, plus a state map for decay rules.
+// LDS tile buffers of a workgroup: the tile stepped in place, plus the alive map for decay
+// rules (the loaded tile then holds states).
 inline int cat_tiles_in_lds(int T, int epi) {
     (void)T;
     return (epi == EPI_DECAY) ? 2 : 1;
@@ -101,6 +130,8 @@ struct KernelLaunch {
     size_t lds;
 };
 KernelLaunch cat_launch_shape(const CatParams &p, int elem, int epi, int waves);
+// Resident workgroups of the CAT kernel per compute unit for this shape (0 if it cannot run).
+int cat_occupancy(const CatParams &p, int elem, int epi, int waves);
 KernelLaunch direct_launch_shape(const DirectParams &p);
 size_t cat_lds_bytes(const CatParams &p, int elem, int epi);
 
