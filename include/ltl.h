@@ -119,21 +119,50 @@ int32_t ltl_destroy(ltl_sim_t *sim);
 const char *ltl_last_error(void);
 
 /* ----------------------------------------------------------------------------------
- * Batched simulation: `count` independent automata of any sizes and rules advance
- * together, one persistent kernel launch per step over a cost-sorted (instance, tile)
- * work list; multi-step loops are replayed from a hipGraph.
+ * Batched simulation: `count` independent automata, each with its own size and rule,
+ * advance together in one kernel launch per T steps (tuning.steps_per_launch). The CAT
+ * methods use a persistent kernel over a work list with one entry per (instance, tile),
+ * sorted by decreasing estimated cost and taken by workgroups from a device-wide counter;
+ * the direct method launches one workgroup per entry. Multi-launch calls are replayed from a
+ * cached hipGraph. Each instance follows exactly the semantics of a single simulation of its
+ * own (dead ghost halo around each grid; no interaction between instances), so instance i
+ * after n batched steps equals ltl_create + ltl_step(n) of that grid and rule, cell for cell.
+ *
  *  H, W, rules    host arrays of `count` entries (copied).
- *  arena_a/b      two device buffers of >= ltl_batch_buffer_bytes() each; instance i
- *                 occupies H[i] rows of ltl_pitch(W[i]) bytes at a library-chosen offset.
- *  init           host array of `count` device pointers, instance i has row pitch init_pitch[i].
- * Methods: LTL_CAT_I8 or LTL_DIRECT. */
+ *  method         one ltl_method_t for every instance (LTL_CAT_F8 requires R <= 7 for all).
+ *  arena_a/b      two device buffers of bytes >= ltl_batch_buffer_bytes() each, 256-byte
+ *                 aligned; instance i occupies H[i] rows of ltl_pitch(W[i]) bytes at a
+ *                 library-chosen offset (ltl_batch_current gives it). Owned by the caller; the
+ *                 library owns their contents until ltl_batch_destroy.
+ *  init           host array of `count` device pointers, instance i has row pitch init_pitch[i]
+ *                 >= W[i]; read before ltl_batch_create returns.
+ *  stream         HIP stream for all work of this handle.
+ * Errors as ltl_create, for the first failing instance (its index is in ltl_last_error).
+ * The tuning's tile shape is the largest tile; each instance uses that tile grid with its
+ * tiles shrunk evenly to cover its grid with the least padding. The work-list counters live
+ * in the handle, so two launches of one handle must not run concurrently (one stream). */
 int32_t ltl_batch_buffer_bytes(int32_t count, const int32_t *H, const int32_t *W, size_t *bytes);
 int32_t ltl_batch_create(ltl_batch_t **out, int32_t count, const int32_t *H, const int32_t *W,
                          const ltl_rule_t *rules, int32_t method, void *arena_a, void *arena_b,
                          size_t bytes, const void *const *init, const size_t *init_pitch,
                          hipStream_t stream);
+/* Enqueue n_steps >= 0 steps of every instance (batch_step(a); batch_step(b) equals
+ * batch_step(a + b) cell for cell). */
 int32_t ltl_batch_step(ltl_batch_t *batch, int32_t n_steps);
+/* Enqueue a copy of instance `index` (H x W states) into device memory dst, row pitch dst_pitch >= W. */
 int32_t ltl_batch_read(ltl_batch_t *batch, int32_t index, void *dst, size_t dst_pitch);
+/* Device address and row pitch of instance `index`'s current states in the arenas (columns
+ * W..pitch-1 are always 0), and the number of steps taken so far. */
+int32_t ltl_batch_current(ltl_batch_t *batch, int32_t index, void **buf, size_t *pitch, int64_t *steps_done);
+/* Launch shape of the batch: zero fields take defaults (T = 1, 128 x 192 tiles, fewest waves
+ * that fit every instance). Validated against every instance (LTL_ERR_ARG). set_tuning
+ * synchronizes the stream (launch descriptors are rebuilt). */
+int32_t ltl_batch_get_tuning(ltl_batch_t *batch, ltl_tuning_t *tuning);
+int32_t ltl_batch_set_tuning(ltl_batch_t *batch, const ltl_tuning_t *tuning);
+/* Time candidate shapes (probe_steps steps each on a device copy of the arenas; the batch
+ * itself does not advance), keep the fastest, return it in *best (may be NULL). Synchronizes. */
+int32_t ltl_batch_autotune(ltl_batch_t *batch, int32_t probe_steps, ltl_tuning_t *best);
+/* Release the handle; does not free the arenas or synchronize. NULL is accepted. */
 int32_t ltl_batch_destroy(ltl_batch_t *batch);
 
 #ifdef __cplusplus

@@ -1,0 +1,605 @@
+// CAT step on gfx950: Moore neighbourhood counts as two band-matrix products per tile on
+// MFMA, followed by the LTL transition, with T steps fused per launch.
+//
+// Method (paper, "Formulation of CAT", Eq. 2-3 and Eq. F^H / F^R; Algorithm 1):
+//   H = Lambda x Pi   (horizontal window sums of the alive map)
+//   R = Pi x H        (vertical window sums of H) = box count of radius r, centre included
+// with Pi[a][b] = 1 iff |a - b| <= r. The paper splits Pi into three 16x16 band fragments
+// and runs 3 + 3 FP16 16x16x16 MMAs per 16x16 fragment. Here one int8 16x16x64 MFMA covers
+// the 48 columns a 16-column output needs (16 + 2r <= 48 for r <= 16), so each direction
+// costs one MFMA per 16x16 block:
+//
+//  * MFMA #1 (horizontal): A = 16 grid rows x 64 columns of the LDS tile, read as one 16-byte
+//    chunk per lane; B = band operand built in registers. One A load feeds two MFMAs (the two
+//    16-column halves of a 32-column strip) with two different bands, because the 64-column
+//    window holds both halves' neighbourhoods. Output: lane (col j, group g) holds H rows
+//    4g..4g+3 of column j, which are exact small integers (<= 33) and pack into one dword.
+//  * MFMA #2 (vertical) computes R^T = H^T x Pi (Pi is symmetric). Its A operand needs, per
+//    lane (col c, group g), four consecutive H rows of column c -- exactly the dword MFMA #1
+//    left in that lane. So the int32 -> int8 repack between the products (named as the
+//    obstacle to INT8 MMAs in the paper's conclusions) is three register ops, with no LDS
+//    round trip: the K index of MFMA #2 is laid out as a ring of four 16-row H blocks, one
+//    dword each, and the band operand comes in four phases that follow the ring.
+//  * The R^T accumulator gives each lane 4 horizontally adjacent counts of one row, so the
+//    epilogue reads one dword of centre states and writes one dword of next states.
+//
+// The K order inside an operand is immaterial as long as A and B agree on it (a dot product
+// is invariant under a common permutation), which is how the bands are built below.
+//
+// Precision variants (all exact by construction, so every variant gives the same grid):
+//  * ELEM_I8  int8 operands, int32 accumulation (v_mfma_i32_16x16x64_i8): exact for r <= 16.
+//  * ELEM_F8  fp8-e4m3 operands (v_mfma_f32_16x16x32_fp8_fp8), fp32 accumulation: H <= 2r+1 is
+//             exact in e4m3 only while 2r+1 <= 16 (r <= 7; the host refuses larger r).
+//  * ELEM_F16 fp16 operands (v_mfma_f32_16x16x32_f16), fp32 accumulation: exact for r <= 16
+//             (the paper's own precision argument: counts <= 33^2 - 1 < 2^11).
+// The fp32 accumulators of MFMA #2 start at 2^23, so the count lands in the low mantissa bits
+// and the same integer epilogue applies. The fp8 encoding of 1.0 is taken from the hardware
+// conversion instruction, so tile, band and H encodings always match the MFMA's format.
+//
+// Temporal blocking (multi-step idea cited in the paper's related work): the tile plus a
+// margin L = roundup16(r (T-1)) + 16 is loaded once into LDS; step t recomputes the tile
+// grown by roundup16(r (T - t)) cells, so after T steps the tile itself is exact. Cells
+// outside the grid are forced to 0 after every step (dead ghost halo).
+#pragma once
+#include "ltl_internal.h"
+
+namespace ltl {
+
+typedef int32_t v4i __attribute__((ext_vector_type(4)));
+typedef int32_t v2i __attribute__((ext_vector_type(2)));
+typedef int32_t v16i __attribute__((ext_vector_type(16)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef _Float16 v8h __attribute__((ext_vector_type(8)));
+// global-memory dword (explicit address space: global_store_*, not flat_* which would also
+// count against the LDS wait counter)
+typedef __attribute__((address_space(1))) uint32_t gdword;
+
+// Low bytes of the four int32 lanes of d packed into one dword (three byte permutes).
+__device__ __forceinline__ uint32_t pack_bytes(v4i d) {
+    uint32_t lo = __builtin_amdgcn_perm((uint32_t)d[1], (uint32_t)d[0], 0x0c0c0400u);  // d0.b0, d1.b0
+    uint32_t hi = __builtin_amdgcn_perm((uint32_t)d[3], (uint32_t)d[2], 0x0c0c0400u);  // d2.b0, d3.b0
+    return __builtin_amdgcn_perm(hi, lo, 0x05040100u);
+}
+
+__device__ __forceinline__ uint32_t bfi(uint32_t mask, uint32_t a, uint32_t b) {
+    return (mask & a) | (~mask & b);
+}
+
+// Byte mask (0xFF per byte) of the four cells gc..gc+3 that lie inside [0, W).
+__device__ __forceinline__ uint32_t col_mask(int gc, int W) {
+    uint32_t m = 0;
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+        m |= ((unsigned)(gc + v) < (unsigned)W ? 0xFFu : 0u) << (8 * v);
+    return m;
+}
+
+// Next states of 4 adjacent cells from their box counts n (centre included) and states s.
+// `m` is the validity mask of the 4 cells (0xFF per byte inside the grid); cells outside get 0.
+// Returns the state dword; *alive receives the alive-indicator dword (state == 1).
+//
+// Two-state rules test lo(s) <= n <= hi(s) on 8-bit (BYTE) or 16-bit (HALF) SWAR lanes:
+// a = 0x80 + n - lo has its top bit set iff n >= lo, b = 0x80 + hi - n iff n <= hi, and the
+// per-lane offsets come from the centre state in one 3-input bitwise op each.
+template <int EPI>
+__device__ __forceinline__ uint32_t transition4(v4i n, uint32_t s, uint32_t m, const RuleConsts &rc,
+                                                uint32_t *alive) {
+    if constexpr (EPI == EPI_BYTE) {
+        uint32_t N = pack_bytes(n);
+        uint32_t sm = 0x80808080u - s;                 // 0x80 per dead lane, 0x7F per alive lane
+        uint32_t a = N + (rc.Klo ^ (sm & rc.Dlo));
+        uint32_t b = (rc.Khi ^ (sm & rc.Dhi)) - N;
+        uint32_t x = (a & b & (m & 0x80808080u)) >> 7;
+        *alive = x;
+        return x;
+    } else if constexpr (EPI == EPI_HALF) {
+        // low 16 bits of each count (also correct for the 2^23-biased fp32 accumulators)
+        uint32_t p01 = __builtin_amdgcn_perm((uint32_t)n[1], (uint32_t)n[0], 0x05040100u);
+        uint32_t p23 = __builtin_amdgcn_perm((uint32_t)n[3], (uint32_t)n[2], 0x05040100u);
+        uint32_t s01 = __builtin_amdgcn_perm(0u, s, 0x0c010c00u);  // bytes 0, 1 -> 16-bit lanes
+        uint32_t s23 = __builtin_amdgcn_perm(0u, s, 0x0c030c02u);
+        uint32_t m01 = __builtin_amdgcn_perm(0u, m, 0x010c000cu);  // mask bytes 0, 1 -> lane top bytes
+        uint32_t m23 = __builtin_amdgcn_perm(0u, m, 0x030c020cu);
+        uint32_t sm01 = 0x80008000u - s01;
+        uint32_t sm23 = 0x80008000u - s23;
+        uint32_t x01 = (p01 + (rc.Klo ^ (sm01 & rc.Dlo))) & ((rc.Khi ^ (sm01 & rc.Dhi)) - p01) & (m01 & 0x80008000u);
+        uint32_t x23 = (p23 + (rc.Klo ^ (sm23 & rc.Dlo))) & ((rc.Khi ^ (sm23 & rc.Dhi)) - p23) & (m23 & 0x80008000u);
+        // bits 15 and 31 of x01, x23 -> bit 7 of bytes 0..3, then down to bit 0
+        uint32_t x = __builtin_amdgcn_perm(x23, x01, 0x07050301u) >> 7;
+        *alive = x;
+        return x;
+    } else {
+        uint32_t out = 0, al = 0;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            int sv = (int)((s >> (8 * v)) & 0xFFu);
+            int c = n[v] & 0xFFFF;   // counts <= 1089; also strips the bias of fp32 accumulators
+            int nx;
+            if (sv == 0) {
+                nx = (rc.b1 <= c && c <= rc.b2) ? 1 : 0;
+            } else if (sv == 1) {
+                int k = c - (rc.M == 0 ? 1 : 0);
+                nx = (rc.s1 <= k && k <= rc.s2) ? 1 : 2;
+            } else {
+                nx = (sv + 1 < rc.C) ? sv + 1 : 0;
+            }
+            out |= (uint32_t)nx << (8 * v);
+            al |= (uint32_t)(nx == 1) << (8 * v);
+        }
+        *alive = al & m;
+        return out & m;
+    }
+}
+
+// alive indicator (byte == 1) of a dword of states, any byte values
+__device__ __forceinline__ uint32_t alive_of(uint32_t s) {
+    uint32_t x = s ^ 0x01010101u;                              // zero byte iff state == 1
+    uint32_t y = ((x & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | x;         // bit 7 iff byte != 0
+    return (~y & 0x80808080u) >> 7;
+}
+
+// ---------------------------------------------------------------- element encodings
+// Per element type: bytes per cell of the alive map in LDS, the longest run of output blocks a
+// wave handles per step (bounded by the register tuple that holds H), the number of band
+// operands, and the encode / decode between alive bytes (0/1) and the LDS encoding.
+template <int ELEM> struct ElemT;
+template <> struct ElemT<ELEM_I8> { static constexpr int CELL = 1, MAXC = CAT_MAXC_I8, NOPS = 4; };
+template <> struct ElemT<ELEM_F8> { static constexpr int CELL = 1, MAXC = CAT_MAXC_F8, NOPS = 8; };
+template <> struct ElemT<ELEM_F16> { static constexpr int CELL = 2, MAXC = CAT_MAXC_F16, NOPS = 6; };
+
+struct Codec {
+    uint32_t one8;   // fp8 encoding of 1.0 (byte), as the hardware converts it
+    uint32_t sh8;    // its lowest set bit
+};
+
+__device__ __forceinline__ Codec make_codec() {
+    Codec c;
+    c.one8 = (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(1.0f, 0.0f, 0, false) & 0xFFu;
+    c.sh8 = (uint32_t)__builtin_ctz(c.one8);
+    return c;
+}
+
+// alive bytes (0/1) -> fp8 bytes (0 / 1.0): a byte permute with the alive bytes as selectors
+__device__ __forceinline__ uint32_t enc8(uint32_t alive, const Codec &c) {
+    return __builtin_amdgcn_perm(0u, c.one8 << 8, alive);
+}
+__device__ __forceinline__ uint32_t dec8(uint32_t x, const Codec &c) { return (x >> c.sh8) & 0x01010101u; }
+// alive bytes -> four fp16 (0 / 1.0 = 0x3C00), two per dword
+__device__ __forceinline__ uint2 enc16(uint32_t alive) {
+    uint32_t lo = __builtin_amdgcn_perm(0u, alive, 0x0c010c00u);   // bytes 0, 1 -> 16-bit lanes
+    uint32_t hi = __builtin_amdgcn_perm(0u, alive, 0x0c030c02u);
+    return make_uint2(__umul24(lo, 0x3C00u), __umul24(hi, 0x3C00u));
+}
+// four fp16 (0 / 1.0) -> alive bytes: the high byte of 1.0 is 0x3C, whose bit 2 is set
+__device__ __forceinline__ uint32_t dec16(uint32_t lo, uint32_t hi) {
+    return (__builtin_amdgcn_perm(hi, lo, 0x07050301u) >> 2) & 0x01010101u;
+}
+
+// Geometry of one step: strips of 32 columns, each cut into `nseg` row segments of at most
+// MAXC 16-row blocks. Every segment is one wave's work item; a step needs items <= waves (the
+// host planner checks this for every step of a launch).
+struct StepGeom {
+    int E, nstrips, nrb, nseg, seglen;
+};
+
+template <int MAXC>
+__device__ __forceinline__ StepGeom step_geom(const CatParams &p, int t) {
+    StepGeom g;
+    g.E = (p.r * (p.T - t) + 15) & ~15;
+    g.nstrips = (p.TW + 2 * g.E) >> 5;
+    g.nrb = (p.TH + 2 * g.E) >> 4;
+    g.nseg = (g.nrb + MAXC - 1) / MAXC;
+    g.seglen = (g.nrb + g.nseg - 1) / g.nseg;
+    return g;
+}
+
+// Band operands of one launch (up to 8 per lane, 16 bytes each; fp8 operands use 8 bytes).
+struct Bands {
+    v4i op[8];
+};
+
+template <int K>
+__device__ __forceinline__ v4i window4(const v16i &h) {
+    return __builtin_shufflevector(h, h, K, K + 1, K + 2, K + 3);
+}
+template <int K>
+__device__ __forceinline__ long window2(const v16i &h) {
+    v2i w = __builtin_shufflevector(h, h, K, K + 1);
+    return __builtin_bit_cast(long, w);
+}
+__device__ __forceinline__ long lo8(const v4i &x) {
+    v2i w = __builtin_shufflevector(x, x, 0, 1);
+    return __builtin_bit_cast(long, w);
+}
+__device__ __forceinline__ v8h as_h8(const v4i &x) { return __builtin_bit_cast(v8h, x); }
+__device__ __forceinline__ uint32_t pack_f8(v4f d) {
+    int x = __builtin_amdgcn_cvt_pk_fp8_f32(d[0], d[1], 0, false);
+    return (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(d[2], d[3], x, true);
+}
+__device__ __forceinline__ uint32_t pack_f16(float a, float b) {
+    return __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_pkrtz(a, b));
+}
+
+// H of one item and one 16-column half lives in a 16-register tuple: element k holds the
+// packed H of block rb0 - 1 + k (fp16: elements 2k, 2k + 1). Output block M needs
+// k = M, M+1, M+2. int8: MFMA #2 reads the even-aligned 4-register window starting at M (M
+// even) or M - 1 (M odd), one MFMA per block and two band phases. fp8 (K = 32): two MFMAs on
+// 2-register windows. fp16 (K = 32): two MFMAs on the 4-register windows of blocks (M, M+1)
+// and (M+2, M+3). No register copies in any case.
+
+// Phase A of one item: H (horizontal band sums) of blocks rb0 - 1 .. rb0 + count for both
+// 16-column halves of the strip, packed, in registers. Software-pipelined in pairs of blocks:
+// the A chunks of the next pair are read from LDS before the MFMAs of this pair run.
+template <int ELEM>
+__device__ __forceinline__ void phase_a(const uint8_t *At, uint32_t a_off, uint32_t PA, int rb0, int count,
+                                        const Bands &bd, v16i &Ha, v16i &Hb) {
+    const int nh = count + 2;
+    if constexpr (ELEM == ELEM_I8) {
+        const v4i zero = {0, 0, 0, 0};
+        v4i a[4];
+#define CAT_LDA(K) a[(K) & 3] = *reinterpret_cast<const v4i *>(At + (a_off + (uint32_t)(16 * (rb0 - 1 + (K))) * PA));
+#define CAT_HB(K)                                                                                  \
+        {                                                                                          \
+            v4i da = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[(K) & 3], bd.op[0], zero, 0, 0, 0);   \
+            v4i db = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[(K) & 3], bd.op[1], zero, 0, 0, 0);   \
+            Ha[(K)] = (int32_t)pack_bytes(da);                                                     \
+            Hb[(K)] = (int32_t)pack_bytes(db);                                                     \
+        }
+#define CAT_APAIR(P)                                                                               \
+        if (2 * (P) < nh) {                                                                        \
+            if (2 * (P) + 2 < nh) {                                                                \
+                CAT_LDA(2 * (P) + 2)                                                               \
+                if (2 * (P) + 3 < nh) CAT_LDA(2 * (P) + 3)                                         \
+            }                                                                                      \
+            CAT_HB(2 * (P))                                                                        \
+            if (2 * (P) + 1 < nh) CAT_HB(2 * (P) + 1)                                              \
+        }
+        CAT_LDA(0) CAT_LDA(1)
+        CAT_APAIR(0) CAT_APAIR(1) CAT_APAIR(2) CAT_APAIR(3) CAT_APAIR(4) CAT_APAIR(5) CAT_APAIR(6) CAT_APAIR(7)
+#undef CAT_APAIR
+#undef CAT_HB
+#undef CAT_LDA
+    } else if constexpr (ELEM == ELEM_F8) {
+        // two K = 32 chunks (8 bytes per lane each, 32 columns apart) per 64-column window
+        const v4f zf = {0.f, 0.f, 0.f, 0.f};
+        long a0[4], a1[4];
+#define CAT_LDA(K)                                                                                 \
+        {                                                                                          \
+            const uint8_t *q = At + (a_off + (uint32_t)(16 * (rb0 - 1 + (K))) * PA);               \
+            a0[(K) & 3] = *reinterpret_cast<const long *>(q);                                      \
+            a1[(K) & 3] = *reinterpret_cast<const long *>(q + 32);                                 \
+        }
+#define CAT_HB(K)                                                                                  \
+        {                                                                                          \
+            v4f da = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a0[(K) & 3], lo8(bd.op[0]), zf, 0, 0, 0); \
+            da = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a1[(K) & 3], lo8(bd.op[1]), da, 0, 0, 0); \
+            v4f db = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a0[(K) & 3], lo8(bd.op[2]), zf, 0, 0, 0); \
+            db = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a1[(K) & 3], lo8(bd.op[3]), db, 0, 0, 0); \
+            Ha[(K)] = (int32_t)pack_f8(da);                                                        \
+            Hb[(K)] = (int32_t)pack_f8(db);                                                        \
+        }
+#define CAT_APAIR(P)                                                                               \
+        if (2 * (P) < nh) {                                                                        \
+            if (2 * (P) + 2 < nh) {                                                                \
+                CAT_LDA(2 * (P) + 2)                                                               \
+                if (2 * (P) + 3 < nh) CAT_LDA(2 * (P) + 3)                                         \
+            }                                                                                      \
+            CAT_HB(2 * (P))                                                                        \
+            if (2 * (P) + 1 < nh) CAT_HB(2 * (P) + 1)                                              \
+        }
+        CAT_LDA(0) CAT_LDA(1)
+        CAT_APAIR(0) CAT_APAIR(1) CAT_APAIR(2) CAT_APAIR(3) CAT_APAIR(4) CAT_APAIR(5) CAT_APAIR(6) CAT_APAIR(7)
+#undef CAT_APAIR
+#undef CAT_HB
+#undef CAT_LDA
+    } else {
+        // fp16: two K = 32 chunks (8 halves = 16 bytes per lane each, 64 bytes apart)
+        const v4f zf = {0.f, 0.f, 0.f, 0.f};
+        v4i a0[4], a1[4];
+#define CAT_LDA(K)                                                                                 \
+        {                                                                                          \
+            const uint8_t *q = At + (a_off + (uint32_t)(16 * (rb0 - 1 + (K))) * PA);               \
+            a0[(K) & 3] = *reinterpret_cast<const v4i *>(q);                                       \
+            a1[(K) & 3] = *reinterpret_cast<const v4i *>(q + 64);                                  \
+        }
+#define CAT_HB(K)                                                                                  \
+        {                                                                                          \
+            v4f da = __builtin_amdgcn_mfma_f32_16x16x32_f16(as_h8(a0[(K) & 3]), as_h8(bd.op[0]), zf, 0, 0, 0); \
+            da = __builtin_amdgcn_mfma_f32_16x16x32_f16(as_h8(a1[(K) & 3]), as_h8(bd.op[1]), da, 0, 0, 0); \
+            v4f db = __builtin_amdgcn_mfma_f32_16x16x32_f16(as_h8(a0[(K) & 3]), as_h8(bd.op[2]), zf, 0, 0, 0); \
+            db = __builtin_amdgcn_mfma_f32_16x16x32_f16(as_h8(a1[(K) & 3]), as_h8(bd.op[3]), db, 0, 0, 0); \
+            Ha[2 * (K)] = (int32_t)pack_f16(da[0], da[1]);                                         \
+            Ha[2 * (K) + 1] = (int32_t)pack_f16(da[2], da[3]);                                     \
+            Hb[2 * (K)] = (int32_t)pack_f16(db[0], db[1]);                                         \
+            Hb[2 * (K) + 1] = (int32_t)pack_f16(db[2], db[3]);                                     \
+        }
+#define CAT_APAIR(P)                                                                               \
+        if (2 * (P) < nh) {                                                                        \
+            if (2 * (P) + 2 < nh) {                                                                \
+                CAT_LDA(2 * (P) + 2)                                                               \
+                if (2 * (P) + 3 < nh) CAT_LDA(2 * (P) + 3)                                         \
+            }                                                                                      \
+            CAT_HB(2 * (P))                                                                        \
+            if (2 * (P) + 1 < nh) CAT_HB(2 * (P) + 1)                                              \
+        }
+        CAT_LDA(0) CAT_LDA(1)
+        CAT_APAIR(0) CAT_APAIR(1) CAT_APAIR(2) CAT_APAIR(3)
+#undef CAT_APAIR
+#undef CAT_HB
+#undef CAT_LDA
+    }
+}
+
+// Vertical band product of output block M for one half (counts as int32 or biased fp32 bits).
+template <int ELEM, int M>
+__device__ __forceinline__ v4i vproduct(const v16i &H, const Bands &bd) {
+    if constexpr (ELEM == ELEM_I8) {
+        const v4i zero = {0, 0, 0, 0};
+        constexpr int W0 = (M & 1) ? M - 1 : M;
+        return __builtin_amdgcn_mfma_i32_16x16x64_i8(window4<W0>(H), (M & 1) ? bd.op[3] : bd.op[2], zero, 0, 0, 0);
+    } else if constexpr (ELEM == ELEM_F8) {
+        const v4f bias = {8388608.f, 8388608.f, 8388608.f, 8388608.f};
+        constexpr int W0 = (M & 1) ? M - 1 : M;
+        v4f c = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(window2<W0>(H), lo8((M & 1) ? bd.op[6] : bd.op[4]), bias,
+                                                           0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(window2<W0 + 2>(H), lo8((M & 1) ? bd.op[7] : bd.op[5]), c, 0,
+                                                       0, 0);
+        return __builtin_bit_cast(v4i, c);
+    } else {
+        const v4f bias = {8388608.f, 8388608.f, 8388608.f, 8388608.f};
+        v4f c = __builtin_amdgcn_mfma_f32_16x16x32_f16(as_h8(window4<2 * M>(H)), as_h8(bd.op[4]), bias, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_f16(as_h8(window4<2 * M + 4>(H)), as_h8(bd.op[5]), c, 0, 0, 0);
+        return __builtin_bit_cast(v4i, c);
+    }
+}
+
+// Offsets of this lane's cells in the LDS tiles: Q holds states (pitch PS, one byte per cell),
+// A the alive map in the element encoding (pitch PA). For int8 and fp8 without decay the two
+// tiles are the same bytes.
+struct LaneOff {
+    uint32_t q, a;   // block-row-0 offset of the lane's first cell of half a (half b: +16 cells)
+};
+
+// Phase B of one item: vertical band products, transition, store (in place in LDS for an
+// intermediate step, to the output grid on the last step of the launch). Software-pipelined in
+// pairs of output blocks: the MFMAs and centre-state reads of the next pair are issued before
+// the VALU transition of this pair, so their latencies overlap it.
+template <int ELEM, int EPI, bool MASKED, bool LAST>
+__device__ __forceinline__ void phase_b(const CatParams &p, uint8_t *Qt, uint8_t *At, LaneOff lo, int rb0, int count,
+                                        int gr0, uint32_t goff0, int gca, uint32_t cma, uint32_t cmb, const Bands &bd,
+                                        const Codec &cd, const v16i &Ha, const v16i &Hb) {
+    constexpr int CELL = ElemT<ELEM>::CELL;
+    constexpr bool SEPARATE = (EPI == EPI_DECAY) || (ELEM == ELEM_F16);   // Q and A are distinct tiles
+    const uint32_t PS = (uint32_t)p.PS, PA = (uint32_t)p.PA;
+    v4i ca[4], cb[4];
+    uint32_t sa[4], sb[4];
+    // counts and centre states of block M (slot M & 3)
+#define CAT_ISSUE(M)                                                                               \
+    {                                                                                              \
+        ca[(M) & 3] = vproduct<ELEM, (M)>(Ha, bd);                                                 \
+        cb[(M) & 3] = vproduct<ELEM, (M)>(Hb, bd);                                                 \
+        if constexpr (EPI == EPI_DECAY || ELEM == ELEM_I8) {                                       \
+            const uint32_t qo = lo.q + (uint32_t)(16 * (rb0 + (M))) * PS;                          \
+            sa[(M) & 3] = *reinterpret_cast<const uint32_t *>(Qt + qo);                            \
+            sb[(M) & 3] = *reinterpret_cast<const uint32_t *>(Qt + qo + 16);                       \
+        } else if constexpr (ELEM == ELEM_F8) {                                                    \
+            const uint32_t ao = lo.a + (uint32_t)(16 * (rb0 + (M))) * PA;                          \
+            sa[(M) & 3] = dec8(*reinterpret_cast<const uint32_t *>(At + ao), cd);                  \
+            sb[(M) & 3] = dec8(*reinterpret_cast<const uint32_t *>(At + ao + 16), cd);             \
+        } else {                                                                                   \
+            const uint32_t ao = lo.a + (uint32_t)(16 * (rb0 + (M))) * PA;                          \
+            const uint2 xa = *reinterpret_cast<const uint2 *>(At + ao);                            \
+            const uint2 xb = *reinterpret_cast<const uint2 *>(At + ao + 32);                       \
+            sa[(M) & 3] = dec16(xa.x, xa.y);                                                       \
+            sb[(M) & 3] = dec16(xb.x, xb.y);                                                       \
+        }                                                                                          \
+    }
+    // transition and store of block M
+#define CAT_FINISH(M)                                                                              \
+    {                                                                                              \
+        const int grow = gr0 + 16 * (M);                                                           \
+        uint32_t rowm = 0xFFFFFFFFu;                                                               \
+        if (MASKED) rowm = ((unsigned)grow < (unsigned)p.H) ? 0xFFFFFFFFu : 0u;                    \
+        uint32_t ala, alb;                                                                         \
+        const uint32_t na = transition4<EPI>(ca[(M) & 3], sa[(M) & 3], rowm & cma, p.rc, &ala);    \
+        const uint32_t nb = transition4<EPI>(cb[(M) & 3], sb[(M) & 3], rowm & cmb, p.rc, &alb);    \
+        if constexpr (LAST) {                                                                      \
+            const uint32_t go = goff0 + (uint32_t)(16 * (M)) * (uint32_t)p.pitch;                  \
+            if (!MASKED || rowm) {                                                                 \
+                if (!MASKED || (unsigned)gca < (unsigned)p.pitch) *(gdword *)(p.dst + go) = na;    \
+                if (!MASKED || (unsigned)(gca + 16) < (unsigned)p.pitch) *(gdword *)(p.dst + go + 16) = nb; \
+            }                                                                                      \
+        } else {                                                                                   \
+            const uint32_t qo = lo.q + (uint32_t)(16 * (rb0 + (M))) * PS;                          \
+            const uint32_t ao = lo.a + (uint32_t)(16 * (rb0 + (M))) * PA;                          \
+            if constexpr (EPI == EPI_DECAY) {                                                      \
+                *reinterpret_cast<uint32_t *>(Qt + qo) = na;                                       \
+                *reinterpret_cast<uint32_t *>(Qt + qo + 16) = nb;                                  \
+            }                                                                                      \
+            if constexpr (ELEM == ELEM_I8) {                                                       \
+                *reinterpret_cast<uint32_t *>(At + ao) = ala;                                      \
+                *reinterpret_cast<uint32_t *>(At + ao + 16) = alb;                                 \
+            } else if constexpr (ELEM == ELEM_F8) {                                                \
+                *reinterpret_cast<uint32_t *>(At + ao) = enc8(ala, cd);                            \
+                *reinterpret_cast<uint32_t *>(At + ao + 16) = enc8(alb, cd);                       \
+            } else {                                                                               \
+                *reinterpret_cast<uint2 *>(At + ao) = enc16(ala);                                  \
+                *reinterpret_cast<uint2 *>(At + ao + 32) = enc16(alb);                             \
+            }                                                                                      \
+        }                                                                                          \
+    }
+    // pair P = blocks 2P, 2P + 1; block `count` (one past the item) may be issued: its windows
+    // and centre row are inside the tile and nothing is stored for it
+#define CAT_BPAIR(P, NEXT)                                                                         \
+    if (2 * (P) < count) {                                                                         \
+        if (NEXT && 2 * (P) + 2 < count) { CAT_ISSUE(2 * (P) + 2) CAT_ISSUE(2 * (P) + 3) }         \
+        CAT_FINISH(2 * (P))                                                                        \
+        if (2 * (P) + 1 < count) CAT_FINISH(2 * (P) + 1)                                           \
+    }
+    (void)CELL;
+    (void)SEPARATE;
+    if constexpr (ELEM == ELEM_F16) {
+        CAT_ISSUE(0) CAT_ISSUE(1)
+        CAT_BPAIR(0, 1) CAT_BPAIR(1, 1)
+        CAT_BPAIR(2, 0)
+    } else {
+        CAT_ISSUE(0) CAT_ISSUE(1)
+        CAT_BPAIR(0, 1) CAT_BPAIR(1, 1) CAT_BPAIR(2, 1) CAT_BPAIR(3, 1) CAT_BPAIR(4, 1) CAT_BPAIR(5, 1)
+        CAT_BPAIR(6, 0)
+    }
+#undef CAT_BPAIR
+#undef CAT_FINISH
+#undef CAT_ISSUE
+}
+
+// T steps of one tile, in place in LDS (the last step writes the output grid).
+template <int ELEM, int EPI, bool MASKED>
+__device__ __forceinline__ void cat_steps(const CatParams &p, uint8_t *Qt, uint8_t *At, int gi0, int gj0, int wave,
+                                          int lane, const Bands &bd, const Codec &cd) {
+    constexpr int CELL = ElemT<ELEM>::CELL;
+    constexpr int MAXC = ElemT<ELEM>::MAXC;
+    const int li = lane & 15, lg = lane >> 4;
+    const uint32_t PS = (uint32_t)p.PS, PA = (uint32_t)p.PA;
+    const int L = p.L;
+    for (int t = 1; t <= p.T; ++t) {
+        const bool last = (t == p.T);
+        const StepGeom g = step_geom<MAXC>(p, t);
+        const int items = g.nstrips * g.nseg;
+        int j0 = 0, rb0 = 0, count = 0;
+        if (wave < items) {
+            const int strip = wave % g.nstrips;
+            const int seg = wave / g.nstrips;
+            const int mb_lo = seg * g.seglen;
+            const int mb_hi = min(g.nrb, mb_lo + g.seglen);
+            j0 = -g.E + 32 * strip;
+            rb0 = -(g.E >> 4) + mb_lo;
+            count = max(0, mb_hi - mb_lo);
+        }
+        v16i Ha, Hb;
+        if constexpr (ELEM != ELEM_I8) {
+            // slots no block fills may enter a window with zero weight; keep them finite
+            Ha = (v16i)0;
+            Hb = (v16i)0;
+        }
+        // this lane's A chunk (row li of a block, from column j0 - 16 + 16 lg, or + 8 lg for the
+        // K = 32 element types) and its first centre cell (row li, column j0 + 4 lg)
+        const int chunk_col = (ELEM == ELEM_I8) ? (L + j0 - 16 + 16 * lg) : (L + j0 - 16 + 8 * lg);
+        const uint32_t a_off = (uint32_t)((L + li) * (int)PA + chunk_col * CELL);
+        LaneOff lo;
+        lo.q = (uint32_t)((L + li) * (int)PS + (L + j0 + 4 * lg));
+        lo.a = (uint32_t)((L + li) * (int)PA + (L + j0 + 4 * lg) * CELL);
+        if (count > 0) phase_a<ELEM>(At, a_off, PA, rb0, count, bd, Ha, Hb);
+        if (!last) __syncthreads();   // every read of the old states precedes any in-place write
+        if (count > 0) {
+            const int gca = gj0 + j0 + 4 * lg;
+            uint32_t cma = 0xFFFFFFFFu, cmb = 0xFFFFFFFFu;
+            if constexpr (MASKED) {
+                cma = col_mask(gca, p.W);
+                cmb = col_mask(gca + 16, p.W);
+            }
+            const int gr0 = gi0 + 16 * rb0 + li;
+            const uint32_t goff0 = (uint32_t)(gr0 * p.pitch + gca);
+            if (last)
+                phase_b<ELEM, EPI, MASKED, true>(p, Qt, At, lo, rb0, count, gr0, goff0, gca, cma, cmb, bd, cd, Ha, Hb);
+            else
+                phase_b<ELEM, EPI, MASKED, false>(p, Qt, At, lo, rb0, count, gr0, goff0, gca, cma, cmb, bd, cd, Ha, Hb);
+        }
+        if (!last) __syncthreads();   // new states complete before the next step reads them
+    }
+}
+
+// Stream the (TH + 2L) x PS window of the tile at (gi0, gj0) into LDS at `buf` with direct
+// global->LDS loads: wave w moves KiB chunks w, w + nwaves, ...; lane l of a chunk carries
+// the 16 bytes at buffer offset 1024 c + 16 l. Cells outside the grid come from the zero page.
+__device__ __forceinline__ void issue_tile_load(const CatParams &p, int gi0, int gj0, uint8_t *buf, int wave,
+                                                int nwaves, int lane, float inv_ps) {
+    const int rows = p.TH + 2 * p.L;
+    const int nchunks = p.lds_tile >> 10;
+    for (int c = wave; c < nchunks; c += nwaves) {
+        const int o = (c << 10) + (lane << 4);
+        int lr = (int)((float)o * inv_ps);
+        int lc = o - lr * p.PS;
+        if (lc < 0) { lr -= 1; lc += p.PS; }
+        if (lc >= p.PS) { lr += 1; lc -= p.PS; }
+        const int gr = gi0 - p.L + lr;
+        const int gc = gj0 - p.L + lc;
+        const uint8_t *g = p.zero;
+        if (lr < rows && (unsigned)gr < (unsigned)p.H && (unsigned)gc < (unsigned)p.pitch)
+            g = p.src + (size_t)gr * p.pitch + gc;
+        // The load is issued from inline assembly: the compiler cannot see which LDS bytes an
+        // LDS-DMA writes, so for its own builtin it would make every later LDS access wait for
+        // all outstanding vector-memory operations. The caller waits (vmcnt(0) + barrier) before
+        // the buffer is read.
+        const uint32_t lds_addr = (uint32_t)(uintptr_t)(buf + (c << 10));
+        asm volatile("s_mov_b32 m0, %0\n\tglobal_load_lds_dwordx4 %1, off"
+                     :
+                     : "s"(__builtin_amdgcn_readfirstlane(lds_addr)), "v"(g)
+                     : "memory", "m0");
+    }
+}
+
+// One tile: load the window with direct LDS loads, derive the alive map in the element
+// encoding, then T steps in place (the last one writes the output grid). Ends without a
+// barrier: a caller that reuses the LDS for another tile synchronizes first.
+// `slot`, if not null: thread 0 stores `next` there once the tile's loads have completed
+// (the batched kernel passes a work-list index that was taken before the loads were issued).
+template <int ELEM, int EPI>
+__device__ __forceinline__ void cat_tile(const CatParams &p, int tile, uint8_t *lds, int tid, int lane, int wave,
+                                         int nwaves, const Codec &cd, uint32_t *slot = nullptr,
+                                         uint32_t next = 0) {
+    const int gi0 = (tile / p.ntx) * p.TH;
+    const int gj0 = (tile % p.ntx) * p.TW;
+
+    uint8_t *Qt = lds;                 // loaded window: states, one byte per cell
+    uint8_t *At = lds + p.a_tile;      // alive map in the element encoding (== Qt when shared)
+    issue_tile_load(p, gi0, gj0, Qt, wave, nwaves, lane, 1.0f / (float)p.PS);
+    Bands bd;
+    const v4i *bt = reinterpret_cast<const v4i *>(p.bands);
+#pragma unroll
+    for (int k = 0; k < ElemT<ELEM>::NOPS; ++k) {
+        bd.op[k] = bt[k * 64 + lane];
+        if constexpr (ELEM == ELEM_F8) {   // the table holds 0/1 bytes
+            bd.op[k][0] = (int32_t)enc8((uint32_t)bd.op[k][0], cd);
+            bd.op[k][1] = (int32_t)enc8((uint32_t)bd.op[k][1], cd);
+        }
+    }
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    if (slot != nullptr && tid == 0) *slot = next;
+    __syncthreads();
+
+    // alive map from the loaded states (int8 without decay reads the states directly)
+    if constexpr (!(ELEM == ELEM_I8 && EPI != EPI_DECAY)) {
+        const int W2 = p.TW + 2 * p.L;          // window columns (the PS - W2 pad is never read)
+        const int vpr = W2 >> 4;
+        const int nvec = (p.TH + 2 * p.L) * vpr;
+        for (int v = tid; v < nvec; v += 64 * nwaves) {
+            const int row = v / vpr;
+            const int col = (v - row * vpr) << 4;
+            const uint4 q = *reinterpret_cast<const uint4 *>(Qt + row * p.PS + col);
+            uint4 al = q;
+            if constexpr (EPI == EPI_DECAY)
+                al = make_uint4(alive_of(q.x), alive_of(q.y), alive_of(q.z), alive_of(q.w));
+            if constexpr (ELEM == ELEM_I8) {
+                *reinterpret_cast<uint4 *>(At + row * p.PA + col) = al;
+            } else if constexpr (ELEM == ELEM_F8) {
+                *reinterpret_cast<uint4 *>(At + row * p.PA + col) =
+                    make_uint4(enc8(al.x, cd), enc8(al.y, cd), enc8(al.z, cd), enc8(al.w, cd));
+            } else {
+                uint2 e0 = enc16(al.x), e1 = enc16(al.y), e2 = enc16(al.z), e3 = enc16(al.w);
+                uint8_t *d = At + row * p.PA + 2 * col;
+                *reinterpret_cast<uint4 *>(d) = make_uint4(e0.x, e0.y, e1.x, e1.y);
+                *reinterpret_cast<uint4 *>(d + 16) = make_uint4(e2.x, e2.y, e3.x, e3.y);
+            }
+        }
+        __syncthreads();
+    }
+    // no masking needed when every cell this tile computes lies inside the grid
+    const int E1 = p.L - 16;
+    const bool interior = gi0 - E1 >= 0 && gi0 + p.TH + E1 <= p.H && gj0 - E1 >= 0 && gj0 + p.TW + E1 <= p.W;
+    if (interior)
+        cat_steps<ELEM, EPI, false>(p, Qt, At, gi0, gj0, wave, lane, bd, cd);
+    else
+        cat_steps<ELEM, EPI, true>(p, Qt, At, gi0, gj0, wave, lane, bd, cd);
+}
+
+}  // namespace ltl

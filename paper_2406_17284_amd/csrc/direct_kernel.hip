@@ -24,11 +24,9 @@ __device__ __forceinline__ int direct_next(int s, int n, const RuleConsts &rc) {
     return (s + 1 < rc.C) ? s + 1 : 0;
 }
 
-__global__ void __launch_bounds__(DIRECT_THREADS) direct_step(DirectParams p) {
-    extern __shared__ uint8_t lds[];
+// One DIRECT_TH x DIRECT_TW output tile whose top-left cell is (gi0, gj0).
+__device__ __forceinline__ void direct_tile(const DirectParams &p, int gi0, int gj0, uint8_t *lds) {
     const int r = p.r;
-    const int gi0 = blockIdx.y * DIRECT_TH;
-    const int gj0 = blockIdx.x * DIRECT_TW;
     const int rows = DIRECT_TH + 2 * r;
     const int cols = DIRECT_TW + 2 * r;
     for (int idx = threadIdx.x; idx < rows * cols; idx += blockDim.x) {
@@ -76,6 +74,27 @@ __global__ void __launch_bounds__(DIRECT_THREADS) direct_step(DirectParams p) {
         *reinterpret_cast<uint32_t *>(p.dst + (size_t)gr * p.pitch + gc) = out;
     }
 }
+
+__global__ void __launch_bounds__(DIRECT_THREADS) direct_step(DirectParams p) {
+    extern __shared__ uint8_t lds[];
+    direct_tile(p, blockIdx.y * DIRECT_TH, blockIdx.x * DIRECT_TW, lds);
+}
+
+// Batched form: one workgroup per work-list entry (instance, tile).
+__global__ void __launch_bounds__(DIRECT_THREADS) direct_batch(DirectBatchParams bp) {
+    extern __shared__ uint8_t lds[];
+    const BatchItem item = bp.items[blockIdx.x];
+    const DirectBatchInst *bi = bp.inst + item.inst;
+    const DirectParams p = bi->p;
+    const int ty = item.tile / bi->ntx;
+    const int tx = item.tile - ty * bi->ntx;
+    direct_tile(p, ty * DIRECT_TH, tx * DIRECT_TW, lds);
+}
+
+const void *direct_batch_func() { return (const void *)&direct_batch; }
+int direct_tile_rows() { return DIRECT_TH; }
+int direct_tile_cols() { return DIRECT_TW; }
+int direct_threads() { return DIRECT_THREADS; }
 
 KernelLaunch direct_launch_shape(const DirectParams &p) {
     KernelLaunch k;

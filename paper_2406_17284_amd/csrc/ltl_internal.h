@@ -32,42 +32,83 @@ struct RuleConsts {
 struct CatParams {
     const uint8_t *src;
     uint8_t *dst;
-    const int32_t *bands;    // band operands for radius r: [4][64 lanes][4 dwords] (band_table layout)
+    const int32_t *bands;    // band operands of this radius and element type (band_table layout)
     const uint8_t *zero;     // >= 16 zero bytes in device memory (source of out-of-grid loads)
     int32_t H, W, pitch;     // grid rows, columns, row pitch (bytes)
     int32_t r;               // radius 1..16
     int32_t T;               // steps in this launch
     int32_t TH, TW;          // output tile (multiples of 16 / 32)
     int32_t L;               // LDS margin around the output tile: roundup16(r (T-1)) + 16
-    int32_t PS;              // LDS row pitch = TW + 2L + 16 (rows stored densely)
+    int32_t PS;              // state tile pitch (bytes) = TW + 2L + 16, rows stored densely
+    int32_t PA;              // alive tile pitch (bytes) in the element encoding
     int32_t lds_rows;        // TH + 2L
-    int32_t lds_tile;        // bytes of one LDS tile buffer: lds_rows * PS rounded up to 1 KiB
+    int32_t lds_tile;        // bytes of the state tile: lds_rows * PS rounded up to 1 KiB
+    int32_t a_tile;          // LDS offset of the alive tile (0: the state tile itself)
+    int32_t lds_total;       // dynamic LDS bytes of the launch
     int32_t ntx, nty;        // tiles across / down the grid
     RuleConsts rc;
 };
 
-// Band operands (one v4i per lane, 16 bytes, K slot 16 g + 4 d + e = byte e of dword d of lane
-// group g = lane / 16; n = lane % 16 is the output index):
-//  0, 1: MFMA #1 for the two 16-column halves of a 32-column strip whose 64-column window
-//        starts 16 columns left of the strip: weight 1 iff |k - 16 - 16 h - n| <= r;
-//  2, 3: MFMA #2, dword d holding the H block at distance ((d - p) & 3) - 1 (in 16-row
-//        blocks) from the output block, p = 0, 1: weight 1 iff |16 delta + 4 g + e - n| <= r.
-#define LTL_BAND_OPERANDS 4
-#define LTL_BAND_TABLE_INTS (LTL_BAND_OPERANDS * 64 * 4)   // per radius
-__host__ __device__ inline int32_t band_dword(int r, int which, int lane, int d) {
-    int n = lane & 15, g = lane >> 4;
-    uint32_t w = 0;
-    for (int e = 0; e < 4; ++e) {
-        int dist;
-        if (which < 2) {
-            dist = 16 * g + 4 * d + e - 16 - 16 * which - n;
+// Band operands, host-built per (element type, radius): LTL_BAND_OPS operands x 64 lanes x 4
+// dwords. Lane l = 16 g + n (n = output index, g = lane group); the K slots a lane carries are
+// numbered as the MFMA A operand numbers them (int8 16x16x64: 16 bytes, K = 16 g + 4 d + e;
+// fp8 16x16x32: 8 bytes, K = 8 g + 4 d + e; fp16 16x16x32: 8 halves, K = 8 g + j).
+//  int8 : 0, 1  MFMA #1, halves 0/1 of a 32-column strip whose 64-column window starts 16
+//               columns left of it: weight 1 iff |k - 16 - 16 h - n| <= r
+//         2, 3  MFMA #2, 4-block window (slot d = dword d) starting at block m-1 (2) or m-2 (3)
+//  fp8  : 0..3  MFMA #1 (half h, chunk c) = op 2h + c, chunk c covers window columns 32c..32c+31
+//         4..7  MFMA #2 on 2-block windows: (m-1, m), (m+1, m+2), (m-2, m-1), (m, m+1)
+//  fp16 : 0..3  MFMA #1 as fp8; 4, 5 MFMA #2 on the 2-block windows (m-1, m), (m+1, m+2)
+// MFMA #2 rows: block at distance delta from the output block, row 4 g + e of it, weight 1 iff
+// |16 delta + 4 g + e - n| <= r. int8 and fp8 tables hold 0/1 bytes (fp8 is encoded on the
+// device with the hardware's 1.0); fp16 holds 0x3C00 halves.
+#define LTL_BAND_OPS 8
+#define LTL_BAND_TABLE_INTS (LTL_BAND_OPS * 64 * 4)   // per (element type, radius)
+
+inline bool band_hit(int dist, int r) { return dist >= -r && dist <= r; }
+
+inline void band_table(int elem, int r, int32_t *out) {
+    for (int i = 0; i < LTL_BAND_TABLE_INTS; ++i) out[i] = 0;
+    for (int lane = 0; lane < 64; ++lane) {
+        const int n = lane & 15, g = lane >> 4;
+        auto put_byte = [&](int op, int d, int e, bool on) {
+            if (on) out[(op * 64 + lane) * 4 + d] |= 1 << (8 * e);
+        };
+        auto put_half = [&](int op, int j, bool on) {
+            if (on) out[(op * 64 + lane) * 4 + j / 2] |= 0x3C00 << (16 * (j & 1));
+        };
+        if (elem == ELEM_I8) {
+            for (int d = 0; d < 4; ++d)
+                for (int e = 0; e < 4; ++e) {
+                    const int k = 16 * g + 4 * d + e;
+                    put_byte(0, d, e, band_hit(k - 16 - n, r));
+                    put_byte(1, d, e, band_hit(k - 32 - n, r));
+                    // window slot d of a window starting at block m-1 (op 2) or m-2 (op 3)
+                    put_byte(2, d, e, band_hit(16 * (d - 1) + 4 * g + e - n, r));
+                    put_byte(3, d, e, band_hit(16 * (d - 2) + 4 * g + e - n, r));
+                }
         } else {
-            int delta = ((d - (which - 2)) & 3) - 1;
-            dist = 16 * delta + 4 * g + e - n;
+            for (int h = 0; h < 2; ++h)
+                for (int c = 0; c < 2; ++c)
+                    for (int j = 0; j < 8; ++j) {
+                        const bool on = band_hit(32 * c + 8 * g + j - 16 - 16 * h - n, r);
+                        if (elem == ELEM_F8) put_byte(2 * h + c, j / 4, j % 4, on);
+                        else put_half(2 * h + c, j, on);
+                    }
+            if (elem == ELEM_F8) {
+                const int start[4] = {-1, 1, -2, 0};   // first block of each 2-block window
+                for (int w = 0; w < 4; ++w)
+                    for (int d = 0; d < 2; ++d)
+                        for (int e = 0; e < 4; ++e)
+                            put_byte(4 + w, d, e, band_hit(16 * (start[w] + d) + 4 * g + e - n, r));
+            } else {
+                const int start[2] = {-1, 1};
+                for (int w = 0; w < 2; ++w)
+                    for (int j = 0; j < 8; ++j)
+                        put_half(4 + w, j, band_hit(16 * (start[w] + j / 4) + 4 * g + (j % 4) - n, r));
+            }
         }
-        w |= (uint32_t)((dist >= -r && dist <= r) ? 1 : 0) << (8 * e);
     }
-    return (int32_t)w;
 }
 
 struct DirectParams {
@@ -85,37 +126,79 @@ inline int roundup(int x, int m) { return (x + m - 1) / m * m; }
 
 inline int cat_margin(int r, int T) { return roundup(r * (T - 1), 16) + 16; }
 
-inline int cat_lds_pitch(int TW, int L, int elem_bytes) {
-    // bytes per LDS row: the loaded window is TW + 2L columns (a multiple of 32) plus 16 more,
-    // so the pitch is = 16 (mod 32) and the 16 rows of a 16-byte-per-lane operand read fall
-    // into distinct bank groups; rows are stored densely so 1 KiB of consecutive LDS maps to
-    // consecutive window bytes (one direct global->LDS load per wave)
-    return (TW + 2 * L) * elem_bytes + 16;
-}
-
-// LDS tile buffers of a workgroup: the tile stepped in place, plus the alive map for decay
-// rules (the loaded tile then holds states).
-inline int cat_tiles_in_lds(int T, int epi) {
-    (void)T;
-    return (epi == EPI_DECAY) ? 2 : 1;
-}
-
-// Longest 16-row run of output blocks one wave handles in one step.
-#define CAT_MAXC 14
+// Longest run of 16-row output blocks one wave handles per step, per element type (bounded by
+// the 16-register tuple that holds an item's H blocks).
+#define CAT_MAXC_I8 14
+#define CAT_MAXC_F8 14
+#define CAT_MAXC_F16 5
+inline int cat_maxc(int elem) { return elem == ELEM_F16 ? CAT_MAXC_F16 : elem == ELEM_F8 ? CAT_MAXC_F8 : CAT_MAXC_I8; }
+inline int cat_cell_bytes(int elem) { return elem == ELEM_F16 ? 2 : 1; }
 
 // Whether a launch shape can run: in every step of a T-step launch the strips x segments
 // must not outnumber the waves (each wave keeps one item's H blocks in registers across the
 // barrier that separates the reads of the old states from the in-place writes).
-inline bool cat_shape_fits(int r, int T, int TH, int TW, int waves) {
+inline bool cat_shape_fits(int elem, int r, int T, int TH, int TW, int waves) {
+    const int maxc = cat_maxc(elem);
     for (int t = 1; t <= T; ++t) {
         int E = roundup(r * (T - t), 16);
         int nstrips = (TW + 2 * E) / 32;
         int nrb = (TH + 2 * E) / 16;
-        int nseg = (nrb + CAT_MAXC - 1) / CAT_MAXC;
+        int nseg = (nrb + maxc - 1) / maxc;
         if (nstrips * nseg > waves) return false;
     }
     return true;
 }
+
+// LDS geometry of a launch: the state tile holds the loaded window, TW + 2L columns (a
+// multiple of 32) plus 16 more bytes per row, so its pitch is = 16 (mod 32) and the 16 rows of
+// a 16-byte-per-lane operand read fall into distinct bank groups; rows are dense so 1 KiB of
+// consecutive LDS maps to consecutive window bytes (one direct global->LDS load per wave).
+// The alive tile is the state tile itself for int8 / fp8 two-state rules, else a second tile
+// in the element encoding.
+inline void cat_lds_layout(int elem, int epi, int TH, int TW, int L, int *PS, int *PA, int *lds_tile, int *a_tile,
+                           int *lds_total) {
+    const int rows = TH + 2 * L;
+    *PS = TW + 2 * L + 16;
+    *lds_tile = roundup(rows * *PS, 1024);
+    const bool separate = (epi == EPI_DECAY) || (elem == ELEM_F16);
+    *PA = cat_cell_bytes(elem) * (TW + 2 * L) + 16;
+    *a_tile = separate ? *lds_tile : 0;
+    *lds_total = *lds_tile + (separate ? roundup(rows * *PA, 1024) : 0);
+}
+
+// Batched simulation: one persistent launch advances every instance by T steps. The
+// instances' grids sit at their own offsets of two arenas; the work list holds one entry per
+// (instance, tile), grouped by epilogue class and sorted by decreasing estimated cost within
+// a class; workgroups take entries from a device-wide counter per class.
+struct BatchInst {
+    CatParams p;           // launch parameters of the instance (src/dst of the launch's parity)
+};
+
+struct BatchItem {
+    int32_t inst, tile;
+};
+
+struct BatchParams {
+    const BatchInst *inst;     // per instance, for the arena this launch reads
+    const BatchItem *items;    // entries of epilogue class c at items[start[c] .. start[c] + count[c])
+    uint32_t *queue;           // [c] next entry of class c, [3] workgroups done; all 0 between launches
+    int32_t start[3], count[3];
+    int32_t slot;              // LDS byte offset of two dwords that pass the next entry to all waves
+};
+
+// Direct-stencil comparison method over the same work-list idea (one workgroup per entry).
+struct DirectBatchInst {
+    DirectParams p;        // src/dst of the launch's parity
+    int32_t ntx;           // direct tiles across the grid
+    int32_t pad[3];
+};
+
+struct DirectBatchParams {
+    const DirectBatchInst *inst;   // per instance, for the arena this launch reads
+    const BatchItem *items;
+    int32_t nitems;
+    int32_t pad;
+};
 
 // Launchers (return the HIP status of the launch).
 hipError_t launch_cat(const CatParams &p, int elem, int epi, int waves, hipStream_t s);
@@ -134,5 +217,14 @@ KernelLaunch cat_launch_shape(const CatParams &p, int elem, int epi, int waves);
 int cat_occupancy(const CatParams &p, int elem, int epi, int waves);
 KernelLaunch direct_launch_shape(const DirectParams &p);
 size_t cat_lds_bytes(const CatParams &p, int elem, int epi);
+// Batched launches. cat_batch_func: the persistent kernel of an element type (launched with
+// `grid` workgroups of 64 * waves threads and `lds` bytes of dynamic LDS).
+const void *cat_batch_func(int elem);
+int cat_batch_occupancy(int elem, int waves, size_t lds);
+const void *direct_batch_func();
+int direct_tile_rows();
+int direct_tile_cols();
+int direct_threads();
+
 
 }  // namespace ltl

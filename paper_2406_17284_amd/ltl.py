@@ -33,6 +33,7 @@ EXPORTS = [
     "ltl_buffer_bytes", "ltl_pitch", "ltl_create", "ltl_step", "ltl_read", "ltl_current",
     "ltl_get_tuning", "ltl_set_tuning", "ltl_autotune", "ltl_destroy", "ltl_last_error",
     "ltl_batch_buffer_bytes", "ltl_batch_create", "ltl_batch_step", "ltl_batch_read",
+    "ltl_batch_current", "ltl_batch_get_tuning", "ltl_batch_set_tuning", "ltl_batch_autotune",
     "ltl_batch_destroy",
 ]
 
@@ -83,6 +84,10 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "ltl_batch_create": ([ctypes.POINTER(P), I32, P, P, P, I32, P, P, SZ, P, P, P], I32),
         "ltl_batch_step": ([P, I32], I32),
         "ltl_batch_read": ([P, I32, P, SZ], I32),
+        "ltl_batch_current": ([P, I32, ctypes.POINTER(P), PSZ, ctypes.POINTER(ctypes.c_int64)], I32),
+        "ltl_batch_get_tuning": ([P, ctypes.POINTER(ltl_tuning_t)], I32),
+        "ltl_batch_set_tuning": ([P, ctypes.POINTER(ltl_tuning_t)], I32),
+        "ltl_batch_autotune": ([P, I32, ctypes.POINTER(ltl_tuning_t)], I32),
         "ltl_batch_destroy": ([P], I32),
     }
     for name, (args, res) in sig.items():
@@ -216,6 +221,32 @@ def ltl_batch_read(batch: int, index: int, dst: int, dst_pitch: int) -> None:
     _check(load().ltl_batch_read(ctypes.c_void_p(batch), int(index), ctypes.c_void_p(dst), dst_pitch))
 
 
+def ltl_batch_current(batch: int, index: int):
+    buf = ctypes.c_void_p(0)
+    pitch = ctypes.c_size_t(0)
+    steps = ctypes.c_int64(0)
+    _check(load().ltl_batch_current(ctypes.c_void_p(batch), int(index), ctypes.byref(buf), ctypes.byref(pitch),
+                                    ctypes.byref(steps)))
+    return buf.value, pitch.value, steps.value
+
+
+def ltl_batch_get_tuning(batch: int) -> ltl_tuning_t:
+    t = ltl_tuning_t()
+    _check(load().ltl_batch_get_tuning(ctypes.c_void_p(batch), ctypes.byref(t)))
+    return t
+
+
+def ltl_batch_set_tuning(batch: int, steps_per_launch=0, tile_rows=0, tile_cols=0, waves=0, use_graph=1) -> None:
+    t = ltl_tuning_t(steps_per_launch, tile_rows, tile_cols, waves, use_graph)
+    _check(load().ltl_batch_set_tuning(ctypes.c_void_p(batch), ctypes.byref(t)))
+
+
+def ltl_batch_autotune(batch: int, probe_steps: int) -> ltl_tuning_t:
+    t = ltl_tuning_t()
+    _check(load().ltl_batch_autotune(ctypes.c_void_p(batch), int(probe_steps), ctypes.byref(t)))
+    return t
+
+
 def ltl_batch_destroy(batch: int) -> None:
     _check(load().ltl_batch_destroy(ctypes.c_void_p(batch)))
 
@@ -280,6 +311,84 @@ class Simulation:
 
             torch.cuda.synchronize(self.device)
             ltl_destroy(self.handle)
+            self.handle = 0
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Many automata advanced together; the two arenas are torch uint8 tensors on the GPU.
+    ``inits``: 2-D uint8 CUDA tensors (one per instance), ``rules``: one rule per instance."""
+
+    def __init__(self, inits, rules, method="cat_i8", stream=None, tuning: Optional[dict] = None):
+        import torch
+
+        if isinstance(method, str):
+            method = METHODS[method]
+        if len(inits) != len(rules) or not inits:
+            raise ValueError("need one rule per initial grid, at least one instance")
+        for g in inits:
+            if g.device.type != "cuda" or g.dtype != torch.uint8 or g.dim() != 2 or g.stride(1) != 1:
+                raise ValueError("every initial grid must be a row-major 2-D uint8 CUDA tensor")
+        self.device = inits[0].device
+        self.H = [int(g.shape[0]) for g in inits]
+        self.W = [int(g.shape[1]) for g in inits]
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.nbytes = ltl_batch_buffer_bytes(self.H, self.W)
+        self.arenas = [torch.empty(self.nbytes, dtype=torch.uint8, device=self.device) for _ in range(2)]
+        self.handle = ltl_batch_create(self.H, self.W, rules, method, self.arenas[0].data_ptr(),
+                                       self.arenas[1].data_ptr(), self.nbytes, [g.data_ptr() for g in inits],
+                                       [g.stride(0) for g in inits], self.stream)
+        if tuning:
+            ltl_batch_set_tuning(self.handle, **tuning)
+
+    def __len__(self) -> int:
+        return len(self.H)
+
+    def step(self, n: int = 1) -> "Batch":
+        ltl_batch_step(self.handle, n)
+        return self
+
+    def read(self, index: int, out=None):
+        import torch
+
+        if out is None:
+            out = torch.empty((self.H[index], self.W[index]), dtype=torch.uint8, device=self.device)
+        ltl_batch_read(self.handle, index, out.data_ptr(), out.stride(0))
+        return out
+
+    def current_padded(self, index: int):
+        """Instance `index`'s current state in the library layout (H rows x pitch), a view."""
+        ptr, pitch, _ = ltl_batch_current(self.handle, index)
+        for a in self.arenas:
+            off = ptr - a.data_ptr()
+            if 0 <= off < self.nbytes:
+                return a[off: off + self.H[index] * pitch].view(self.H[index], pitch)
+        raise RuntimeError("instance buffer outside both arenas")
+
+    @property
+    def steps_done(self) -> int:
+        return ltl_batch_current(self.handle, 0)[2]
+
+    def tuning(self) -> dict:
+        return ltl_batch_get_tuning(self.handle).as_dict()
+
+    def set_tuning(self, **kw) -> None:
+        ltl_batch_set_tuning(self.handle, **kw)
+
+    def autotune(self, probe_steps: int = 4) -> dict:
+        return ltl_batch_autotune(self.handle, probe_steps).as_dict()
+
+    def close(self) -> None:
+        if self.handle:
+            import torch
+
+            torch.cuda.synchronize(self.device)
+            ltl_batch_destroy(self.handle)
             self.handle = 0
 
     def __del__(self):

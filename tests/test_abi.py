@@ -76,3 +76,49 @@ def test_null_handles():
     assert lib.ltl_batch_destroy(None) == ltl.LTL_OK
     t = ltl.ltl_tuning_t()
     assert lib.ltl_get_tuning(None, ctypes.byref(t)) == ltl.LTL_ERR_ARG
+
+
+def test_batch_buffer_bytes():
+    # each instance: H rows at the 64-byte pitch, rounded up to 256 bytes
+    assert ltl.ltl_batch_buffer_bytes([3], [100]) == 512
+    assert ltl.ltl_batch_buffer_bytes([3, 1, 8], [100, 1, 64]) == 512 + 256 + 512
+    for H, W in [([], []), ([0], [4]), ([4, 5], [4, -1])]:
+        with pytest.raises(ltl.LtlError) as e:
+            ltl.ltl_batch_buffer_bytes(H, W)
+        assert e.value.code == ltl.LTL_ERR_ARG
+
+
+def _batch_create(H=(8, 8), W=(8, 8), rules=((1, 0, 1, 3, 4, 3, 3), (2, 3, 0, 5, 9, 4, 7)), method=ltl.LTL_CAT_I8,
+                  a=256, b=512, nbytes=1 << 20, inits=(1024, 2048), pitches=(8, 8)):
+    return ltl.ltl_batch_create(list(H), list(W), list(rules), method, a, b, nbytes, list(inits), list(pitches))
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(a=0), ltl.LTL_ERR_ARG),
+    (dict(a=256, b=256), ltl.LTL_ERR_ARG),
+    (dict(a=100), ltl.LTL_ERR_ARG),
+    (dict(inits=(1024, 0)), ltl.LTL_ERR_ARG),
+    (dict(pitches=(8, 7)), ltl.LTL_ERR_ARG),
+    (dict(H=(8, 0)), ltl.LTL_ERR_ARG),
+    (dict(rules=((1, 0, 1, 3, 4, 3, 3), (17, 0, 1, 3, 4, 3, 3))), ltl.LTL_ERR_RULE),
+    (dict(rules=((1, 0, 1, 3, 4, 3, 3), (1, 0, 1, 3, 4, 3, 3, "N"))), ltl.LTL_ERR_UNSUPPORTED),
+    (dict(rules=((7, 0, 1, 3, 4, 3, 3), (8, 0, 1, 3, 4, 3, 3)), method=ltl.LTL_CAT_F8), ltl.LTL_ERR_INEXACT),
+    (dict(method=9), ltl.LTL_ERR_ARG),
+    (dict(nbytes=1023), ltl.LTL_ERR_SIZE),
+])
+def test_batch_create_rejects_bad_arguments(kw, code):
+    with pytest.raises(ltl.LtlError) as e:
+        _batch_create(**kw)
+    assert e.value.code == code
+    assert ltl.last_error()
+
+
+def test_batch_null_handles():
+    lib = ltl.load()
+    assert lib.ltl_batch_step(None, 1) == ltl.LTL_ERR_ARG
+    assert lib.ltl_batch_read(None, 0, None, 0) == ltl.LTL_ERR_ARG
+    assert lib.ltl_batch_current(None, 0, None, None, None) == ltl.LTL_ERR_ARG
+    t = ltl.ltl_tuning_t()
+    assert lib.ltl_batch_get_tuning(None, ctypes.byref(t)) == ltl.LTL_ERR_ARG
+    assert lib.ltl_batch_set_tuning(None, ctypes.byref(t)) == ltl.LTL_ERR_ARG
+    assert lib.ltl_batch_autotune(None, 1, None) == ltl.LTL_ERR_ARG

@@ -1,0 +1,217 @@
+"""GPU parity of the batched simulation: every instance of a heterogeneous batch (sizes,
+radii, rules, state counts) against the CPU oracle of that instance alone, cell for cell.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2406_17284_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+CAT_METHODS = ["cat_i8", "cat_f16", "cat_f8"]
+ALL_METHODS = CAT_METHODS + ["direct"]
+
+SHAPES = [(1, 1), (17, 33), (40, 200), (130, 70), (200, 260), (64, 64), (300, 31), (96, 160), (5, 400),
+          (250, 250), (33, 17), (129, 129)]
+
+
+@pytest.fixture(scope="module")
+def ltl():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2406_17284_amd import ltl as mod
+    mod.load()
+    return mod
+
+
+def gpu_grid(a: np.ndarray):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def random_rule(rng, max_r, decay=True):
+    r = int(rng.integers(1, max_r + 1))
+    n = (2 * r + 1) ** 2
+    C = int(rng.choice([0, 0, 2, 3, 5, 9])) if decay else 0
+    M = int(rng.integers(0, 2))
+    lo, hi = max(0, int(0.1 * n)), int(0.6 * n)
+    s = sorted(int(x) for x in rng.integers(lo, hi + 1, size=2))
+    b = sorted(int(x) for x in rng.integers(lo, hi + 1, size=2))
+    if rng.random() < 0.15:        # an empty range (s1 > s2)
+        s = [s[1] + 1, s[0]]
+    return inputs.Rule(r, C, M, s[0], s[1], b[0], b[1])
+
+
+def small_batch(seed, max_r=16, decay=True, shapes=SHAPES):
+    rng = np.random.default_rng(seed)
+    grids, rules = [], []
+    for k, (H, W) in enumerate(shapes):
+        rule = random_rule(rng, max_r, decay)
+        if rule.C >= 3:
+            g = inputs.state_grid(H, W, rule.C, seed=1000 * seed + k)
+        else:
+            g = inputs.bernoulli_grid(H, W, 0.5, seed=1000 * seed + k)
+        grids.append(g)
+        rules.append(rule)
+    return grids, rules
+
+
+def check_batch(batch, refs, what):
+    for i, ref in enumerate(refs):
+        got = batch.read(i).cpu().numpy()
+        if not np.array_equal(got, ref):
+            bad = np.argwhere(got != ref)
+            raise AssertionError(f"{what}: instance {i} ({ref.shape}) differs at {len(bad)} cells, "
+                                 f"first {bad[:5].tolist()}")
+        pad = batch.current_padded(i).cpu().numpy()
+        assert not pad[:, ref.shape[1]:].any(), f"{what}: instance {i} padding columns not dead"
+
+
+@pytest.mark.parametrize("method", ALL_METHODS)
+@pytest.mark.parametrize("seed", [1, 2])
+def test_batch_every_step(ltl, method, seed):
+    grids, rules = small_batch(seed, max_r=7 if method == "cat_f8" else 16)
+    batch = ltl.Batch([gpu_grid(g) for g in grids], rules, method)
+    refs = [g.copy() for g in grids]
+    for t in range(5):
+        batch.step(1)
+        refs = [oracle.step(x, r) for x, r in zip(refs, rules)]
+        check_batch(batch, refs, f"{method} seed {seed} step {t + 1}")
+    batch.close()
+
+
+@pytest.mark.parametrize("method", CAT_METHODS)
+@pytest.mark.parametrize("tuning", [
+    dict(steps_per_launch=1, tile_rows=64, tile_cols=64),
+    dict(steps_per_launch=2, tile_rows=128, tile_cols=192),
+    dict(steps_per_launch=3, tile_rows=64, tile_cols=128),
+    dict(steps_per_launch=1, tile_rows=16, tile_cols=32),
+    dict(steps_per_launch=4, tile_rows=32, tile_cols=64, use_graph=0),
+], ids=lambda t: "T{steps_per_launch}_{tile_rows}x{tile_cols}".format(**t))
+def test_batch_tunings(ltl, method, tuning):
+    grids, rules = small_batch(3, max_r=7 if method == "cat_f8" else 9)
+    batch = ltl.Batch([gpu_grid(g) for g in grids], rules, method)
+    try:
+        batch.set_tuning(**tuning)
+    except ltl.LtlError as e:
+        # only a shape the kernel cannot run may be refused
+        assert e.code == ltl.LTL_ERR_ARG
+        pytest.skip(f"shape refused: {e}")
+    batch.step(7)
+    check_batch(batch, [oracle.run(g, r, 7) for g, r in zip(grids, rules)], f"{method} {tuning}")
+    batch.close()
+
+
+def test_batch_resume_and_graph(ltl):
+    grids, rules = small_batch(4, max_r=6)
+    refs = [oracle.run(g, r, 9) for g, r in zip(grids, rules)]
+    for use_graph in (0, 1):
+        for chunks in ([9], [2, 3, 4], [1] * 9, [4, 0, 5]):
+            batch = ltl.Batch([gpu_grid(g) for g in grids], rules, "cat_i8",
+                              tuning=dict(steps_per_launch=2, use_graph=use_graph))
+            for n in chunks:
+                batch.step(n)
+            assert batch.steps_done == 9
+            check_batch(batch, refs, f"graph={use_graph} chunks={chunks}")
+            batch.close()
+
+
+def test_batch_single_instance_equals_simulation(ltl):
+    g = inputs.bernoulli_grid(300, 500, 0.5, seed=77)
+    rule = inputs.BOSCO_M1
+    batch = ltl.Batch([gpu_grid(g)], [rule], "cat_i8")
+    sim = ltl.Simulation(gpu_grid(g), rule, "cat_i8")
+    batch.step(6)
+    sim.step(6)
+    a, b = batch.read(0).cpu().numpy(), sim.read().cpu().numpy()
+    assert np.array_equal(a, b)
+    assert np.array_equal(a, oracle.run(g, rule, 6))
+    batch.close()
+    sim.close()
+
+
+def test_batch_f8_refuses_large_radius(ltl):
+    g = np.zeros((8, 8), dtype=np.uint8)
+    rules = [inputs.Rule(3, 0, 1, 10, 20, 10, 20), inputs.Rule(8, 0, 1, 50, 90, 60, 80)]
+    with pytest.raises(ltl.LtlError) as e:
+        ltl.Batch([gpu_grid(g), gpu_grid(g)], rules, "cat_f8")
+    assert e.value.code == ltl.LTL_ERR_INEXACT
+
+
+def test_batch_rejects_bad_states(ltl):
+    g = np.zeros((8, 8), dtype=np.uint8)
+    bad = g.copy()
+    bad[3, 3] = 4
+    rules = [inputs.Rule(2, 0, 1, 5, 9, 5, 7), inputs.Rule(2, 4, 1, 5, 9, 5, 7)]
+    ltl.Batch([gpu_grid(g), gpu_grid(bad - 1)], rules, "cat_i8").close()   # state 3 < C = 4
+    with pytest.raises(ltl.LtlError) as e:
+        ltl.Batch([gpu_grid(bad), gpu_grid(g)], rules, "cat_i8")   # state 4 >= 2 for C = 0
+    assert e.value.code == ltl.LTL_ERR_STATE
+
+
+def test_batch_autotune_keeps_results(ltl):
+    grids, rules = small_batch(5, max_r=16, decay=False)
+    batch = ltl.Batch([gpu_grid(g) for g in grids], rules, "cat_i8")
+    batch.step(2)
+    best = batch.autotune(probe_steps=3)
+    assert best == batch.tuning()
+    assert batch.steps_done == 2
+    batch.step(3)
+    check_batch(batch, [oracle.run(g, r, 5) for g, r in zip(grids, rules)], f"autotuned {best}")
+    batch.close()
+
+
+# ------------------------------------------------------------------ the 512-instance workload
+def _instance_grid(inst):
+    return inputs.bernoulli_grid(inst.H, inst.W, 0.5, inst.seed)
+
+
+@pytest.mark.parametrize("method", ["cat_i8"])
+def test_batch_512_instances(ltl, method):
+    """The batched workload at full size (512 instances, 32 steps, one hipGraph): the cheapest
+    instances against the oracle in full, cells of the largest ones against the oracle on
+    their dependency cones, and every instance against the single-grid path."""
+    insts = inputs.batch_instances()
+    steps = 32
+    dev = [inputs.bernoulli_grid_torch(x.H, x.W, 0.5, x.seed, device="cuda") for x in insts]
+    grids = [g.cpu().numpy() for g in dev]
+    assert np.array_equal(grids[0], _instance_grid(insts[0]))   # same cells as the numpy generator
+    batch = ltl.Batch(dev, [x.rule for x in insts], method)
+    batch.step(steps)
+    torch.cuda.synchronize()
+    got = [batch.read(i).cpu().numpy() for i in range(len(insts))]
+    batch.close()
+
+    oracle.set_threads(0)
+    cost = [x.H * x.W * (2 * x.rule.R + 1) ** 2 for x in insts]
+    order = np.argsort(cost)
+    spent = 0
+    for i in order[:64]:
+        if spent > 4e9:
+            break
+        spent += cost[i] * steps
+        ref = oracle.run(grids[i], insts[i].rule, steps)
+        assert np.array_equal(got[i], ref), f"instance {i} ({insts[i].H}x{insts[i].W} {insts[i].rule.text()})"
+
+    # dependency-cone samples of the largest instances (corner, edge, interior cells)
+    largest = sorted(range(len(insts)), key=lambda i: -insts[i].H * insts[i].W)[:12]
+    for i in largest:
+        x = insts[i]
+        reach = steps * x.rule.R
+        for (ci, cj) in [(0, 0), (x.H - 1, x.W // 2), (x.H // 2, x.W // 3)]:
+            window = (min(x.H, ci + reach + 1) - max(0, ci - reach)) * (min(x.W, cj + reach + 1) - max(0, cj - reach))
+            if window * (2 * x.rule.R + 1) ** 2 * steps > 3e9:
+                continue
+            ref = oracle.cone_run(lambda rows, cols, x=x: inputs.bernoulli_grid(x.H, x.W, 0.5, x.seed, rows=rows, cols=cols),
+                                  x.H, x.W, x.rule, steps, ci, cj, radius=2)
+            a0, b0 = max(0, ci - 2), max(0, cj - 2)
+            assert np.array_equal(got[i][a0:a0 + ref.shape[0], b0:b0 + ref.shape[1]], ref), f"instance {i} cell {(ci, cj)}"
+
+    # every instance equals its own single-grid simulation
+    for i, x in enumerate(insts):
+        sim = ltl.Simulation(dev[i], x.rule, method, tuning=dict(steps_per_launch=1))
+        sim.step(steps)
+        assert np.array_equal(got[i], sim.read().cpu().numpy()), f"instance {i} vs single grid"
+        sim.close()

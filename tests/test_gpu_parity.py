@@ -59,6 +59,17 @@ def run_and_compare(ltl, g0, rule, method, steps, tuning=None, chunks=None):
 
 
 METHODS = ["cat_i8", "direct"]
+ALL_METHODS = ["cat_i8", "cat_f16", "cat_f8", "direct"]
+
+
+def f8_refuses(ltl, rule):
+    """fp8-e4m3 counts are exact only for 2r+1 <= 16: larger radii must be refused."""
+    if rule.R <= 7:
+        return False
+    with pytest.raises(ltl.LtlError) as e:
+        ltl.Simulation(gpu_grid(np.zeros((8, 8), dtype=np.uint8)), rule, "cat_f8")
+    assert e.value.code == ltl.LTL_ERR_INEXACT
+    return True
 
 SMALL_RULES = [
     inputs.LIFE,
@@ -79,26 +90,31 @@ SMALL_RULES = [
 ]
 
 
-@pytest.mark.parametrize("method", METHODS)
+@pytest.mark.parametrize("method", ALL_METHODS)
 @pytest.mark.parametrize("rule", SMALL_RULES, ids=lambda r: r.text())
 def test_every_step_small_ragged(ltl, method, rule):
+    if method == "cat_f8" and f8_refuses(ltl, rule):
+        return
     g0 = inputs.bernoulli_grid(83, 151, 0.5, seed=rule.R * 7 + rule.C)
     run_and_compare_each_step(ltl, g0, rule, method, 6)
 
 
 @pytest.mark.parametrize("shape", [(1, 1), (1, 40), (37, 1), (16, 32), (17, 33), (255, 257), (300, 65)])
-@pytest.mark.parametrize("method", METHODS)
+@pytest.mark.parametrize("method", ALL_METHODS)
 def test_shapes(ltl, shape, method):
     rule = inputs.Rule(3, 0, 1, 12, 22, 13, 16)
     g0 = inputs.bernoulli_grid(shape[0], shape[1], 0.5, seed=shape[0] * 1000 + shape[1])
     run_and_compare(ltl, g0, rule, method, 5)
 
 
-def shape_feasible(r, T, TH, TW, waves=8, maxc=14, lds_max=160 * 1024):
-    """Whether the CAT kernel can run this launch shape: the LDS tile fits and in every step the
+def shape_feasible(r, T, TH, TW, waves=8, maxc=14, cell=1, lds_max=160 * 1024):
+    """Whether the CAT kernel can run this launch shape: the LDS tiles fit and in every step the
     32-column strips times the row segments (at most `maxc` 16-row blocks) fit the waves."""
     margin = -(-r * (T - 1) // 16) * 16 + 16
-    lds = -(-(TH + 2 * margin) * (TW + 2 * margin + 16) // 1024) * 1024
+    rows, cols = TH + 2 * margin, TW + 2 * margin
+    lds = -(-rows * (cols + 16) // 1024) * 1024
+    if cell == 2:   # fp16: a second tile holds the alive map, two bytes per cell
+        lds += -(-rows * (2 * cols + 16) // 1024) * 1024
     if lds > lds_max:
         return False
     for t in range(1, T + 1):
@@ -110,19 +126,24 @@ def shape_feasible(r, T, TH, TW, waves=8, maxc=14, lds_max=160 * 1024):
     return True
 
 
+@pytest.mark.parametrize("method", ["cat_i8", "cat_f16", "cat_f8"])
 @pytest.mark.parametrize("T", [1, 2, 3, 4, 7])
 @pytest.mark.parametrize("r", [1, 2, 5, 6, 9, 16])
-def test_temporal_blocking(ltl, T, r):
+def test_temporal_blocking(ltl, T, r, method):
     rule = inputs.sweep_rule(r)
+    if method == "cat_f8" and f8_refuses(ltl, rule):
+        return
     g0 = inputs.bernoulli_grid(200, 333, 0.5, seed=100 + r)
     tuning = dict(steps_per_launch=T, tile_rows=64, tile_cols=64, waves=0)
-    if not shape_feasible(r, T, 64, 64):
+    maxc = 5 if method == "cat_f16" else 14
+    cell = 2 if method == "cat_f16" else 1
+    if not shape_feasible(r, T, 64, 64, maxc=maxc, cell=cell):
         # the library must refuse a launch shape it cannot run
         with pytest.raises(ltl.LtlError) as e:
-            run_and_compare(ltl, g0, rule, "cat_i8", 9, tuning=tuning)
+            run_and_compare(ltl, g0, rule, method, 9, tuning=tuning)
         assert e.value.code == ltl.LTL_ERR_ARG
         return
-    run_and_compare(ltl, g0, rule, "cat_i8", 9, tuning=tuning)
+    run_and_compare(ltl, g0, rule, method, 9, tuning=tuning)
 
 
 @pytest.mark.parametrize("tile", [(16, 32), (32, 64), (64, 64), (128, 128), (48, 96), (192, 128), (128, 224), (80, 224)])
@@ -145,11 +166,12 @@ def test_wave_count_must_cover_the_strips(ltl):
     sim.close()
 
 
-def test_decay_multistep(ltl):
+@pytest.mark.parametrize("method", ["cat_i8", "cat_f16", "cat_f8"])
+def test_decay_multistep(ltl, method):
     rule = inputs.Rule(5, 6, 0, 30, 54, 32, 41)
     g0 = inputs.state_grid(190, 230, 6, seed=12)
     for T in (1, 2, 4):
-        run_and_compare(ltl, g0, rule, "cat_i8", 8, tuning=dict(steps_per_launch=T))
+        run_and_compare(ltl, g0, rule, method, 8, tuning=dict(steps_per_launch=T, waves=0))
     run_and_compare(ltl, g0, rule, "direct", 8)
 
 
