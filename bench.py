@@ -4,7 +4,12 @@ A bench step is one full run of the workload: ``ltl_step(100)`` on the Bosco-typ
 R5 C0 M1 S34..58 B34..45 N_M over a 4096 x 4096 uint8 grid (Bernoulli(0.5), seed 2, dead
 ghost halo), inputs resident in HBM. Prints one JSON line.
 
-  python bench.py [--gpus 1] [--steps K] [--warmup W] [--sweep] [--no-cpu]
+Also reported (not the headline value): the batched workload (512 instances of log-uniform
+sides in [128, 2048], r uniform in 1..16, per-instance rules; one ``ltl_batch_step(32)``
+hipGraph per bench step), and with --sweep the radius sweep r = 1..16 on 16384^2 for the
+int8, fp16 and fp8 (r <= 7) CAT variants and the direct stencil.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--sweep] [--no-cpu] [--no-batch] [--autotune]
 """
 from __future__ import annotations
 
@@ -22,6 +27,34 @@ METRIC = "cell-updates/s vs radius r=1..16, CAT int8-MFMA vs direct stencil, bit
 INT8_PEAK_TOPS = 5000.0  # MI355X dense int8 MFMA
 HBM_PEAK_GBS = 8000.0
 OPS_PER_CELL = 256       # two 16x16x64 int8 MFMAs per 256 cells, 2 ops per multiply-add
+DEFAULT_TUNING = "5,128,192,8"   # steps per launch, tile rows, tile cols, waves
+KERNEL_SRC = [os.path.join(ROOT, "paper_2406_17284_amd", "csrc", f) for f in ("cat_device.h", "cat_kernel.hip")]
+BATCH_TUNING = "2,192,192,8"   # the autotuner's pick for the 512-instance batch on MI355X
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "cat_step_i8_bosco4096_traffic.json")
+
+
+def kernel_hash() -> str:
+    import hashlib
+
+    h = hashlib.sha256()
+    for path in KERNEL_SRC:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def recorded_traffic(tuning):
+    """HBM bytes per launch from the committed FETCH_SIZE / WRITE_SIZE counter record, if it was
+    taken on this kernel source and launch shape; else None."""
+    try:
+        with open(TRAFFIC_RECORD) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    shape = [tuning[k] for k in ("steps_per_launch", "tile_rows", "tile_cols", "waves")]
+    if rec.get("kernel_sha256") != kernel_hash() or rec.get("tuning") != shape:
+        return None
+    return rec["hbm_bytes_per_launch"]
 
 
 def timed_runs(sim, n_per_run, runs, torch):
@@ -39,6 +72,48 @@ def timed_runs(sim, n_per_run, runs, torch):
     return ev0.elapsed_time(ev1) / 1e3, wall
 
 
+def bench_batch(args, ltl, inputs, torch):
+    """The batched workload: 512 automata advanced together, 32 steps per bench step."""
+    insts = inputs.batch_instances()
+    steps = 32
+    dev = [inputs.bernoulli_grid_torch(x.H, x.W, 0.5, x.seed, device="cuda") for x in insts]
+    rules = [x.rule for x in insts]
+    cells = sum(x.H * x.W for x in insts)
+    res = {"workload": "512 instances, sides log-uniform in [128, 2048], r uniform in 1..16, S/B uniform in "
+                       "[0.2, 0.5] x (2r+1)^2, M1, Bernoulli(0.5), 32 steps per bench step (one hipGraph)",
+           "cells": cells}
+    bt = ltl.Batch(dev, rules, "cat_i8")
+    if args.autotune:
+        bt.autotune(probe_steps=4)
+    else:
+        T, th, tw, wv = (int(x) for x in args.batch_tuning.split(","))
+        bt.set_tuning(steps_per_launch=T, tile_rows=th, tile_cols=tw, waves=wv)
+    for _ in range(max(1, args.warmup)):
+        bt.step(steps)
+    secs, _ = timed_runs(bt, steps, args.steps, torch)
+    res["value"] = cells * steps * args.steps / secs
+    res["unit"] = "cell-updates/s"
+    res["ms_per_bench_step"] = secs / args.steps * 1e3
+    res["tuning"] = bt.tuning()
+    bt.close()
+
+    db = ltl.Batch(dev, rules, "direct")
+    db.step(steps)
+    dsecs, _ = timed_runs(db, steps, 1, torch)
+    res["direct_stencil_cell_updates_per_s"] = cells * steps / dsecs
+    db.close()
+
+    # cross-check: a fresh CAT batch and the direct batch after the same 32 steps, all instances
+    a = ltl.Batch(dev, rules, "cat_i8")
+    b = ltl.Batch(dev, rules, "direct")
+    a.step(steps)
+    b.step(steps)
+    res["cat_vs_direct_equal"] = all(torch.equal(a.read(i), b.read(i)) for i in range(len(insts)))
+    a.close()
+    b.close()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -47,8 +122,11 @@ def main():
     ap.add_argument("--sweep", action="store_true", help="also time the radius sweep r=1..16 on 16384^2")
     ap.add_argument("--sweep-side", type=int, default=16384)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--no-autotune", action="store_true")
-    ap.add_argument("--tuning", type=str, default="", help="T,tile_rows,tile_cols,waves")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 512-instance batched workload")
+    ap.add_argument("--batch-tuning", type=str, default=BATCH_TUNING, help="T,tile_rows,tile_cols,waves of the batch")
+    ap.add_argument("--autotune", action="store_true", help="pick the launch shape with ltl_autotune")
+    ap.add_argument("--tuning", type=str, default=DEFAULT_TUNING,
+                    help="T,tile_rows,tile_cols,waves (default: the autotuner's pick on MI355X)")
     ap.add_argument("--calib-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (HBM counter calibration) and exit")
     args = ap.parse_args()
@@ -80,11 +158,11 @@ def main():
 
     # ---- CAT int8
     sim = ltl.Simulation(g0, w.rule, "cat_i8")
-    if args.tuning:
+    if args.autotune:
+        sim.autotune(probe_steps=20)
+    else:
         T, th, tw, wv = (int(x) for x in args.tuning.split(","))
         sim.set_tuning(steps_per_launch=T, tile_rows=th, tile_cols=tw, waves=wv)
-    elif not args.no_autotune:
-        sim.autotune(probe_steps=20)
     tuning = sim.tuning()
     for _ in range(args.warmup):
         sim.step(w.steps)
@@ -144,7 +222,7 @@ def main():
             "peak": INT8_PEAK_TOPS,
             "unit": "TFLOP/s",
             "frac": achieved_tops / INT8_PEAK_TOPS,
-            "traffic": None,
+            "traffic": recorded_traffic(tuning),
             "kernel": "cat_step_i8",
             "ops_per_cell_update": OPS_PER_CELL,
             "avg_launch_us": avg_launch_s * 1e6,
@@ -160,9 +238,11 @@ def main():
         for r in range(1, 17):
             rule = inputs.sweep_rule(r)
             row = {}
-            for method in ("cat_i8", "direct"):
+            for method in ("cat_i8", "cat_f16", "cat_f8", "direct"):
+                if method == "cat_f8" and r > 7:
+                    continue   # fp8-e4m3 counts are exact only for 2r+1 <= 16
                 s = ltl.Simulation(gs, rule, method)
-                if method == "cat_i8" and not args.no_autotune:
+                if method != "direct":
                     s.autotune(probe_steps=10)
                 s.step(50)
                 secs_r, _ = timed_runs(s, 50, 1, torch)
@@ -171,6 +251,9 @@ def main():
             sweep[str(r)] = row
         out["sweep"] = {"workload": f"{side}x{side}, r=1..16 sweep rules, Bernoulli(0.5) seed 3, 50 steps",
                         "cell_updates_per_s": sweep}
+
+    if not args.no_batch:
+        out["batched"] = bench_batch(args, ltl, inputs, torch)
 
     if not args.no_cpu:
         import oracle

@@ -470,11 +470,21 @@ ltl_tuning_t batch_fill_tuning(const ltl_batch &b, const ltl_tuning_t &in) {
     return t;
 }
 
+// Default: one step per launch, 128 x 192 tiles (rows shrunk by 16 at a time until every
+// instance's strips x segments fit 8 waves; fp16 holds fewer row blocks per wave).
 ltl_tuning_t batch_default_tuning(const ltl_batch &b) {
     ltl_tuning_t t;
     std::memset(&t, 0, sizeof(t));
     t.use_graph = 1;
-    return batch_fill_tuning(b, t);
+    t = batch_fill_tuning(b, t);
+    if (b.method != LTL_DIRECT) {
+        while (t.tile_rows > 16 && !batch_fits(b, t)) {
+            t.tile_rows -= 16;
+            t.waves = 0;
+            t = batch_fill_tuning(b, t);
+        }
+    }
+    return t;
 }
 
 size_t batch_cat_lds(const ltl_batch &b, const ltl_tuning_t &t, int T, int32_t *slot) {

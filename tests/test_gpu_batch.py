@@ -142,10 +142,11 @@ def test_batch_f8_refuses_large_radius(ltl):
 
 def test_batch_rejects_bad_states(ltl):
     g = np.zeros((8, 8), dtype=np.uint8)
-    bad = g.copy()
+    ok3, bad = g.copy(), g.copy()
+    ok3[3, 3] = 3
     bad[3, 3] = 4
     rules = [inputs.Rule(2, 0, 1, 5, 9, 5, 7), inputs.Rule(2, 4, 1, 5, 9, 5, 7)]
-    ltl.Batch([gpu_grid(g), gpu_grid(bad - 1)], rules, "cat_i8").close()   # state 3 < C = 4
+    ltl.Batch([gpu_grid(g), gpu_grid(ok3)], rules, "cat_i8").close()   # state 3 < C = 4
     with pytest.raises(ltl.LtlError) as e:
         ltl.Batch([gpu_grid(bad), gpu_grid(g)], rules, "cat_i8")   # state 4 >= 2 for C = 0
     assert e.value.code == ltl.LTL_ERR_STATE
