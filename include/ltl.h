@@ -37,7 +37,7 @@ enum {
     LTL_ERR_RULE = -2,        /* R outside 1..16, C == 1 or > 255, M not 0/1, threshold < 0 or > (2R+1)^2 */
     LTL_ERR_UNSUPPORTED = -3, /* neighbourhood other than Moore ('M') */
     LTL_ERR_INEXACT = -4,     /* FP8 method with 2R+1 > 16: counts would not be exact in e4m3 */
-    LTL_ERR_SIZE = -5,        /* buffer smaller than ltl_buffer_bytes() */
+    LTL_ERR_SIZE = -5,        /* buffer smaller than ltl_buffer_bytes(), or grid over 2^31 - 1 bytes */
     LTL_ERR_HIP = -6,         /* HIP runtime error (message in ltl_last_error) */
     LTL_ERR_STATE = -7        /* an initial cell holds a state >= max(C, 2) */
 };
@@ -86,6 +86,8 @@ int32_t ltl_pitch(int32_t W, int32_t *pitch);
  *  init       device pointer to H rows of W uint8 states, row pitch init_pitch >= W bytes;
  *             read before ltl_create returns. Every state must be < max(C, 2) (else LTL_ERR_STATE).
  *  stream     HIP stream for all work of this handle (0 = null stream).
+ * A grid may hold at most 2^31 - 1 bytes in the library layout (H x ltl_pitch(W); e.g. up to
+ * 46340 x 46340 cells); larger grids are refused with LTL_ERR_SIZE.
  * ltl_create synchronizes `stream` once (state validation); later calls do not. */
 int32_t ltl_create(ltl_sim_t **out, int32_t H, int32_t W, const ltl_rule_t *rule, int32_t method,
                    void *buf_a, void *buf_b, size_t buf_bytes, const void *init, size_t init_pitch,

@@ -106,6 +106,10 @@ RuleConsts make_consts(const ltl_rule_t &r, int epi) {
 
 int pitch_of(int W) { return roundup(W, 64); }
 
+// Largest grid the kernels address: row offsets are 32-bit (H x pitch < 2^31 bytes).
+constexpr size_t kMaxGridBytes = 0x7FFFFFFF;
+bool grid_too_large(int H, int W) { return (size_t)H * (size_t)pitch_of(W) > kMaxGridBytes; }
+
 size_t max_lds_bytes() {
     static size_t v = 0;
     if (v == 0) {
@@ -855,6 +859,7 @@ int32_t ltl_create(ltl_sim_t **out, int32_t H, int32_t W, const ltl_rule_t *rule
     if (!buf_a || !buf_b || !init) return fail(LTL_ERR_ARG, "NULL buffer");
     if (buf_a == buf_b) return fail(LTL_ERR_ARG, "the two buffers must differ");
     if (init_pitch < (size_t)W) return fail(LTL_ERR_ARG, "init_pitch < W");
+    if (grid_too_large(H, W)) return fail(LTL_ERR_SIZE, "grid larger than 2^31 - 1 bytes (H x ltl_pitch(W))");
     if (((uintptr_t)buf_a & 255) || ((uintptr_t)buf_b & 255)) return fail(LTL_ERR_ARG, "buffers must be 256-byte aligned");
     int32_t rc = validate_rule(rule, method);
     if (rc != LTL_OK) return rc;
@@ -1068,6 +1073,8 @@ int32_t ltl_batch_create(ltl_batch_t **out, int32_t count, const int32_t *H, con
         if ((rc = validate_rule(rules + i, method)) != LTL_OK) return fail(rc, "instance " + std::to_string(i) + ": " + g_err);
         if (!init[i]) return fail(LTL_ERR_ARG, "instance " + std::to_string(i) + ": NULL initial grid");
         if (init_pitch[i] < (size_t)W[i]) return fail(LTL_ERR_ARG, "instance " + std::to_string(i) + ": init_pitch < W");
+        if (grid_too_large(H[i], W[i]))
+            return fail(LTL_ERR_SIZE, "instance " + std::to_string(i) + ": grid larger than 2^31 - 1 bytes");
     }
     if (bytes < need) return fail(LTL_ERR_SIZE, "arenas need " + std::to_string(need) + " bytes each");
 

@@ -60,6 +60,7 @@ def _create(H=8, W=8, rule=(1, 0, 1, 3, 4, 3, 3), method=ltl.LTL_CAT_I8, a=256, 
     (dict(rule=(8, 0, 1, 3, 4, 3, 3), method=ltl.LTL_CAT_F8), ltl.LTL_ERR_INEXACT),
     (dict(method=7), ltl.LTL_ERR_ARG),
     (dict(nbytes=63), ltl.LTL_ERR_SIZE),
+    (dict(H=32768, W=65536, nbytes=1 << 31, pitch=65536), ltl.LTL_ERR_SIZE),   # 2^31 bytes: too large
 ])
 def test_create_rejects_bad_arguments(kw, code):
     with pytest.raises(ltl.LtlError) as e:
@@ -105,6 +106,7 @@ def _batch_create(H=(8, 8), W=(8, 8), rules=((1, 0, 1, 3, 4, 3, 3), (2, 3, 0, 5,
     (dict(rules=((7, 0, 1, 3, 4, 3, 3), (8, 0, 1, 3, 4, 3, 3)), method=ltl.LTL_CAT_F8), ltl.LTL_ERR_INEXACT),
     (dict(method=9), ltl.LTL_ERR_ARG),
     (dict(nbytes=1023), ltl.LTL_ERR_SIZE),
+    (dict(H=(8, 46341), W=(8, 46341), pitches=(8, 46341), nbytes=1 << 33), ltl.LTL_ERR_SIZE),
 ])
 def test_batch_create_rejects_bad_arguments(kw, code):
     with pytest.raises(ltl.LtlError) as e:

@@ -1,0 +1,120 @@
+"""GPU parity at the workloads' full sizes, in the launch configuration the benchmark times.
+
+At these sizes the oracle cannot run the whole grid, so the checks are:
+  * sampled cells against the oracle on their dependency cones (oracle.cone_run): corner,
+    edge and interior windows, after a few steps for every radius and after all steps where
+    the cone stays small;
+  * properties that hold at any size: every CAT precision variant and the direct stencil
+    (independent kernels, each oracle-verified cell for cell at smaller sizes) produce the
+    identical grid; the padding columns stay dead.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2406_17284_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+CONE_BUDGET = 3e9          # oracle cell-additions per sampled window
+
+
+@pytest.fixture(scope="module")
+def ltl():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2406_17284_amd import ltl as mod
+    mod.load()
+    oracle.set_threads(0)
+    return mod
+
+
+def sample_points(H, W):
+    return [(0, 0), (H - 1, W - 1), (0, W // 2), (H // 2, 0), (H // 2, W // 2), (H // 3, (2 * W) // 3),
+            (H - 1, 7), (5, W - 3)]
+
+
+def cone_checks(sim_state, H, W, rule, steps, seed, budget=CONE_BUDGET, radius=2):
+    """Compare windows of the GPU grid `sim_state` (torch, H x W) after `steps` steps with the
+    oracle on the dependency cone of each sample point. Returns the number of windows checked."""
+    checked = 0
+    reach = steps * rule.R
+    for (i, j) in sample_points(H, W):
+        rows = min(H, i + reach + 1) - max(0, i - reach)
+        cols = min(W, j + reach + 1) - max(0, j - reach)
+        if rows * cols * (2 * rule.R + 1) ** 2 * steps > budget:
+            continue
+        ref = oracle.cone_run(lambda rr, cc: inputs.bernoulli_grid(H, W, 0.5, seed, rows=rr, cols=cc),
+                              H, W, rule, steps, i, j, radius=radius)
+        a0, b0 = max(0, i - radius), max(0, j - radius)
+        got = sim_state[a0:a0 + ref.shape[0], b0:b0 + ref.shape[1]].cpu().numpy()
+        assert np.array_equal(got, ref), f"{rule.text()} step {steps} window at {(i, j)}"
+        checked += 1
+    return checked
+
+
+SWEEP_SIDE = 16384
+SWEEP_STEPS = 50
+EARLY = 6
+
+
+@pytest.fixture(scope="module")
+def sweep_grid(ltl):
+    return inputs.bernoulli_grid_torch(SWEEP_SIDE, SWEEP_SIDE, 0.5, 3, device="cuda")
+
+
+@pytest.mark.parametrize("r", list(range(1, 17)))
+def test_radius_sweep_16384(ltl, sweep_grid, r):
+    """Radius sweep workload: 16384^2, sweep rule of radius r, 50 steps, autotuned CAT int8 (as
+    the benchmark runs it); fp16 for every r and fp8 for r <= 7 must give the same grid, and
+    so must the direct stencil."""
+    rule = inputs.sweep_rule(r)
+    side = SWEEP_SIDE
+    cat = ltl.Simulation(sweep_grid, rule, "cat_i8")
+    cat.autotune(probe_steps=10)
+    cat.step(EARLY)
+    n = cone_checks(cat.read(), side, side, rule, EARLY, seed=3)
+    assert n >= 4
+    cat.step(SWEEP_STEPS - EARLY)
+    final = cat.read()
+    assert not cat.current_padded()[:, side:].any()
+    cone_checks(final, side, side, rule, SWEEP_STEPS, seed=3)
+    cat.close()
+
+    others = ["direct", "cat_f16"] + (["cat_f8"] if r <= 7 else [])
+    for method in others:
+        s = ltl.Simulation(sweep_grid, rule, method)
+        s.step(SWEEP_STEPS)
+        assert torch.equal(s.read(), final), f"{method} r={r} differs from cat_i8 after {SWEEP_STEPS} steps"
+        s.close()
+
+
+def test_decay_c8_32768(ltl):
+    """Multi-state decay workload: R16 C8 M0 S300..500 B330..420, 32768^2, 20 steps. At
+    density 0.5 every box count exceeds both ranges, so almost every cell dies in step 1 and
+    the grid is fully dead by step 20; the structured checks are therefore at steps 3 and 6,
+    while all decay states 2..7 are present."""
+    w = inputs.WORKLOADS["decay32768"]
+    g = inputs.bernoulli_grid_torch(w.H, w.W, w.p, w.seed, device="cuda")
+    cat = ltl.Simulation(g, w.rule, "cat_i8")
+    direct = ltl.Simulation(g, w.rule, "direct")
+    cat.autotune(probe_steps=4)
+    del g
+    done = 0
+    for k in (3, 6, w.steps):
+        cat.step(k - done)
+        direct.step(k - done)
+        done = k
+        state = cat.read()
+        if k < w.steps:
+            assert cone_checks(state, w.H, w.W, w.rule, k, seed=w.seed) >= 4
+        assert torch.equal(state, direct.read()), f"cat_i8 and direct differ after {k} steps"
+        if k == 6:
+            counts = torch.bincount(state.flatten().to(torch.int64), minlength=w.rule.C)
+            assert bool((counts[2:] > 0).all()), counts.tolist()   # every decay state occurs
+        del state
+    assert not cat.current_padded()[:, w.W:].any()
+    cat.close()
+    direct.close()
