@@ -6,13 +6,14 @@ package. It shares no code with the HIP library and never imports it.
 Two independent implementations of the same definition:
 
 * ``count`` / ``step`` / ``run``: the C oracle in ``ltl_oracle.c`` (direct
-  (2r+1)^2 box count with a dead ghost halo, then the LTL transition), OpenMP
-  over rows, reached through ctypes;
+  (2r+1)^2 box count with a dead ghost halo or on a torus, then the LTL
+  transition), OpenMP over rows, reached through ctypes;
 * ``np_count`` / ``np_step`` / ``np_run``: a NumPy transcription for tiny grids
-  (zero-padded shifted-window sum), used to cross-check the C code.
+  (zero-padded shifted-window sum, or a sum of ``np.roll`` shifts on a torus),
+  used to cross-check the C code.
 
 Paper passages followed: "Formulation of CAT", Eq. 2-3 (the Moore reduction is a
-box sum of half-width r, dead ghost halo), the centre remark after Fig. 3
+box sum of half-width r, dead ghost halo; the experiments' periodic boundary, "Experimental design"), the centre remark after Fig. 3
 (centre removal when the rule excludes it), the rule notation of "Chosen CA
 tests" (R, C, M, S, B, N), and the ping-pong step of "Pseudocode of CAT's
 Kernel" (synchronous update). Readings for what the paper leaves open are in the
@@ -53,6 +54,12 @@ def _load() -> ctypes.CDLL:
         I64, I = ctypes.c_int64, ctypes.c_int
         lib.oracle_count.argtypes = [P, I64, I64, I, P]
         lib.oracle_count.restype = None
+        lib.oracle_count_periodic.argtypes = [P, I64, I64, I, P]
+        lib.oracle_count_periodic.restype = None
+        lib.oracle_step_b.argtypes = [P, P, I64, I64, I, I, I, I, I, I, I, I]
+        lib.oracle_step_b.restype = I
+        lib.oracle_run_b.argtypes = [P, I64, I64, I, I, I, I, I, I, I, I, I]
+        lib.oracle_run_b.restype = I
         lib.oracle_step.argtypes = [P, P, I64, I64, I, I, I, I, I, I, I]
         lib.oracle_step.restype = I
         lib.oracle_run.argtypes = [P, I64, I64, I, I, I, I, I, I, I, I]
@@ -73,38 +80,48 @@ def set_threads(n: int = 0) -> int:
     return _load().oracle_set_threads(int(n))
 
 
-def count(grid: np.ndarray, r: int) -> np.ndarray:
-    """Box count of alive (== 1) cells of radius r, centre included, dead outside."""
+def count(grid: np.ndarray, r: int, periodic: bool = False) -> np.ndarray:
+    """Box count of alive (== 1) cells of radius r, centre included; dead outside, or
+    on a torus when ``periodic``."""
     g = np.ascontiguousarray(grid, dtype=np.uint8)
     H, W = g.shape
     out = np.empty((H, W), dtype=np.int32)
-    _load().oracle_count(g.ctypes.data, H, W, int(r), out.ctypes.data)
+    fn = _load().oracle_count_periodic if periodic else _load().oracle_count
+    fn(g.ctypes.data, H, W, int(r), out.ctypes.data)
     return out
 
 
-def step(grid: np.ndarray, rule) -> np.ndarray:
+def step(grid: np.ndarray, rule, periodic: bool = False) -> np.ndarray:
     g = np.ascontiguousarray(grid, dtype=np.uint8)
     out = np.empty_like(g)
-    rc = _load().oracle_step(g.ctypes.data, out.ctypes.data, g.shape[0], g.shape[1], *_rule_args(rule))
+    rc = _load().oracle_step_b(g.ctypes.data, out.ctypes.data, g.shape[0], g.shape[1], *_rule_args(rule),
+                               int(bool(periodic)))
     if rc != 0:
         raise RuntimeError("oracle_step failed")
     return out
 
 
-def run(grid: np.ndarray, rule, steps: int) -> np.ndarray:
+def run(grid: np.ndarray, rule, steps: int, periodic: bool = False) -> np.ndarray:
     g = np.array(grid, dtype=np.uint8, order="C", copy=True)
-    rc = _load().oracle_run(g.ctypes.data, g.shape[0], g.shape[1], *_rule_args(rule), int(steps))
+    rc = _load().oracle_run_b(g.ctypes.data, g.shape[0], g.shape[1], *_rule_args(rule), int(steps),
+                              int(bool(periodic)))
     if rc != 0:
         raise RuntimeError("oracle_run failed")
     return g
 
 
 # --------------------------------------------------------------- NumPy version
-def np_count(grid: np.ndarray, r: int) -> np.ndarray:
+def np_count(grid: np.ndarray, r: int, periodic: bool = False) -> np.ndarray:
     """Same box count as :func:`count`, as a sum of (2r+1)^2 shifted windows of a
-    zero-padded alive map."""
+    zero-padded alive map, or of (2r+1)^2 cyclic shifts (``np.roll``) on a torus."""
     a = (np.asarray(grid) == 1).astype(np.int32)
     H, W = a.shape
+    if periodic:
+        out = np.zeros((H, W), dtype=np.int32)
+        for di in range(-r, r + 1):
+            for dj in range(-r, r + 1):
+                out += np.roll(a, (-di, -dj), axis=(0, 1))
+        return out
     p = np.zeros((H + 2 * r, W + 2 * r), dtype=np.int32)
     p[r:r + H, r:r + W] = a
     out = np.zeros((H, W), dtype=np.int32)
@@ -114,11 +131,11 @@ def np_count(grid: np.ndarray, r: int) -> np.ndarray:
     return out
 
 
-def np_step(grid: np.ndarray, rule) -> np.ndarray:
+def np_step(grid: np.ndarray, rule, periodic: bool = False) -> np.ndarray:
     R, C, M, S1, S2, B1, B2 = _rule_args(rule)
     s = np.asarray(grid, dtype=np.int32)
     states = C if C >= 3 else 2
-    n = np_count(s, R)
+    n = np_count(s, R, periodic)
     c = n - ((s == 1) & (M == 0)).astype(np.int32)
     born = (B1 <= c) & (c <= B2)
     keep = (S1 <= c) & (c <= S2)
@@ -128,10 +145,10 @@ def np_step(grid: np.ndarray, rule) -> np.ndarray:
     return nxt.astype(np.uint8)
 
 
-def np_run(grid: np.ndarray, rule, steps: int) -> np.ndarray:
+def np_run(grid: np.ndarray, rule, steps: int, periodic: bool = False) -> np.ndarray:
     g = np.asarray(grid, dtype=np.uint8)
     for _ in range(steps):
-        g = np_step(g, rule)
+        g = np_step(g, rule, periodic)
     return g
 
 

@@ -12,6 +12,12 @@
  * Eq. 2-3 compute exactly this box sum as Lambda x Pi followed by Pi x H with Pi the
  * band matrix of ones of half-width r; the oracle writes the sum out directly.
  *
+ * Periodic boundary (the paper's experimental setting, "Experimental design"; the overview
+ * figure fills the ghost halo from the opposite edges): the grid is a torus and the count
+ * sums the (2r+1)^2 offsets (di, dj) of the cell at ((i + di) mod H, (j + dj) mod W). On a
+ * torus smaller than the box, one cell can be reached by several offsets and is then
+ * counted once per offset (the sum is the cyclic convolution with the box).
+ *
  * Readings taken where the paper is silent (each is listed in the design notes):
  *  - only state 1 is alive; with M = 0 the centre's own alive bit is removed once
  *    (the band of Eq. 2-3 holds the diagonal once, so the box counts the centre once);
@@ -60,6 +66,28 @@ void oracle_count(const uint8_t *s, int64_t H, int64_t W, int r, int32_t *cnt)
     }
 }
 
+/* Periodic box count: offsets wrap around both dimensions (cyclic convolution of the
+ * alive map with the (2r+1) x (2r+1) box). */
+void oracle_count_periodic(const uint8_t *s, int64_t H, int64_t W, int r, int32_t *cnt)
+{
+    int64_t i;
+#pragma omp parallel for schedule(static)
+    for (i = 0; i < H; ++i) {
+        for (int64_t j = 0; j < W; ++j) {
+            int32_t c = 0;
+            for (int di = -r; di <= r; ++di) {
+                int64_t ii = ((i + di) % H + H) % H;
+                const uint8_t *row = s + ii * W;
+                for (int dj = -r; dj <= r; ++dj) {
+                    int64_t jj = ((j + dj) % W + W) % W;
+                    c += (row[jj] == 1);
+                }
+            }
+            cnt[i * W + j] = c;
+        }
+    }
+}
+
 /* The transition of one cell given its state and its box count n (centre included). */
 static uint8_t transition(uint8_t s, int32_t n, int C, int M, int S1, int S2, int B1, int B2)
 {
@@ -77,9 +105,10 @@ static uint8_t transition(uint8_t s, int32_t n, int C, int M, int S1, int S2, in
     return (uint8_t)((s + 1 < states) ? s + 1 : 0);
 }
 
-/* One synchronous step: out = f(s). out must not alias s. Returns 0 or -1 on bad args. */
-int oracle_step(const uint8_t *s, uint8_t *out, int64_t H, int64_t W,
-                int R, int C, int M, int S1, int S2, int B1, int B2)
+/* One synchronous step: out = f(s). out must not alias s. periodic: 0 dead ghost halo,
+ * 1 torus. Returns 0 or -1 on bad args. */
+int oracle_step_b(const uint8_t *s, uint8_t *out, int64_t H, int64_t W,
+                  int R, int C, int M, int S1, int S2, int B1, int B2, int periodic)
 {
     if (!s || !out || H < 0 || W < 0 || R < 0)
         return -1;
@@ -88,7 +117,10 @@ int oracle_step(const uint8_t *s, uint8_t *out, int64_t H, int64_t W,
     int32_t *cnt = (int32_t *)malloc((size_t)H * (size_t)W * sizeof(int32_t));
     if (!cnt)
         return -1;
-    oracle_count(s, H, W, R, cnt);
+    if (periodic)
+        oracle_count_periodic(s, H, W, R, cnt);
+    else
+        oracle_count(s, H, W, R, cnt);
     int64_t k, n = H * W;
 #pragma omp parallel for schedule(static)
     for (k = 0; k < n; ++k)
@@ -97,9 +129,15 @@ int oracle_step(const uint8_t *s, uint8_t *out, int64_t H, int64_t W,
     return 0;
 }
 
+int oracle_step(const uint8_t *s, uint8_t *out, int64_t H, int64_t W,
+                int R, int C, int M, int S1, int S2, int B1, int B2)
+{
+    return oracle_step_b(s, out, H, W, R, C, M, S1, S2, B1, B2, 0);
+}
+
 /* steps synchronous steps applied to grid in place (ping-pong with a scratch copy). */
-int oracle_run(uint8_t *grid, int64_t H, int64_t W, int R, int C, int M,
-               int S1, int S2, int B1, int B2, int steps)
+int oracle_run_b(uint8_t *grid, int64_t H, int64_t W, int R, int C, int M,
+                 int S1, int S2, int B1, int B2, int steps, int periodic)
 {
     if (!grid || steps < 0)
         return -1;
@@ -110,7 +148,7 @@ int oracle_run(uint8_t *grid, int64_t H, int64_t W, int R, int C, int M,
         return -1;
     uint8_t *a = grid, *b = tmp;
     for (int t = 0; t < steps; ++t) {
-        if (oracle_step(a, b, H, W, R, C, M, S1, S2, B1, B2) != 0) {
+        if (oracle_step_b(a, b, H, W, R, C, M, S1, S2, B1, B2, periodic) != 0) {
             free(tmp);
             return -1;
         }
@@ -120,6 +158,12 @@ int oracle_run(uint8_t *grid, int64_t H, int64_t W, int R, int C, int M,
         memcpy(grid, a, (size_t)H * (size_t)W);
     free(tmp);
     return 0;
+}
+
+int oracle_run(uint8_t *grid, int64_t H, int64_t W, int R, int C, int M,
+               int S1, int S2, int B1, int B2, int steps)
+{
+    return oracle_run_b(grid, H, W, R, C, M, S1, S2, B1, B2, steps, 0);
 }
 
 int oracle_set_threads(int n)

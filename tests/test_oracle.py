@@ -337,3 +337,120 @@ def test_cone_run_matches_full_run():
     for (i, j) in [(0, 0), (45, 60), (89, 119), (10, 100)]:
         got = oracle.cone_run(fn, H, W, rule, 5, i, j, radius=2)
         assert np.array_equal(got, ref[max(0, i - 2):i + 3, max(0, j - 2):j + 3])
+
+
+# ------------------------------------------------------------------ periodic boundary (torus)
+def _circ_dist(a, b, n):
+    d = abs(a - b) % n
+    return min(d, n - d)
+
+
+@pytest.mark.parametrize("impl", ["c", "np"])
+@pytest.mark.parametrize("name,torus", [("glider", (10, 10)), ("glider", (8, 13)), ("lwss", (9, 12)),
+                                         ("blinker", (5, 5)), ("block", (4, 4))])
+def test_periodic_spaceships_return(name, torus, impl):
+    """On an H x W torus a pattern moving (di, dj) per period is back where it started after
+    lcm-many periods; the dead halo would have destroyed it at the edge."""
+    import math
+    pat, period, di, dj = PATTERNS[name]
+    H, W = torus
+    g0 = np.zeros((H, W), dtype=np.uint8)
+    g0[1:1 + pat.shape[0], 1:1 + pat.shape[1]] = pat
+    k = 1
+    while (k * di) % H or (k * dj) % W:
+        k += 1
+    run = oracle.run if impl == "c" else oracle.np_run
+    g = run(g0, LIFE, k * period, periodic=True)
+    assert np.array_equal(g, g0)
+    # one period moves it by (di, dj) around the torus
+    assert np.array_equal(run(g0, LIFE, period, periodic=True), np.roll(g0, (di, dj), axis=(0, 1)))
+
+
+@pytest.mark.parametrize("r", [1, 2, 5])
+@pytest.mark.parametrize("shape", [(11, 11), (12, 17), (40, 33)])
+def test_periodic_count_single_cell_is_a_wrapped_box(r, shape):
+    H, W = shape
+    for (ci, cj) in [(0, 0), (H - 1, W - 1), (H // 2, 0)]:
+        g = np.zeros((H, W), dtype=np.uint8)
+        g[ci, cj] = 1
+        exp = np.array([[1 if _circ_dist(i, ci, H) <= r and _circ_dist(j, cj, W) <= r else 0
+                         for j in range(W)] for i in range(H)], dtype=np.int32)
+        assert np.array_equal(oracle.count(g, r, periodic=True), exp)
+        assert np.array_equal(oracle.np_count(g, r, periodic=True), exp)
+
+
+@pytest.mark.parametrize("r", [1, 3, 6])
+@pytest.mark.parametrize("n", [1, 2, 3, 7])
+def test_periodic_count_on_a_torus_smaller_than_the_box(r, n):
+    """Closed form: offset d in [-r, r] reaches the cell at distance d mod n, so cell (a, b)
+    is counted m(a - i) * m(b - j) times, m(k) = #{d in [-r, r] : d = k mod n}."""
+    rng = np.random.default_rng(r * 10 + n)
+    g = (rng.random((n, n + 1)) < 0.5).astype(np.uint8)
+    H, W = g.shape
+
+    def m(k, size):
+        return sum(1 for d in range(-r, r + 1) if (d - k) % size == 0)
+
+    exp = np.zeros((H, W), dtype=np.int32)
+    for i in range(H):
+        for j in range(W):
+            exp[i, j] = sum(int(g[a, b]) * m(a - i, H) * m(b - j, W) for a in range(H) for b in range(W))
+    assert np.array_equal(oracle.count(g, r, periodic=True), exp)
+    assert np.array_equal(oracle.np_count(g, r, periodic=True), exp)
+
+
+@pytest.mark.parametrize("r", [1, 2, 5, 9])
+def test_periodic_box_sized_torus_counts_the_population(r):
+    """On a (2r+1) x (2r+1) torus the box of every cell is the whole torus, each cell once."""
+    n = 2 * r + 1
+    g = (np.random.default_rng(r).random((n, n)) < 0.3).astype(np.uint8)
+    assert (oracle.count(g, r, periodic=True) == int(g.sum())).all()
+    assert (oracle.np_count(g, r, periodic=True) == int(g.sum())).all()
+
+
+@pytest.mark.parametrize("r", [1, 2, 4, 8])
+def test_periodic_count_matches_scipy_wrap_convolution(r):
+    from scipy import ndimage
+    rng = np.random.default_rng(r)
+    g = (rng.random((3 * r + 7, 5 * r + 3)) < 0.4).astype(np.uint8)
+    exp = ndimage.convolve(g.astype(np.int32), np.ones((2 * r + 1, 2 * r + 1), dtype=np.int32), mode="wrap")
+    assert np.array_equal(oracle.count(g, r, periodic=True), exp)
+
+
+@pytest.mark.parametrize("rule", [LIFE, inputs.Rule(3, 0, 0, 12, 22, 13, 16), inputs.Rule(2, 5, 1, 6, 11, 6, 8),
+                                  inputs.Rule(7, 0, 1, 60, 110, 55, 80)], ids=lambda r: r.text())
+def test_periodic_step_commutes_with_translations(rule):
+    """A torus has no distinguished cell: shifting the grid commutes with the step."""
+    rng = np.random.default_rng(7)
+    states = max(rule.C, 2)
+    g = rng.integers(0, states, size=(23, 31)).astype(np.uint8)
+    ref = oracle.step(g, rule, periodic=True)
+    for shift in [(1, 0), (0, 1), (5, 13), (22, 30)]:
+        assert np.array_equal(oracle.step(np.roll(g, shift, axis=(0, 1)), rule, periodic=True),
+                              np.roll(ref, shift, axis=(0, 1)))
+    # and the dead halo does not (the edge is distinguished)
+    dead = oracle.step(g, rule)
+    assert not np.array_equal(oracle.step(np.roll(g, (5, 13), axis=(0, 1)), rule), np.roll(dead, (5, 13), axis=(0, 1)))
+
+
+def test_periodic_equals_dead_halo_far_from_the_edges():
+    rule = inputs.BOSCO_M1
+    rng = np.random.default_rng(3)
+    g = np.zeros((120, 130), dtype=np.uint8)
+    g[50:70, 55:75] = (rng.random((20, 20)) < 0.5)
+    # the pattern's dependency cone grows r cells per step: 4 steps stay 30 cells clear of the edges
+    assert np.array_equal(oracle.run(g, rule, 4, periodic=True), oracle.run(g, rule, 4))
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_periodic_c_and_numpy_oracles_agree(seed):
+    rng = np.random.default_rng(100 + seed)
+    r = int(rng.integers(1, 8))
+    n = (2 * r + 1) ** 2
+    C = int(rng.choice([0, 2, 4]))
+    s = sorted(int(x) for x in rng.integers(0, n + 1, size=2))
+    b = sorted(int(x) for x in rng.integers(0, n + 1, size=2))
+    rule = inputs.Rule(r, C, int(rng.integers(0, 2)), s[0], s[1], b[0], b[1])
+    H, W = int(rng.integers(1, 40)), int(rng.integers(1, 40))
+    g = rng.integers(0, max(C, 2), size=(H, W)).astype(np.uint8)
+    assert np.array_equal(oracle.run(g, rule, 3, periodic=True), oracle.np_run(g, rule, 3, periodic=True))
