@@ -68,6 +68,11 @@ typedef struct {
     int32_t use_graph;        /* 1: replay multi-launch loops from a cached hipGraph */
 } ltl_tuning_t;
 
+typedef enum {
+    LTL_BOUNDARY_DEAD = 0,
+    LTL_BOUNDARY_PERIODIC = 1
+} ltl_boundary_t;
+
 typedef struct ltl_sim ltl_sim_t;
 typedef struct ltl_batch ltl_batch_t;
 
@@ -112,6 +117,16 @@ int32_t ltl_set_tuning(ltl_sim_t *sim, const ltl_tuning_t *tuning);
  * copy of the current state so the simulation itself does not advance), keep the
  * fastest and return it in *best (may be NULL). Synchronizes the stream. */
 int32_t ltl_autotune(ltl_sim_t *sim, int32_t probe_steps, ltl_tuning_t *best);
+
+/* Boundary condition of the grid (default LTL_BOUNDARY_DEAD).
+ *  LTL_BOUNDARY_DEAD      ghost halo of dead cells: every cell outside the grid is 0 forever.
+ *  LTL_BOUNDARY_PERIODIC  the grid is a torus (the paper's experimental setting, "Experimental
+ *                         design"): the box of a cell wraps around both edges, offset (di, dj)
+ *                         reaching cell ((i + di) mod H, (j + dj) mod W); on a torus smaller
+ *                         than the box a cell is counted once per offset that reaches it.
+ *                         Requires W % 16 == 0 (else LTL_ERR_UNSUPPORTED).
+ * Takes effect for the following steps; columns W..pitch-1 of the buffers stay 0. */
+int32_t ltl_set_boundary(ltl_sim_t *sim, int32_t boundary);
 
 /* Release the handle (graphs, descriptors). Does not free the caller's buffers and does
  * not synchronize; the caller synchronizes the stream first. NULL is accepted. */

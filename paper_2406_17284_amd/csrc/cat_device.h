@@ -398,16 +398,17 @@ __device__ __forceinline__ void phase_b(const CatParams &p, uint8_t *Qt, uint8_t
 #define CAT_FINISH(M)                                                                              \
     {                                                                                              \
         const int grow = gr0 + 16 * (M);                                                           \
-        uint32_t rowm = 0xFFFFFFFFu;                                                               \
-        if (MASKED) rowm = ((unsigned)grow < (unsigned)p.H) ? 0xFFFFFFFFu : 0u;                    \
+        /* rows outside the grid: dead (forced to 0) under the dead halo, torus copies otherwise */ \
+        const bool rowin = !MASKED || (unsigned)grow < (unsigned)p.H;                              \
+        const uint32_t rowm = (rowin || p.periodic) ? 0xFFFFFFFFu : 0u;                            \
         uint32_t ala, alb;                                                                         \
         const uint32_t na = transition4<EPI>(ca[(M) & 3], sa[(M) & 3], rowm & cma, p.rc, &ala);    \
         const uint32_t nb = transition4<EPI>(cb[(M) & 3], sb[(M) & 3], rowm & cmb, p.rc, &alb);    \
         if constexpr (LAST) {                                                                      \
             const uint32_t go = goff0 + (uint32_t)(16 * (M)) * (uint32_t)p.pitch;                  \
-            if (!MASKED || rowm) {                                                                 \
-                if (!MASKED || (unsigned)gca < (unsigned)p.pitch) *(gdword *)(p.dst + go) = na;    \
-                if (!MASKED || (unsigned)(gca + 16) < (unsigned)p.pitch) *(gdword *)(p.dst + go + 16) = nb; \
+            if (rowin) {                                                                           \
+                if (!MASKED || (unsigned)gca < (unsigned)p.store_w) *(gdword *)(p.dst + go) = na;  \
+                if (!MASKED || (unsigned)(gca + 16) < (unsigned)p.store_w) *(gdword *)(p.dst + go + 16) = nb; \
             }                                                                                      \
         } else {                                                                                   \
             const uint32_t qo = lo.q + (uint32_t)(16 * (rb0 + (M))) * PS;                          \
@@ -493,9 +494,11 @@ __device__ __forceinline__ void cat_steps(const CatParams &p, uint8_t *Qt, uint8
         if (count > 0) {
             const int gca = gj0 + j0 + 4 * lg;
             uint32_t cma = 0xFFFFFFFFu, cmb = 0xFFFFFFFFu;
-            if constexpr (MASKED) {
-                cma = col_mask(gca, p.W);
-                cmb = col_mask(gca + 16, p.W);
+            if constexpr (MASKED) {   // dead halo: cells right of the grid stay 0
+                if (!p.periodic) {
+                    cma = col_mask(gca, p.W);
+                    cmb = col_mask(gca + 16, p.W);
+                }
             }
             const int gr0 = gi0 + 16 * rb0 + li;
             const uint32_t goff0 = (uint32_t)(gr0 * p.pitch + gca);
@@ -510,7 +513,8 @@ __device__ __forceinline__ void cat_steps(const CatParams &p, uint8_t *Qt, uint8
 
 // Stream the (TH + 2L) x PS window of the tile at (gi0, gj0) into LDS at `buf` with direct
 // global->LDS loads: wave w moves KiB chunks w, w + nwaves, ...; lane l of a chunk carries
-// the 16 bytes at buffer offset 1024 c + 16 l. Cells outside the grid come from the zero page.
+// the 16 bytes at buffer offset 1024 c + 16 l. Cells outside the grid come from the zero page
+// (dead halo) or from the opposite edge (torus).
 __device__ __forceinline__ void issue_tile_load(const CatParams &p, int gi0, int gj0, uint8_t *buf, int wave,
                                                 int nwaves, int lane, float inv_ps) {
     const int rows = p.TH + 2 * p.L;
@@ -524,8 +528,18 @@ __device__ __forceinline__ void issue_tile_load(const CatParams &p, int gi0, int
         const int gr = gi0 - p.L + lr;
         const int gc = gj0 - p.L + lc;
         const uint8_t *g = p.zero;
-        if (lr < rows && (unsigned)gr < (unsigned)p.H && (unsigned)gc < (unsigned)p.pitch)
+        if (p.periodic) {
+            // torus: wrap both coordinates (W is a multiple of 16, so a 16-byte vector at a
+            // 16-aligned column wraps as a whole)
+            if (lr < rows) {
+                int wr = gr % p.H, wc = gc % p.W;
+                wr += (wr < 0) ? p.H : 0;
+                wc += (wc < 0) ? p.W : 0;
+                g = p.src + (size_t)wr * p.pitch + wc;
+            }
+        } else if (lr < rows && (unsigned)gr < (unsigned)p.H && (unsigned)gc < (unsigned)p.pitch) {
             g = p.src + (size_t)gr * p.pitch + gc;
+        }
         // The load is issued from inline assembly: the compiler cannot see which LDS bytes an
         // LDS-DMA writes, so for its own builtin it would make every later LDS access wait for
         // all outstanding vector-memory operations. The caller waits (vmcnt(0) + barrier) before

@@ -35,8 +35,14 @@ __device__ __forceinline__ void direct_tile(const DirectParams &p, int gi0, int 
         int gr = gi0 - r + lr;
         int gc = gj0 - r + lc;
         uint8_t v = 0;
-        if ((unsigned)gr < (unsigned)p.H && (unsigned)gc < (unsigned)p.W)
+        if (p.periodic) {   // torus: wrap both coordinates
+            int wr = gr % p.H, wc = gc % p.W;
+            wr += (wr < 0) ? p.H : 0;
+            wc += (wc < 0) ? p.W : 0;
+            v = p.src[(size_t)wr * p.pitch + wc];
+        } else if ((unsigned)gr < (unsigned)p.H && (unsigned)gc < (unsigned)p.W) {
             v = p.src[(size_t)gr * p.pitch + gc];
+        }
         lds[lr * p.LP + lc] = (v == 1) ? 1 : 0;
     }
     __syncthreads();

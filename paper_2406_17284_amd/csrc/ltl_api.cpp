@@ -138,6 +138,7 @@ struct ltl_sim {
     ltl_tuning_t tuning{};
     uint32_t *dflag = nullptr;
     uint8_t *dconst = nullptr;   // band tables for r = 1..16, then a zero page
+    int periodic = 0;            // LTL_BOUNDARY_PERIODIC: the grid is a torus
     std::map<std::pair<int32_t, int>, hipGraphExec_t> graphs;
 };
 
@@ -190,6 +191,8 @@ CatParams cat_params(const ltl_sim &s, const ltl_tuning_t &t, int T, const uint8
     p.nty = (s.H + p.TH - 1) / p.TH;
     p.bands = reinterpret_cast<const int32_t *>(s.dconst);
     p.zero = s.dconst + kBandBytes;
+    p.periodic = s.periodic;
+    p.store_w = s.periodic ? s.W : s.pitch;
     p.rc = s.rc;
     return p;
 }
@@ -205,6 +208,7 @@ DirectParams direct_params(const ltl_sim &s, const uint8_t *src, uint8_t *dst) {
     p.TH = 32;
     p.TW = 64;
     p.LP = 64 + 2 * p.r;
+    p.periodic = s.periodic;
     p.rc = s.rc;
     return p;
 }
@@ -430,6 +434,8 @@ CatParams batch_cat_params(const ltl_batch &b, int i, const ltl_tuning_t &t, int
     p.nty = (p.H + p.TH - 1) / p.TH;
     p.bands = reinterpret_cast<const int32_t *>(b.dconst + (p.r - 1) * kBandBytes);
     p.zero = b.dconst + kMaxR * kBandBytes;
+    p.periodic = 0;              // batched instances have a dead ghost halo
+    p.store_w = p.pitch;
     p.rc = b.rc[i];
     return p;
 }
@@ -982,6 +988,7 @@ int32_t ltl_autotune(ltl_sim_t *sim, int32_t probe_steps, ltl_tuning_t *best) {
     ltl_sim probe;
     probe.H = s.H; probe.W = s.W; probe.pitch = s.pitch; probe.rule = s.rule; probe.method = s.method;
     probe.epi = s.epi; probe.rc = s.rc; probe.buf[0] = scratch[0]; probe.buf[1] = scratch[1];
+    probe.periodic = s.periodic;
     probe.dconst = s.dconst;
     probe.stream = s.stream;
     hipEvent_t ev0, ev1;
@@ -1032,6 +1039,16 @@ done:
     clear_graphs(s);
     s.tuning = best_t;
     if (best) *best = best_t;
+    return LTL_OK;
+}
+
+int32_t ltl_set_boundary(ltl_sim_t *sim, int32_t boundary) {
+    if (!sim) return fail(LTL_ERR_ARG, "sim is NULL");
+    if (boundary != LTL_BOUNDARY_DEAD && boundary != LTL_BOUNDARY_PERIODIC) return fail(LTL_ERR_ARG, "unknown boundary");
+    if (boundary == LTL_BOUNDARY_PERIODIC && sim->W % 16 != 0)
+        return fail(LTL_ERR_UNSUPPORTED, "a periodic grid needs W divisible by 16");
+    clear_graphs(*sim);
+    sim->periodic = (boundary == LTL_BOUNDARY_PERIODIC) ? 1 : 0;
     return LTL_OK;
 }
 

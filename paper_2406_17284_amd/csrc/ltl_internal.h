@@ -46,6 +46,8 @@ struct CatParams {
     int32_t a_tile;          // LDS offset of the alive tile (0: the state tile itself)
     int32_t lds_total;       // dynamic LDS bytes of the launch
     int32_t ntx, nty;        // tiles across / down the grid
+    int32_t periodic;        // 1: the grid is a torus (W % 16 == 0); 0: dead ghost halo
+    int32_t store_w;         // columns the last step stores: W (torus) or pitch (dead halo, zero padding)
     RuleConsts rc;
 };
 
@@ -118,6 +120,7 @@ struct DirectParams {
     int32_t r;
     int32_t TH, TW;       // output tile of the direct kernel
     int32_t LP;           // LDS row pitch
+    int32_t periodic;     // 1: the grid is a torus; 0: dead ghost halo
     RuleConsts rc;
 };
 

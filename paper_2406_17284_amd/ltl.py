@@ -27,11 +27,14 @@ LTL_CAT_F16 = 1
 LTL_CAT_F8 = 2
 LTL_DIRECT = 3
 METHODS = {"cat_i8": LTL_CAT_I8, "cat_f16": LTL_CAT_F16, "cat_f8": LTL_CAT_F8, "direct": LTL_DIRECT}
+LTL_BOUNDARY_DEAD = 0
+LTL_BOUNDARY_PERIODIC = 1
+BOUNDARIES = {"dead": LTL_BOUNDARY_DEAD, "periodic": LTL_BOUNDARY_PERIODIC}
 
 # every symbol the header declares
 EXPORTS = [
     "ltl_buffer_bytes", "ltl_pitch", "ltl_create", "ltl_step", "ltl_read", "ltl_current",
-    "ltl_get_tuning", "ltl_set_tuning", "ltl_autotune", "ltl_destroy", "ltl_last_error",
+    "ltl_get_tuning", "ltl_set_tuning", "ltl_autotune", "ltl_set_boundary", "ltl_destroy", "ltl_last_error",
     "ltl_batch_buffer_bytes", "ltl_batch_create", "ltl_batch_step", "ltl_batch_read",
     "ltl_batch_current", "ltl_batch_get_tuning", "ltl_batch_set_tuning", "ltl_batch_autotune",
     "ltl_batch_destroy",
@@ -78,6 +81,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "ltl_get_tuning": ([P, ctypes.POINTER(ltl_tuning_t)], I32),
         "ltl_set_tuning": ([P, ctypes.POINTER(ltl_tuning_t)], I32),
         "ltl_autotune": ([P, I32, ctypes.POINTER(ltl_tuning_t)], I32),
+        "ltl_set_boundary": ([P, I32], I32),
         "ltl_destroy": ([P], I32),
         "ltl_last_error": ([], ctypes.c_char_p),
         "ltl_batch_buffer_bytes": ([I32, P, P, PSZ], I32),
@@ -185,6 +189,10 @@ def ltl_autotune(sim: int, probe_steps: int) -> ltl_tuning_t:
     return t
 
 
+def ltl_set_boundary(sim: int, boundary: int) -> None:
+    _check(load().ltl_set_boundary(ctypes.c_void_p(sim), int(boundary)))
+
+
 def ltl_destroy(sim: int) -> None:
     _check(load().ltl_destroy(ctypes.c_void_p(sim)))
 
@@ -255,7 +263,8 @@ def ltl_batch_destroy(batch: int) -> None:
 class Simulation:
     """One automaton whose two ping-pong buffers are torch uint8 tensors on the GPU."""
 
-    def __init__(self, init, rule, method="cat_i8", stream=None, tuning: Optional[dict] = None):
+    def __init__(self, init, rule, method="cat_i8", stream=None, tuning: Optional[dict] = None,
+                 boundary="dead"):
         import torch
 
         if isinstance(method, str):
@@ -271,6 +280,8 @@ class Simulation:
         self.handle = ltl_create(self.H, self.W, rule, method, self.bufs[0].data_ptr(), self.bufs[1].data_ptr(),
                                  nbytes, init.data_ptr(), init.stride(0), self.stream)
         self.device = init.device
+        if boundary != "dead":
+            ltl_set_boundary(self.handle, BOUNDARIES[boundary] if isinstance(boundary, str) else int(boundary))
         if tuning:
             ltl_set_tuning(self.handle, **tuning)
 

@@ -75,6 +75,7 @@ def test_null_handles():
     assert lib.ltl_read(None, None, 0) == ltl.LTL_ERR_ARG
     assert lib.ltl_destroy(None) == ltl.LTL_OK
     assert lib.ltl_batch_destroy(None) == ltl.LTL_OK
+    assert lib.ltl_set_boundary(None, ltl.LTL_BOUNDARY_PERIODIC) == ltl.LTL_ERR_ARG
     t = ltl.ltl_tuning_t()
     assert lib.ltl_get_tuning(None, ctypes.byref(t)) == ltl.LTL_ERR_ARG
 

@@ -212,3 +212,73 @@ def test_bosco_4096_full(ltl):
         got = sim.read().cpu().numpy()
         sim.close()
         assert np.array_equal(got, ref), method
+
+
+# ------------------------------------------------------------------ periodic boundary (torus)
+PERIODIC_SHAPES = [(16, 16), (1, 16), (5, 32), (48, 64), (83, 160), (200, 336)]
+PERIODIC_RULES = [inputs.LIFE, inputs.BOSCO_M1, inputs.Rule(9, 0, 0, 90, 160, 97, 122),
+                  inputs.Rule(3, 5, 1, 12, 22, 13, 16), inputs.Rule(16, 0, 1, 272, 490, 294, 370),
+                  inputs.Rule(6, 0, 1, 42, 76, 45, 57)]
+
+
+def run_periodic(ltl, g0, rule, method, steps, tuning=None, every_step=True):
+    sim = ltl.Simulation(gpu_grid(g0), rule, method, tuning=tuning, boundary="periodic")
+    ref = g0.copy()
+    for t in range(steps if every_step else 1):
+        n = 1 if every_step else steps
+        sim.step(n)
+        ref = oracle.run(ref, rule, n, periodic=True)
+        got = sim.read().cpu().numpy()
+        if not np.array_equal(got, ref):
+            bad = np.argwhere(got != ref)
+            raise AssertionError(f"periodic {method} {rule.text()} {g0.shape} tuning={tuning}: step {t + 1} "
+                                 f"differs at {len(bad)} cells, first {bad[:5].tolist()}")
+    assert not sim.current_padded()[:, g0.shape[1]:].any()
+    sim.close()
+
+
+@pytest.mark.parametrize("method", ALL_METHODS)
+@pytest.mark.parametrize("rule", PERIODIC_RULES, ids=lambda r: r.text())
+@pytest.mark.parametrize("shape", PERIODIC_SHAPES, ids=lambda s: f"{s[0]}x{s[1]}")
+def test_periodic_every_step(ltl, method, rule, shape):
+    if method == "cat_f8" and f8_refuses(ltl, rule):
+        return
+    H, W = shape
+    g0 = (inputs.state_grid(H, W, rule.C, seed=H * 1000 + W) if rule.C >= 3
+          else inputs.bernoulli_grid(H, W, 0.5, seed=H * 1000 + W))
+    run_periodic(ltl, g0, rule, method, 4)
+
+
+@pytest.mark.parametrize("method", ["cat_i8", "cat_f16"])
+@pytest.mark.parametrize("T", [2, 3, 5, 7])
+@pytest.mark.parametrize("r", [1, 5, 16])
+def test_periodic_temporal_blocking(ltl, method, T, r):
+    rule = inputs.sweep_rule(r)
+    g0 = inputs.bernoulli_grid(200, 336, 0.5, seed=300 + r)
+    tuning = dict(steps_per_launch=T, tile_rows=64, tile_cols=64, waves=0)
+    maxc = 5 if method == "cat_f16" else 14
+    cell = 2 if method == "cat_f16" else 1
+    if not shape_feasible(r, T, 64, 64, maxc=maxc, cell=cell):
+        pytest.skip("launch shape not runnable")
+    run_periodic(ltl, g0, rule, method, 9, tuning=tuning, every_step=False)
+    # a torus smaller than the loaded window (margins wrap several times)
+    run_periodic(ltl, inputs.bernoulli_grid(24, 32, 0.5, seed=301 + r), rule, method, 7, tuning=tuning,
+                 every_step=False)
+
+
+def test_periodic_needs_width_multiple_of_16(ltl):
+    sim = ltl.Simulation(gpu_grid(np.zeros((8, 40), dtype=np.uint8)), inputs.LIFE, "cat_i8")
+    with pytest.raises(ltl.LtlError) as e:
+        ltl.ltl_set_boundary(sim.handle, ltl.LTL_BOUNDARY_PERIODIC)
+    assert e.value.code == ltl.LTL_ERR_UNSUPPORTED
+    sim.close()
+
+
+def test_periodic_glider_wraps_on_gpu(ltl):
+    g0 = np.zeros((32, 48), dtype=np.uint8)
+    g0[1:4, 1:4] = np.array([[0, 1, 0], [0, 0, 1], [1, 1, 1]], dtype=np.uint8)   # moves (+1, +1) per 4 steps
+    for method in ("cat_i8", "direct"):
+        sim = ltl.Simulation(gpu_grid(g0), inputs.LIFE, method, boundary="periodic")
+        sim.step(4 * 96)          # lcm(32, 48) = 96 periods of (1, 1)
+        assert np.array_equal(sim.read().cpu().numpy(), g0), method
+        sim.close()
