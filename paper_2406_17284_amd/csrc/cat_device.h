@@ -144,6 +144,7 @@ __device__ __forceinline__ uint32_t alive_of(uint32_t s) {
 // operands, and the encode / decode between alive bytes (0/1) and the LDS encoding.
 template <int ELEM> struct ElemT;
 template <> struct ElemT<ELEM_I8> { static constexpr int CELL = 1, MAXC = CAT_MAXC_I8, NOPS = 4; };
+template <> struct ElemT<ELEM_I8W> { static constexpr int CELL = 1, MAXC = CAT_MAXC_I8W, NOPS = 8; };
 template <> struct ElemT<ELEM_F8> { static constexpr int CELL = 1, MAXC = CAT_MAXC_F8, NOPS = 8; };
 template <> struct ElemT<ELEM_F16> { static constexpr int CELL = 2, MAXC = CAT_MAXC_F16, NOPS = 6; };
 
@@ -231,8 +232,50 @@ __device__ __forceinline__ uint32_t pack_f16(float a, float b) {
 // 16-column halves of the strip, packed, in registers. Software-pipelined in pairs of blocks:
 // the A chunks of the next pair are read from LDS before the MFMAs of this pair run.
 template <int ELEM>
-__device__ __forceinline__ void phase_a(const uint8_t *At, uint32_t a_off, uint32_t PA, int rb0, int count,
-                                        const Bands &bd, v16i &Ha, v16i &Hb) {
+__device__ __forceinline__ void phase_a(const uint8_t *At, uint32_t a_off, uint32_t a_off2, uint32_t PA, int rb0,
+                                        int count, const Bands &bd, v16i &Ha, v16i &Hb) {
+    if constexpr (ELEM == ELEM_I8W) {
+        // radius 17..32: H blocks rb0 - 2 .. rb0 + count + 2; per half a K = 64 product on the
+        // chunk at a_off and a K = 32 product on the 8 bytes at a_off2, summed. The two products
+        // get separate zero accumulators and a VALU add: feeding the 16x16x64 result to the
+        // 16x16x32 instruction as its accumulator input gave wrong sums on gfx950 with this
+        // toolchain (the dependency between MFMAs of different shapes is not waited for).
+        const int nh = count + 5;
+        const v4i zero = {0, 0, 0, 0};
+        v4i a[4];
+        long b[4];
+#define CAT_LDA(K)                                                                                 \
+        {                                                                                          \
+            const uint32_t ro = (uint32_t)(16 * (rb0 - 2 + (K))) * PA;                             \
+            a[(K) & 3] = *reinterpret_cast<const v4i *>(At + (a_off + ro));                        \
+            b[(K) & 3] = *reinterpret_cast<const long *>(At + (a_off2 + ro));                      \
+        }
+#define CAT_HB(K)                                                                                  \
+        {                                                                                          \
+            v4i da = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[(K) & 3], bd.op[0], zero, 0, 0, 0);   \
+            v4i ea = __builtin_amdgcn_mfma_i32_16x16x32_i8(b[(K) & 3], lo8(bd.op[1]), zero, 0, 0, 0); \
+            v4i db = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[(K) & 3], bd.op[2], zero, 0, 0, 0);   \
+            v4i eb = __builtin_amdgcn_mfma_i32_16x16x32_i8(b[(K) & 3], lo8(bd.op[3]), zero, 0, 0, 0); \
+            Ha[(K)] = (int32_t)pack_bytes(da + ea);                                                \
+            Hb[(K)] = (int32_t)pack_bytes(db + eb);                                                \
+        }
+#define CAT_APAIR(P)                                                                               \
+        if (2 * (P) < nh) {                                                                        \
+            if (2 * (P) + 2 < nh) {                                                                \
+                CAT_LDA(2 * (P) + 2)                                                               \
+                if (2 * (P) + 3 < nh) CAT_LDA(2 * (P) + 3)                                         \
+            }                                                                                      \
+            CAT_HB(2 * (P))                                                                        \
+            if (2 * (P) + 1 < nh) CAT_HB(2 * (P) + 1)                                              \
+        }
+        CAT_LDA(0) CAT_LDA(1)
+        CAT_APAIR(0) CAT_APAIR(1) CAT_APAIR(2) CAT_APAIR(3) CAT_APAIR(4) CAT_APAIR(5) CAT_APAIR(6) CAT_APAIR(7)
+#undef CAT_APAIR
+#undef CAT_HB
+#undef CAT_LDA
+        return;
+    }
+    (void)a_off2;
     const int nh = count + 2;
     if constexpr (ELEM == ELEM_I8) {
         const v4i zero = {0, 0, 0, 0};
@@ -333,7 +376,17 @@ __device__ __forceinline__ void phase_a(const uint8_t *At, uint32_t a_off, uint3
 // Vertical band product of output block M for one half (counts as int32 or biased fp32 bits).
 template <int ELEM, int M>
 __device__ __forceinline__ v4i vproduct(const v16i &H, const Bands &bd) {
-    if constexpr (ELEM == ELEM_I8) {
+    if constexpr (ELEM == ELEM_I8W) {
+        // tuple element k holds block rb0 - 2 + k; output block rb0 + M needs elements M .. M+4
+        const v4i zero = {0, 0, 0, 0};
+        if constexpr ((M & 1) == 0) {
+            v4i c = __builtin_amdgcn_mfma_i32_16x16x64_i8(window4<M>(H), bd.op[4], zero, 0, 0, 0);
+            return c + __builtin_amdgcn_mfma_i32_16x16x32_i8(window2<M + 4>(H), lo8(bd.op[5]), zero, 0, 0, 0);
+        } else {
+            v4i c = __builtin_amdgcn_mfma_i32_16x16x64_i8(window4<M - 1>(H), bd.op[6], zero, 0, 0, 0);
+            return c + __builtin_amdgcn_mfma_i32_16x16x32_i8(window2<M + 3>(H), lo8(bd.op[7]), zero, 0, 0, 0);
+        }
+    } else if constexpr (ELEM == ELEM_I8) {
         const v4i zero = {0, 0, 0, 0};
         constexpr int W0 = (M & 1) ? M - 1 : M;
         return __builtin_amdgcn_mfma_i32_16x16x64_i8(window4<W0>(H), (M & 1) ? bd.op[3] : bd.op[2], zero, 0, 0, 0);
@@ -378,7 +431,7 @@ __device__ __forceinline__ void phase_b(const CatParams &p, uint8_t *Qt, uint8_t
     {                                                                                              \
         ca[(M) & 3] = vproduct<ELEM, (M)>(Ha, bd);                                                 \
         cb[(M) & 3] = vproduct<ELEM, (M)>(Hb, bd);                                                 \
-        if constexpr (EPI == EPI_DECAY || ELEM == ELEM_I8) {                                       \
+        if constexpr (EPI == EPI_DECAY || ELEM == ELEM_I8 || ELEM == ELEM_I8W) {                   \
             const uint32_t qo = lo.q + (uint32_t)(16 * (rb0 + (M))) * PS;                          \
             sa[(M) & 3] = *reinterpret_cast<const uint32_t *>(Qt + qo);                            \
             sb[(M) & 3] = *reinterpret_cast<const uint32_t *>(Qt + qo + 16);                       \
@@ -417,7 +470,7 @@ __device__ __forceinline__ void phase_b(const CatParams &p, uint8_t *Qt, uint8_t
                 *reinterpret_cast<uint32_t *>(Qt + qo) = na;                                       \
                 *reinterpret_cast<uint32_t *>(Qt + qo + 16) = nb;                                  \
             }                                                                                      \
-            if constexpr (ELEM == ELEM_I8) {                                                       \
+            if constexpr (ELEM == ELEM_I8 || ELEM == ELEM_I8W) {                                   \
                 *reinterpret_cast<uint32_t *>(At + ao) = ala;                                      \
                 *reinterpret_cast<uint32_t *>(At + ao + 16) = alb;                                 \
             } else if constexpr (ELEM == ELEM_F8) {                                                \
@@ -443,6 +496,10 @@ __device__ __forceinline__ void phase_b(const CatParams &p, uint8_t *Qt, uint8_t
         CAT_ISSUE(0) CAT_ISSUE(1)
         CAT_BPAIR(0, 1) CAT_BPAIR(1, 1)
         CAT_BPAIR(2, 0)
+    } else if constexpr (ELEM == ELEM_I8W) {   // at most CAT_MAXC_I8W = 11 blocks
+        CAT_ISSUE(0) CAT_ISSUE(1)
+        CAT_BPAIR(0, 1) CAT_BPAIR(1, 1) CAT_BPAIR(2, 1) CAT_BPAIR(3, 1) CAT_BPAIR(4, 1)
+        CAT_BPAIR(5, 0)
     } else {
         CAT_ISSUE(0) CAT_ISSUE(1)
         CAT_BPAIR(0, 1) CAT_BPAIR(1, 1) CAT_BPAIR(2, 1) CAT_BPAIR(3, 1) CAT_BPAIR(4, 1) CAT_BPAIR(5, 1)
@@ -477,19 +534,22 @@ __device__ __forceinline__ void cat_steps(const CatParams &p, uint8_t *Qt, uint8
             count = max(0, mb_hi - mb_lo);
         }
         v16i Ha, Hb;
-        if constexpr (ELEM != ELEM_I8) {
+        if constexpr (ELEM != ELEM_I8 && ELEM != ELEM_I8W) {
             // slots no block fills may enter a window with zero weight; keep them finite
             Ha = (v16i)0;
             Hb = (v16i)0;
         }
         // this lane's A chunk (row li of a block, from column j0 - 16 + 16 lg, or + 8 lg for the
         // K = 32 element types) and its first centre cell (row li, column j0 + 4 lg)
-        const int chunk_col = (ELEM == ELEM_I8) ? (L + j0 - 16 + 16 * lg) : (L + j0 - 16 + 8 * lg);
+        const int chunk_col = (ELEM == ELEM_I8W) ? (L + j0 - 32 + 16 * lg)
+                              : (ELEM == ELEM_I8) ? (L + j0 - 16 + 16 * lg) : (L + j0 - 16 + 8 * lg);
         const uint32_t a_off = (uint32_t)((L + li) * (int)PA + chunk_col * CELL);
+        // int8 wide: the K = 32 chunk, columns j0 + 32 + 8 lg .. + 7
+        const uint32_t a_off2 = (uint32_t)((L + li) * (int)PA + (L + j0 + 32 + 8 * lg) * CELL);
         LaneOff lo;
         lo.q = (uint32_t)((L + li) * (int)PS + (L + j0 + 4 * lg));
         lo.a = (uint32_t)((L + li) * (int)PA + (L + j0 + 4 * lg) * CELL);
-        if (count > 0) phase_a<ELEM>(At, a_off, PA, rb0, count, bd, Ha, Hb);
+        if (count > 0) phase_a<ELEM>(At, a_off, a_off2, PA, rb0, count, bd, Ha, Hb);
         if (!last) __syncthreads();   // every read of the old states precedes any in-place write
         if (count > 0) {
             const int gca = gj0 + j0 + 4 * lg;
@@ -582,7 +642,7 @@ __device__ __forceinline__ void cat_tile(const CatParams &p, int tile, uint8_t *
     __syncthreads();
 
     // alive map from the loaded states (int8 without decay reads the states directly)
-    if constexpr (!(ELEM == ELEM_I8 && EPI != EPI_DECAY)) {
+    if constexpr (!((ELEM == ELEM_I8 || ELEM == ELEM_I8W) && EPI != EPI_DECAY)) {
         const int W2 = p.TW + 2 * p.L;          // window columns (the PS - W2 pad is never read)
         const int vpr = W2 >> 4;
         const int nvec = (p.TH + 2 * p.L) * vpr;
@@ -593,7 +653,7 @@ __device__ __forceinline__ void cat_tile(const CatParams &p, int tile, uint8_t *
             uint4 al = q;
             if constexpr (EPI == EPI_DECAY)
                 al = make_uint4(alive_of(q.x), alive_of(q.y), alive_of(q.z), alive_of(q.w));
-            if constexpr (ELEM == ELEM_I8) {
+            if constexpr (ELEM == ELEM_I8 || ELEM == ELEM_I8W) {
                 *reinterpret_cast<uint4 *>(At + row * p.PA + col) = al;
             } else if constexpr (ELEM == ELEM_F8) {
                 *reinterpret_cast<uint4 *>(At + row * p.PA + col) =
@@ -608,7 +668,7 @@ __device__ __forceinline__ void cat_tile(const CatParams &p, int tile, uint8_t *
         __syncthreads();
     }
     // no masking needed when every cell this tile computes lies inside the grid
-    const int E1 = p.L - 16;
+    const int E1 = (p.r * (p.T - 1) + 15) & ~15;
     const bool interior = gi0 - E1 >= 0 && gi0 + p.TH + E1 <= p.H && gj0 - E1 >= 0 && gj0 + p.TW + E1 <= p.W;
     if (interior)
         cat_steps<ELEM, EPI, false>(p, Qt, At, gi0, gj0, wave, lane, bd, cd);

@@ -42,7 +42,7 @@ int32_t hip_fail(hipError_t e, const char *what) {
 int32_t validate_rule(const ltl_rule_t *r, int method) {
     if (!r) return fail(LTL_ERR_ARG, "rule is NULL");
     if (r->N != 'M') return fail(LTL_ERR_UNSUPPORTED, "only the Moore neighbourhood (N = 'M') is supported");
-    if (r->R < 1 || r->R > 16) return fail(LTL_ERR_RULE, "radius R must be in 1..16");
+    if (r->R < 1 || r->R > 32) return fail(LTL_ERR_RULE, "radius R must be in 1..32");
     if (r->C < 0 || r->C == 1 || r->C > 255) return fail(LTL_ERR_RULE, "C must be 0 or in 2..255");
     if (r->M != 0 && r->M != 1) return fail(LTL_ERR_RULE, "M must be 0 or 1");
     const int nmax = (2 * r->R + 1) * (2 * r->R + 1);
@@ -52,6 +52,8 @@ int32_t validate_rule(const ltl_rule_t *r, int method) {
     if (method < LTL_CAT_I8 || method > LTL_DIRECT) return fail(LTL_ERR_ARG, "unknown method");
     if (method == LTL_CAT_F8 && 2 * r->R + 1 > 16)
         return fail(LTL_ERR_INEXACT, "FP8 (e4m3) counts are exact only for 2R+1 <= 16");
+    if (method == LTL_CAT_F16 && r->R > 16)
+        return fail(LTL_ERR_UNSUPPORTED, "the FP16 method covers radii 1..16 (int8 covers 1..32)");
     return LTL_OK;
 }
 
@@ -144,7 +146,8 @@ struct ltl_sim {
 
 namespace {
 
-int elem_of(int method) {
+int elem_of(int method, int R) {
+    if (method == LTL_CAT_I8 && R > 16) return ELEM_I8W;
     return method == LTL_CAT_F16 ? ELEM_F16 : method == LTL_CAT_F8 ? ELEM_F8 : ELEM_I8;
 }
 
@@ -166,7 +169,7 @@ ltl_tuning_t default_tuning(const ltl_sim &s) {
     t.tile_cols = 64;
     t.waves = 4;
     // grow the wave count until the widest step fits (one strip segment per wave)
-    while (t.waves < 8 && !cat_shape_fits(elem_of(s.method), s.rule.R, t.steps_per_launch, t.tile_rows, t.tile_cols,
+    while (t.waves < 8 && !cat_shape_fits(elem_of(s.method, s.rule.R), s.rule.R, t.steps_per_launch, t.tile_rows, t.tile_cols,
                                           t.waves))
         t.waves *= 2;
     t.use_graph = 1;
@@ -184,9 +187,9 @@ CatParams cat_params(const ltl_sim &s, const ltl_tuning_t &t, int T, const uint8
     p.T = T;
     p.TH = t.tile_rows;
     p.TW = t.tile_cols;
-    p.L = cat_margin(p.r, T);
+    p.L = cat_margin(elem_of(s.method, s.rule.R), p.r, T);
     p.lds_rows = p.TH + 2 * p.L;
-    cat_lds_layout(elem_of(s.method), s.epi, p.TH, p.TW, p.L, &p.PS, &p.PA, &p.lds_tile, &p.a_tile, &p.lds_total);
+    cat_lds_layout(elem_of(s.method, s.rule.R), s.epi, p.TH, p.TW, p.L, &p.PS, &p.PA, &p.lds_tile, &p.a_tile, &p.lds_total);
     p.ntx = (s.W + p.TW - 1) / p.TW;
     p.nty = (s.H + p.TH - 1) / p.TH;
     p.bands = reinterpret_cast<const int32_t *>(s.dconst);
@@ -220,11 +223,11 @@ int32_t check_tuning(const ltl_sim &s, const ltl_tuning_t &t) {
     if (t.waves < 1 || t.waves > (s.method == LTL_DIRECT ? 16 : 8)) return fail(LTL_ERR_ARG, "waves must be in 1..8");
     if (s.method != LTL_DIRECT) {
         CatParams p = cat_params(s, t, t.steps_per_launch, nullptr, nullptr);
-        size_t lds = cat_lds_bytes(p, elem_of(s.method), s.epi);
+        size_t lds = cat_lds_bytes(p, elem_of(s.method, s.rule.R), s.epi);
         if (lds > max_lds_bytes()) return fail(LTL_ERR_ARG, "launch shape needs " + std::to_string(lds) + " bytes of LDS");
-        if (s.dconst && cat_occupancy(p, elem_of(s.method), s.epi, t.waves) < 1)
+        if (s.dconst && cat_occupancy(p, elem_of(s.method, s.rule.R), s.epi, t.waves) < 1)
             return fail(LTL_ERR_ARG, "launch shape does not fit on a compute unit (registers or LDS)");
-        if (!cat_shape_fits(elem_of(s.method), s.rule.R, t.steps_per_launch, t.tile_rows, t.tile_cols, t.waves))
+        if (!cat_shape_fits(elem_of(s.method, s.rule.R), s.rule.R, t.steps_per_launch, t.tile_rows, t.tile_cols, t.waves))
             return fail(LTL_ERR_ARG, "launch shape has more strip segments than waves in some step");
     } else if (t.steps_per_launch != 1) {
         return fail(LTL_ERR_ARG, "the direct method takes one step per launch");
@@ -251,7 +254,7 @@ PlannedLaunch plan(const ltl_sim &s, int steps_in_launch, int from) {
         pl.k = direct_launch_shape(pl.dp);
     } else {
         pl.cp = cat_params(s, s.tuning, steps_in_launch, src, dst);
-        pl.k = cat_launch_shape(pl.cp, elem_of(s.method), s.epi, s.tuning.waves);
+        pl.k = cat_launch_shape(pl.cp, elem_of(s.method, s.rule.R), s.epi, s.tuning.waves);
     }
     return pl;
 }
@@ -427,9 +430,9 @@ CatParams batch_cat_params(const ltl_batch &b, int i, const ltl_tuning_t &t, int
     p.r = b.rule[i].R;
     p.T = T;
     instance_tile(p.H, p.W, t.tile_rows, t.tile_cols, &p.TH, &p.TW);
-    p.L = cat_margin(p.r, T);
+    p.L = cat_margin(elem_of(b.method, 16), p.r, T);
     p.lds_rows = p.TH + 2 * p.L;
-    cat_lds_layout(elem_of(b.method), b.epi[i], p.TH, p.TW, p.L, &p.PS, &p.PA, &p.lds_tile, &p.a_tile, &p.lds_total);
+    cat_lds_layout(elem_of(b.method, 16), b.epi[i], p.TH, p.TW, p.L, &p.PS, &p.PA, &p.lds_tile, &p.a_tile, &p.lds_total);
     p.ntx = (p.W + p.TW - 1) / p.TW;
     p.nty = (p.H + p.TH - 1) / p.TH;
     p.bands = reinterpret_cast<const int32_t *>(b.dconst + (p.r - 1) * kBandBytes);
@@ -460,7 +463,7 @@ bool batch_fits(const ltl_batch &b, const ltl_tuning_t &t) {
     for (int i = 0; i < b.count; ++i) {
         int th, tw;
         instance_tile(b.H[i], b.W[i], t.tile_rows, t.tile_cols, &th, &tw);
-        if (!cat_shape_fits(elem_of(b.method), b.rule[i].R, t.steps_per_launch, th, tw, t.waves)) return false;
+        if (!cat_shape_fits(elem_of(b.method, 16), b.rule[i].R, t.steps_per_launch, th, tw, t.waves)) return false;
     }
     return true;
 }
@@ -517,7 +520,7 @@ int32_t batch_check_tuning(const ltl_batch &b, const ltl_tuning_t &t) {
     int32_t slot;
     size_t lds = batch_cat_lds(b, t, t.steps_per_launch, &slot);
     if (lds > max_lds_bytes()) return fail(LTL_ERR_ARG, "launch shape needs " + std::to_string(lds) + " bytes of LDS");
-    if (b.dconst && cat_batch_occupancy(elem_of(b.method), t.waves, lds) < 1)
+    if (b.dconst && cat_batch_occupancy(elem_of(b.method, 16), t.waves, lds) < 1)
         return fail(LTL_ERR_ARG, "launch shape does not fit on a compute unit (registers or LDS)");
     return LTL_OK;
 }
@@ -645,7 +648,7 @@ int32_t batch_plan(ltl_batch &b, int T, BatchLaunchPlan **out) {
                     x.p = batch_cat_params(b, i, b.tuning, T, par);
                 }
             pl.lds = batch_cat_lds(b, b.tuning, T, &pl.slot);
-            const int occ = cat_batch_occupancy(elem_of(b.method), b.tuning.waves, pl.lds);
+            const int occ = cat_batch_occupancy(elem_of(b.method, 16), b.tuning.waves, pl.lds);
             if (occ < 1) return fail(LTL_ERR_ARG, "batched launch does not fit on a compute unit");
             pl.grid = std::max(1, std::min(occ * device_cus(), b.nitems));
             int32_t rc = upload(h, b.stream, &pl.dinst);
@@ -682,7 +685,7 @@ int32_t batch_launch(ltl_batch &b, int T, int from, BatchLaunch *l) {
         l->dp.items = b.ditems;
         l->dp.nitems = b.nitems;
     } else {
-        l->func = cat_batch_func(elem_of(b.method));
+        l->func = cat_batch_func(elem_of(b.method, 16));
         l->block = dim3((unsigned)(64 * b.tuning.waves), 1, 1);
         l->bp.inst = (const BatchInst *)pl->dinst + from * b.count;
         l->bp.items = b.ditems;
@@ -896,7 +899,7 @@ int32_t ltl_create(ltl_sim_t **out, int32_t H, int32_t W, const ltl_rule_t *rule
     if ((e = hipMalloc(&s->dflag, sizeof(uint32_t))) != hipSuccess) { s->dflag = nullptr; return bail(hip_fail(e, "hipMalloc")); }
     if ((e = hipMalloc(&s->dconst, kConstBytes)) != hipSuccess) { s->dconst = nullptr; return bail(hip_fail(e, "hipMalloc")); }
     {
-        std::vector<uint8_t> hc = host_constants(elem_of(method), rule->R);
+        std::vector<uint8_t> hc = host_constants(elem_of(method, rule->R), rule->R);
         if ((e = hipMemcpyAsync(s->dconst, hc.data(), kConstBytes, hipMemcpyHostToDevice, stream)) != hipSuccess)
             return bail(hip_fail(e, "hipMemcpyAsync"));
         if ((e = hipStreamSynchronize(stream)) != hipSuccess) return bail(hip_fail(e, "hipStreamSynchronize"));
@@ -946,7 +949,7 @@ int32_t ltl_get_tuning(ltl_sim_t *sim, ltl_tuning_t *tuning) {
 
 static bool s_fits(const ltl_sim &s, const ltl_tuning_t &t) {
     return s.method != LTL_DIRECT &&
-           !cat_shape_fits(elem_of(s.method), s.rule.R, t.steps_per_launch, t.tile_rows, t.tile_cols, t.waves);
+           !cat_shape_fits(elem_of(s.method, s.rule.R), s.rule.R, t.steps_per_launch, t.tile_rows, t.tile_cols, t.waves);
 }
 
 int32_t ltl_set_tuning(ltl_sim_t *sim, const ltl_tuning_t *tuning) {
@@ -1088,6 +1091,8 @@ int32_t ltl_batch_create(ltl_batch_t **out, int32_t count, const int32_t *H, con
     if (rc != LTL_OK) return rc;
     for (int i = 0; i < count; ++i) {
         if ((rc = validate_rule(rules + i, method)) != LTL_OK) return fail(rc, "instance " + std::to_string(i) + ": " + g_err);
+        if (method != LTL_DIRECT && rules[i].R > 16)
+            return fail(LTL_ERR_UNSUPPORTED, "instance " + std::to_string(i) + ": batched CAT covers radii 1..16");
         if (!init[i]) return fail(LTL_ERR_ARG, "instance " + std::to_string(i) + ": NULL initial grid");
         if (init_pitch[i] < (size_t)W[i]) return fail(LTL_ERR_ARG, "instance " + std::to_string(i) + ": init_pitch < W");
         if (grid_too_large(H[i], W[i]))
@@ -1129,7 +1134,7 @@ int32_t ltl_batch_create(ltl_batch_t **out, int32_t count, const int32_t *H, con
         std::vector<uint8_t> hc(cbytes, 0);
         if (method != LTL_DIRECT)
             for (int r = 1; r <= kMaxR; ++r)
-                band_table(elem_of(method), r, reinterpret_cast<int32_t *>(hc.data() + (r - 1) * kBandBytes));
+                band_table(elem_of(method, 16), r, reinterpret_cast<int32_t *>(hc.data() + (r - 1) * kBandBytes));
         if ((e = hipMemcpyAsync(b->dconst, hc.data(), cbytes, hipMemcpyHostToDevice, stream)) != hipSuccess)
             return bail(hip_fail(e, "hipMemcpyAsync"));
         if ((e = hipStreamSynchronize(stream)) != hipSuccess) return bail(hip_fail(e, "hipStreamSynchronize"));

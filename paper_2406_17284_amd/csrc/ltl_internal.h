@@ -11,8 +11,11 @@ namespace ltl {
 //  EPI_DECAY C >= 3 states: per-cell transition with decay
 enum Epi { EPI_BYTE = 0, EPI_HALF = 1, EPI_DECAY = 2 };
 
-// Element type of the band-product operands.
-enum Elem { ELEM_I8 = 0, ELEM_F16 = 1, ELEM_F8 = 2 };
+// Element type of the band-product operands. ELEM_I8W is int8 for radii 17..32: every
+// 16-column half needs 16 + 2r <= 80 columns (a K = 64 and a K = 32 product) and every
+// output block the H blocks two above to two below it (a 4-block and a 2-block window).
+enum Elem { ELEM_I8 = 0, ELEM_F16 = 1, ELEM_F8 = 2, ELEM_I8W = 3 };
+inline bool elem_is_i8(int elem) { return elem == ELEM_I8 || elem == ELEM_I8W; }
 
 // Rule constants prepared on the host (thresholds on the box count n that includes
 // the centre: for an alive centre with M = 0 the survival range is shifted by one).
@@ -61,6 +64,11 @@ struct CatParams {
 //  fp8  : 0..3  MFMA #1 (half h, chunk c) = op 2h + c, chunk c covers window columns 32c..32c+31
 //         4..7  MFMA #2 on 2-block windows: (m-1, m), (m+1, m+2), (m-2, m-1), (m, m+1)
 //  fp16 : 0..3  MFMA #1 as fp8; 4, 5 MFMA #2 on the 2-block windows (m-1, m), (m+1, m+2)
+//  int8 wide (r 17..32): 0, 2  MFMA #1 halves 0/1, K = 64 chunk starting 32 columns left of
+//               the strip (K = 16 g + 4 d + e); 1, 3  the K = 32 chunk 32 columns right of the
+//               strip start (8 bytes, K = 8 g + j)
+//         4, 5  MFMA #2 for an even block offset: 4-block window m-2..m+1, pair m+2, m+3
+//         6, 7  odd offset: 4-block window m-3..m, pair m+1, m+2
 // MFMA #2 rows: block at distance delta from the output block, row 4 g + e of it, weight 1 iff
 // |16 delta + 4 g + e - n| <= r. int8 and fp8 tables hold 0/1 bytes (fp8 is encoded on the
 // device with the hardware's 1.0); fp16 holds 0x3C00 halves.
@@ -79,7 +87,24 @@ inline void band_table(int elem, int r, int32_t *out) {
         auto put_half = [&](int op, int j, bool on) {
             if (on) out[(op * 64 + lane) * 4 + j / 2] |= 0x3C00 << (16 * (j & 1));
         };
-        if (elem == ELEM_I8) {
+        if (elem == ELEM_I8W) {
+            for (int h = 0; h < 2; ++h) {
+                for (int d = 0; d < 4; ++d)
+                    for (int e = 0; e < 4; ++e)
+                        put_byte(2 * h, d, e, band_hit(16 * g + 4 * d + e - 32 - 16 * h - n, r));
+                for (int j = 0; j < 8; ++j)
+                    put_byte(2 * h + 1, j / 4, j % 4, band_hit(32 + 8 * g + j - 16 * h - n, r));
+            }
+            for (int d = 0; d < 4; ++d)
+                for (int e = 0; e < 4; ++e) {
+                    put_byte(4, d, e, band_hit(16 * (d - 2) + 4 * g + e - n, r));
+                    put_byte(6, d, e, band_hit(16 * (d - 3) + 4 * g + e - n, r));
+                }
+            for (int j = 0; j < 8; ++j) {
+                put_byte(5, j / 4, j % 4, band_hit(16 * (2 + j / 4) + 4 * g + (j % 4) - n, r));
+                put_byte(7, j / 4, j % 4, band_hit(16 * (1 + j / 4) + 4 * g + (j % 4) - n, r));
+            }
+        } else if (elem == ELEM_I8) {
             for (int d = 0; d < 4; ++d)
                 for (int e = 0; e < 4; ++e) {
                     const int k = 16 * g + 4 * d + e;
@@ -127,14 +152,20 @@ struct DirectParams {
 // Per-kernel geometry helpers shared by the host planner.
 inline int roundup(int x, int m) { return (x + m - 1) / m * m; }
 
-inline int cat_margin(int r, int T) { return roundup(r * (T - 1), 16) + 16; }
+// LDS margin around the output tile: the growth of the T-step dependency cone plus the H rows
+// and columns one step reads beyond its output (one 16-row block / 16 columns; int8 wide:
+// 32 columns and three 16-row blocks below, two above).
+inline int cat_margin(int elem, int r, int T) { return roundup(r * (T - 1), 16) + (elem == ELEM_I8W ? 48 : 16); }
 
 // Longest run of 16-row output blocks one wave handles per step, per element type (bounded by
 // the 16-register tuple that holds an item's H blocks).
 #define CAT_MAXC_I8 14
 #define CAT_MAXC_F8 14
 #define CAT_MAXC_F16 5
-inline int cat_maxc(int elem) { return elem == ELEM_F16 ? CAT_MAXC_F16 : elem == ELEM_F8 ? CAT_MAXC_F8 : CAT_MAXC_I8; }
+#define CAT_MAXC_I8W 11
+inline int cat_maxc(int elem) {
+    return elem == ELEM_F16 ? CAT_MAXC_F16 : elem == ELEM_F8 ? CAT_MAXC_F8 : elem == ELEM_I8W ? CAT_MAXC_I8W : CAT_MAXC_I8;
+}
 inline int cat_cell_bytes(int elem) { return elem == ELEM_F16 ? 2 : 1; }
 
 // Whether a launch shape can run: in every step of a T-step launch the strips x segments

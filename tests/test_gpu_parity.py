@@ -109,8 +109,12 @@ def test_shapes(ltl, shape, method):
 
 def shape_feasible(r, T, TH, TW, waves=8, maxc=14, cell=1, lds_max=160 * 1024):
     """Whether the CAT kernel can run this launch shape: the LDS tiles fit and in every step the
-    32-column strips times the row segments (at most `maxc` 16-row blocks) fit the waves."""
-    margin = -(-r * (T - 1) // 16) * 16 + 16
+    32-column strips times the row segments (at most `maxc` 16-row blocks) fit the waves.
+    int8 above r = 16 reads two more H blocks per segment (11 output blocks, margin + 32)."""
+    wide = r > 16 and cell == 1 and maxc == 14
+    if wide:
+        maxc = 11
+    margin = -(-r * (T - 1) // 16) * 16 + (48 if wide else 16)
     rows, cols = TH + 2 * margin, TW + 2 * margin
     lds = -(-rows * (cols + 16) // 1024) * 1024
     if cell == 2:   # fp16: a second tile holds the alive map, two bytes per cell
@@ -282,3 +286,52 @@ def test_periodic_glider_wraps_on_gpu(ltl):
         sim.step(4 * 96)          # lcm(32, 48) = 96 periods of (1, 1)
         assert np.array_equal(sim.read().cpu().numpy(), g0), method
         sim.close()
+
+
+# ------------------------------------------------------------------ radius 17..32 (int8 wide)
+WIDE_RULES = [inputs.sweep_rule(17), inputs.Rule(20, 5, 1, 300, 700, 320, 500), inputs.Rule(24, 0, 0, 600, 1100, 650, 900),
+              inputs.Rule(31, 0, 1, 990, 1800, 1070, 1360), inputs.Rule(32, 0, 1, 1056, 1901, 1140, 1436)]
+
+
+@pytest.mark.parametrize("method", ["cat_i8", "direct"])
+@pytest.mark.parametrize("rule", WIDE_RULES, ids=lambda r: r.text())
+def test_wide_radius_every_step(ltl, method, rule):
+    g0 = (inputs.state_grid(83, 151, rule.C, seed=rule.R) if rule.C >= 3
+          else inputs.bernoulli_grid(83, 151, 0.5, seed=rule.R))
+    run_and_compare_each_step(ltl, g0, rule, method, 4)
+
+
+@pytest.mark.parametrize("T", [1, 2, 3])
+@pytest.mark.parametrize("r", [17, 24, 32])
+@pytest.mark.parametrize("tile", [(64, 64), (128, 96), (48, 160)], ids=lambda t: f"{t[0]}x{t[1]}")
+def test_wide_radius_launch_shapes(ltl, T, r, tile):
+    rule = inputs.sweep_rule(r)
+    g0 = inputs.bernoulli_grid(230, 301, 0.5, seed=500 + r)
+    tuning = dict(steps_per_launch=T, tile_rows=tile[0], tile_cols=tile[1], waves=0)
+    if not shape_feasible(r, T, tile[0], tile[1]):
+        with pytest.raises(ltl.LtlError) as e:
+            run_and_compare(ltl, g0, rule, "cat_i8", 5, tuning=tuning)
+        assert e.value.code == ltl.LTL_ERR_ARG
+        return
+    run_and_compare(ltl, g0, rule, "cat_i8", 5, tuning=tuning)
+
+
+def test_wide_radius_periodic(ltl):
+    rule = inputs.sweep_rule(24)
+    run_periodic(ltl, inputs.bernoulli_grid(64, 80, 0.5, seed=24), rule, "cat_i8", 3)
+    run_periodic(ltl, inputs.bernoulli_grid(150, 208, 0.5, seed=25), rule, "cat_i8", 5,
+                 tuning=dict(steps_per_launch=2, tile_rows=64, tile_cols=64), every_step=False)
+
+
+def test_wide_radius_refusals(ltl):
+    g = gpu_grid(np.zeros((8, 8), dtype=np.uint8))
+    for method, code in (("cat_f16", ltl.LTL_ERR_UNSUPPORTED), ("cat_f8", ltl.LTL_ERR_INEXACT)):
+        with pytest.raises(ltl.LtlError) as e:
+            ltl.Simulation(g, inputs.sweep_rule(17), method)
+        assert e.value.code == code
+    with pytest.raises(ltl.LtlError) as e:
+        ltl.Simulation(g, inputs.Rule(33, 0, 1, 1, 2, 1, 2), "cat_i8")
+    assert e.value.code == ltl.LTL_ERR_RULE
+    with pytest.raises(ltl.LtlError) as e:
+        ltl.Batch([g, g], [inputs.LIFE, inputs.sweep_rule(17)], "cat_i8")
+    assert e.value.code == ltl.LTL_ERR_UNSUPPORTED

@@ -165,7 +165,7 @@ def test_bruteforce_decay_states():
         assert np.array_equal(nxt, exp)
 
 
-@pytest.mark.parametrize("r", [1, 2, 5, 16])
+@pytest.mark.parametrize("r", [1, 2, 5, 16, 24, 32])
 def test_count_single_cell_is_a_box(r):
     H, W = 70, 53
     for (i, j) in [(35, 26), (0, 0), (3, W - 2), (H - 1, 10)]:
@@ -177,7 +177,7 @@ def test_count_single_cell_is_a_box(r):
         assert np.array_equal(oracle.np_count(g, r), exp)
 
 
-@pytest.mark.parametrize("r", [1, 3, 7, 16])
+@pytest.mark.parametrize("r", [1, 3, 7, 16, 17, 32])
 @pytest.mark.parametrize("shape", [(1, 1), (5, 40), (37, 29), (64, 64)])
 def test_count_all_alive_closed_form(r, shape):
     H, W = shape
