@@ -72,6 +72,17 @@ def timed_runs(sim, n_per_run, runs, torch):
     return ev0.elapsed_time(ev1) / 1e3, wall
 
 
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def bench_batch(args, ltl, inputs, torch):
     """The batched workload: 512 automata advanced together, 32 steps per bench step."""
     insts = inputs.batch_instances()
@@ -121,6 +132,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--sweep", action="store_true", help="also time the radius sweep r=1..16 on 16384^2")
     ap.add_argument("--sweep-side", type=int, default=16384)
+    ap.add_argument("--sweep-rmax", type=int, default=16, help="largest radius of the sweep (int8 and direct reach 32)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the 512-instance batched workload")
     ap.add_argument("--batch-tuning", type=str, default=BATCH_TUNING, help="T,tile_rows,tile_cols,waves of the batch")
@@ -228,6 +240,15 @@ def main():
             "avg_launch_us": avg_launch_s * 1e6,
             "launches_per_bench_step": launches_per_run,
         },
+        "roofline_hbm": {
+            "bound": "hbm",
+            "achieved": 2 * cells / avg_launch_s / 1e9,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": 2 * cells / avg_launch_s / 1e9 / HBM_PEAK_GBS,
+            "bytes_per_launch": 2 * cells,
+            "note": "algorithmic bytes: one read and one write of the grid per launch",
+        },
         "parity": parity,
     }
 
@@ -235,12 +256,12 @@ def main():
         sweep = {}
         side = args.sweep_side
         gs = inputs.bernoulli_grid_torch(side, side, 0.5, 3, device="cuda")
-        for r in range(1, 17):
+        for r in range(1, args.sweep_rmax + 1):
             rule = inputs.sweep_rule(r)
             row = {}
             for method in ("cat_i8", "cat_f16", "cat_f8", "direct"):
-                if method == "cat_f8" and r > 7:
-                    continue   # fp8-e4m3 counts are exact only for 2r+1 <= 16
+                if (method == "cat_f8" and r > 7) or (method == "cat_f16" and r > 16):
+                    continue   # fp8-e4m3 counts are exact only for 2r+1 <= 16; fp16 covers r <= 16
                 s = ltl.Simulation(gs, rule, method)
                 if method != "direct":
                     s.autotune(probe_steps=10)
@@ -249,7 +270,7 @@ def main():
                 row[method] = side * side * 50 / secs_r
                 s.close()
             sweep[str(r)] = row
-        out["sweep"] = {"workload": f"{side}x{side}, r=1..16 sweep rules, Bernoulli(0.5) seed 3, 50 steps",
+        out["sweep"] = {"workload": f"{side}x{side}, r=1..{args.sweep_rmax} sweep rules, Bernoulli(0.5) seed 3, 50 steps",
                         "cell_updates_per_s": sweep}
 
     # ---- the same workload on a torus (the paper's experimental boundary condition)
@@ -285,8 +306,16 @@ def main():
         sample = f"bosco4096 grid, steps 2..{n_cpu + 1} of 100 ({n_cpu} steps, {t1 + tc:.1f} s total)"
         if n_cpu + 1 == w.steps:
             parity["cat_vs_oracle_equal"] = bool(np.array_equal(res, cat_final))
+        # one thread, one step (the single-thread figure of the same oracle)
+        oracle.set_threads(1)
+        t0 = time.perf_counter()
+        oracle.run(one, w.rule, 1)
+        t_single = time.perf_counter() - t0
+        oracle.set_threads(threads)
         out["cpu_baseline"] = {"value": cells * n_cpu / tc, "unit": "cell-updates/s", "cores": threads,
-                               "kind": "oracle", "sample": sample}
+                               "kind": "oracle", "sample": sample,
+                               "single_thread_value": cells / t_single,
+                               "cpu_model": cpu_model()}
     print(json.dumps(out), flush=True)
 
 
