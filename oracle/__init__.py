@@ -60,6 +60,12 @@ def _load() -> ctypes.CDLL:
         lib.oracle_step_b.restype = I
         lib.oracle_run_b.argtypes = [P, I64, I64, I, I, I, I, I, I, I, I, I]
         lib.oracle_run_b.restype = I
+        lib.oracle_count_cross.argtypes = [P, I64, I64, I, I, P]
+        lib.oracle_count_cross.restype = None
+        lib.oracle_step_nb.argtypes = [P, P, I64, I64, I, I, I, I, I, I, I, I, I]
+        lib.oracle_step_nb.restype = I
+        lib.oracle_run_nb.argtypes = [P, I64, I64, I, I, I, I, I, I, I, I, I, I]
+        lib.oracle_run_nb.restype = I
         lib.oracle_step.argtypes = [P, P, I64, I64, I, I, I, I, I, I, I]
         lib.oracle_step.restype = I
         lib.oracle_run.argtypes = [P, I64, I64, I, I, I, I, I, I, I, I]
@@ -71,8 +77,16 @@ def _load() -> ctypes.CDLL:
 
 
 def _rule_args(rule):
-    R, C, M, S1, S2, B1, B2 = rule.as_tuple() if hasattr(rule, "as_tuple") else rule
+    R, C, M, S1, S2, B1, B2 = rule.as_tuple() if hasattr(rule, "as_tuple") else rule[:7]
     return int(R), int(C), int(M), int(S1), int(S2), int(B1), int(B2)
+
+
+def _is_cross(rule) -> bool:
+    """Rule code N_N: the paper's simplified Von Neumann neighbourhood (the cross of Eq. 4)."""
+    n = getattr(rule, "N", None)
+    if n is None and not hasattr(rule, "as_tuple") and len(rule) > 7:
+        n = rule[7]
+    return n in ("N", ord("N"))
 
 
 def set_threads(n: int = 0) -> int:
@@ -80,12 +94,15 @@ def set_threads(n: int = 0) -> int:
     return _load().oracle_set_threads(int(n))
 
 
-def count(grid: np.ndarray, r: int, periodic: bool = False) -> np.ndarray:
-    """Box count of alive (== 1) cells of radius r, centre included; dead outside, or
-    on a torus when ``periodic``."""
+def count(grid: np.ndarray, r: int, periodic: bool = False, cross: bool = False) -> np.ndarray:
+    """Box count (or, with ``cross``, the count over the plus sign of arm r) of alive
+    (== 1) cells, centre included once; dead outside, or on a torus when ``periodic``."""
     g = np.ascontiguousarray(grid, dtype=np.uint8)
     H, W = g.shape
     out = np.empty((H, W), dtype=np.int32)
+    if cross:
+        _load().oracle_count_cross(g.ctypes.data, H, W, int(r), int(bool(periodic)), out.ctypes.data)
+        return out
     fn = _load().oracle_count_periodic if periodic else _load().oracle_count
     fn(g.ctypes.data, H, W, int(r), out.ctypes.data)
     return out
@@ -94,8 +111,8 @@ def count(grid: np.ndarray, r: int, periodic: bool = False) -> np.ndarray:
 def step(grid: np.ndarray, rule, periodic: bool = False) -> np.ndarray:
     g = np.ascontiguousarray(grid, dtype=np.uint8)
     out = np.empty_like(g)
-    rc = _load().oracle_step_b(g.ctypes.data, out.ctypes.data, g.shape[0], g.shape[1], *_rule_args(rule),
-                               int(bool(periodic)))
+    rc = _load().oracle_step_nb(g.ctypes.data, out.ctypes.data, g.shape[0], g.shape[1], *_rule_args(rule),
+                                int(bool(periodic)), int(_is_cross(rule)))
     if rc != 0:
         raise RuntimeError("oracle_step failed")
     return out
@@ -103,19 +120,32 @@ def step(grid: np.ndarray, rule, periodic: bool = False) -> np.ndarray:
 
 def run(grid: np.ndarray, rule, steps: int, periodic: bool = False) -> np.ndarray:
     g = np.array(grid, dtype=np.uint8, order="C", copy=True)
-    rc = _load().oracle_run_b(g.ctypes.data, g.shape[0], g.shape[1], *_rule_args(rule), int(steps),
-                              int(bool(periodic)))
+    rc = _load().oracle_run_nb(g.ctypes.data, g.shape[0], g.shape[1], *_rule_args(rule), int(steps),
+                               int(bool(periodic)), int(_is_cross(rule)))
     if rc != 0:
         raise RuntimeError("oracle_run failed")
     return g
 
 
 # --------------------------------------------------------------- NumPy version
-def np_count(grid: np.ndarray, r: int, periodic: bool = False) -> np.ndarray:
-    """Same box count as :func:`count`, as a sum of (2r+1)^2 shifted windows of a
-    zero-padded alive map, or of (2r+1)^2 cyclic shifts (``np.roll``) on a torus."""
+def np_count(grid: np.ndarray, r: int, periodic: bool = False, cross: bool = False) -> np.ndarray:
+    """Same count as :func:`count`, as a sum of shifted windows of a zero-padded alive map,
+    or of cyclic shifts (``np.roll``) on a torus: (2r+1)^2 offsets for the box, the 4r+1
+    offsets of the plus sign for the cross."""
     a = (np.asarray(grid) == 1).astype(np.int32)
     H, W = a.shape
+    if cross:
+        offs = [(0, d) for d in range(-r, r + 1)] + [(d, 0) for d in range(-r, r + 1) if d != 0]
+        out = np.zeros((H, W), dtype=np.int32)
+        if periodic:
+            for di, dj in offs:
+                out += np.roll(a, (-di, -dj), axis=(0, 1))
+            return out
+        p = np.zeros((H + 2 * r, W + 2 * r), dtype=np.int32)
+        p[r:r + H, r:r + W] = a
+        for di, dj in offs:
+            out += p[r + di:r + di + H, r + dj:r + dj + W]
+        return out
     if periodic:
         out = np.zeros((H, W), dtype=np.int32)
         for di in range(-r, r + 1):
@@ -135,7 +165,7 @@ def np_step(grid: np.ndarray, rule, periodic: bool = False) -> np.ndarray:
     R, C, M, S1, S2, B1, B2 = _rule_args(rule)
     s = np.asarray(grid, dtype=np.int32)
     states = C if C >= 3 else 2
-    n = np_count(s, R, periodic)
+    n = np_count(s, R, periodic, _is_cross(rule))
     c = n - ((s == 1) & (M == 0)).astype(np.int32)
     born = (B1 <= c) & (c <= B2)
     keep = (S1 <= c) & (c <= S2)

@@ -18,6 +18,12 @@
  * torus smaller than the box, one cell can be reached by several offsets and is then
  * counted once per offset (the sum is the cyclic convolution with the box).
  *
+ * Cross neighbourhood (rule code N_N, the paper's "simplified Von Neumann" of Eq. 4): the
+ * count sums the 2r + 1 cells of the cell's row and the 2r cells above and below it in its
+ * column (a plus sign of arm r, 4r + 1 cells, the centre once). Eq. 4 writes the same sum
+ * as Pi x Lambda + H, which holds the centre twice; the rule's M then decides whether the
+ * centre is counted, exactly as for Moore.
+ *
  * Readings taken where the paper is silent (each is listed in the design notes):
  *  - only state 1 is alive; with M = 0 the centre's own alive bit is removed once
  *    (the band of Eq. 2-3 holds the diagonal once, so the box counts the centre once);
@@ -88,6 +94,34 @@ void oracle_count_periodic(const uint8_t *s, int64_t H, int64_t W, int r, int32_
     }
 }
 
+/* Cross count of radius r (centre once), dead outside the grid or on a torus. */
+void oracle_count_cross(const uint8_t *s, int64_t H, int64_t W, int r, int periodic, int32_t *cnt)
+{
+    int64_t i;
+#pragma omp parallel for schedule(static)
+    for (i = 0; i < H; ++i) {
+        for (int64_t j = 0; j < W; ++j) {
+            int32_t c = 0;
+            for (int d = -r; d <= r; ++d) {
+                int64_t jj = j + d, ii = i + d;
+                if (periodic) {
+                    jj = (jj % W + W) % W;
+                    ii = (ii % H + H) % H;
+                    c += (s[i * W + jj] == 1);
+                    if (d != 0)
+                        c += (s[ii * W + j] == 1);
+                } else {
+                    if (jj >= 0 && jj < W)
+                        c += (s[i * W + jj] == 1);
+                    if (d != 0 && ii >= 0 && ii < H)
+                        c += (s[ii * W + j] == 1);
+                }
+            }
+            cnt[i * W + j] = c;
+        }
+    }
+}
+
 /* The transition of one cell given its state and its box count n (centre included). */
 static uint8_t transition(uint8_t s, int32_t n, int C, int M, int S1, int S2, int B1, int B2)
 {
@@ -107,8 +141,8 @@ static uint8_t transition(uint8_t s, int32_t n, int C, int M, int S1, int S2, in
 
 /* One synchronous step: out = f(s). out must not alias s. periodic: 0 dead ghost halo,
  * 1 torus. Returns 0 or -1 on bad args. */
-int oracle_step_b(const uint8_t *s, uint8_t *out, int64_t H, int64_t W,
-                  int R, int C, int M, int S1, int S2, int B1, int B2, int periodic)
+int oracle_step_nb(const uint8_t *s, uint8_t *out, int64_t H, int64_t W,
+                   int R, int C, int M, int S1, int S2, int B1, int B2, int periodic, int cross)
 {
     if (!s || !out || H < 0 || W < 0 || R < 0)
         return -1;
@@ -117,7 +151,9 @@ int oracle_step_b(const uint8_t *s, uint8_t *out, int64_t H, int64_t W,
     int32_t *cnt = (int32_t *)malloc((size_t)H * (size_t)W * sizeof(int32_t));
     if (!cnt)
         return -1;
-    if (periodic)
+    if (cross)
+        oracle_count_cross(s, H, W, R, periodic, cnt);
+    else if (periodic)
         oracle_count_periodic(s, H, W, R, cnt);
     else
         oracle_count(s, H, W, R, cnt);
@@ -129,6 +165,12 @@ int oracle_step_b(const uint8_t *s, uint8_t *out, int64_t H, int64_t W,
     return 0;
 }
 
+int oracle_step_b(const uint8_t *s, uint8_t *out, int64_t H, int64_t W,
+                  int R, int C, int M, int S1, int S2, int B1, int B2, int periodic)
+{
+    return oracle_step_nb(s, out, H, W, R, C, M, S1, S2, B1, B2, periodic, 0);
+}
+
 int oracle_step(const uint8_t *s, uint8_t *out, int64_t H, int64_t W,
                 int R, int C, int M, int S1, int S2, int B1, int B2)
 {
@@ -136,8 +178,8 @@ int oracle_step(const uint8_t *s, uint8_t *out, int64_t H, int64_t W,
 }
 
 /* steps synchronous steps applied to grid in place (ping-pong with a scratch copy). */
-int oracle_run_b(uint8_t *grid, int64_t H, int64_t W, int R, int C, int M,
-                 int S1, int S2, int B1, int B2, int steps, int periodic)
+int oracle_run_nb(uint8_t *grid, int64_t H, int64_t W, int R, int C, int M,
+                  int S1, int S2, int B1, int B2, int steps, int periodic, int cross)
 {
     if (!grid || steps < 0)
         return -1;
@@ -148,7 +190,7 @@ int oracle_run_b(uint8_t *grid, int64_t H, int64_t W, int R, int C, int M,
         return -1;
     uint8_t *a = grid, *b = tmp;
     for (int t = 0; t < steps; ++t) {
-        if (oracle_step_b(a, b, H, W, R, C, M, S1, S2, B1, B2, periodic) != 0) {
+        if (oracle_step_nb(a, b, H, W, R, C, M, S1, S2, B1, B2, periodic, cross) != 0) {
             free(tmp);
             return -1;
         }
@@ -158,6 +200,12 @@ int oracle_run_b(uint8_t *grid, int64_t H, int64_t W, int R, int C, int M,
         memcpy(grid, a, (size_t)H * (size_t)W);
     free(tmp);
     return 0;
+}
+
+int oracle_run_b(uint8_t *grid, int64_t H, int64_t W, int R, int C, int M,
+                 int S1, int S2, int B1, int B2, int steps, int periodic)
+{
+    return oracle_run_nb(grid, H, W, R, C, M, S1, S2, B1, B2, steps, periodic, 0);
 }
 
 int oracle_run(uint8_t *grid, int64_t H, int64_t W, int R, int C, int M,

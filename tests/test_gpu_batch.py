@@ -216,3 +216,19 @@ def test_batch_512_instances(ltl, method):
         sim.step(steps)
         assert np.array_equal(got[i], sim.read().cpu().numpy()), f"instance {i} vs single grid"
         sim.close()
+
+
+def test_batch_graph_replays_match_eager(ltl):
+    grids, rules = small_batch(6, max_r=9)
+    graph = ltl.Batch([gpu_grid(g) for g in grids], rules, "cat_i8", tuning=dict(steps_per_launch=2, use_graph=1))
+    eager = ltl.Batch([gpu_grid(g) for g in grids], rules, "cat_i8", tuning=dict(steps_per_launch=2, use_graph=0))
+    for k in range(3):
+        graph.step(6)
+        eager.step(6)
+        torch.cuda.synchronize()
+        for i in range(len(grids)):
+            assert torch.equal(graph.read(i), eager.read(i)), f"replay {k} instance {i}"
+        _ = graph.read(0).sum().item()
+    check_batch(graph, [oracle.run(g, r, 18) for g, r in zip(grids, rules)], "graph replays")
+    graph.close()
+    eager.close()

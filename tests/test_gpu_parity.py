@@ -335,3 +335,26 @@ def test_wide_radius_refusals(ltl):
     with pytest.raises(ltl.LtlError) as e:
         ltl.Batch([g, g], [inputs.LIFE, inputs.sweep_rule(17)], "cat_i8")
     assert e.value.code == ltl.LTL_ERR_UNSUPPORTED
+
+
+def test_graph_replays_match_eager(ltl):
+    """The cached hipGraph of an n-step call is replayed several times, with eager work (reads,
+    a single eager step, synchronizations) between the replays; every replay must equal the
+    eager launches of the same steps."""
+    rule = inputs.BOSCO_M1
+    g0 = inputs.bernoulli_grid(300, 420, 0.5, seed=61)
+    tun = dict(steps_per_launch=2, tile_rows=64, tile_cols=128)
+    graph = ltl.Simulation(gpu_grid(g0), rule, "cat_i8", tuning=dict(tun, use_graph=1))
+    eager = ltl.Simulation(gpu_grid(g0), rule, "cat_i8", tuning=dict(tun, use_graph=0))
+    for k in range(4):
+        graph.step(6)       # same n and parity each time: the same cached graph
+        eager.step(6)
+        torch.cuda.synchronize()
+        a, b = graph.read(), eager.read()
+        assert torch.equal(a, b), f"replay {k}"
+        graph.step(2)        # eager-sized calls between the replays (two launches: a second graph)
+        eager.step(2)
+        _ = graph.read().sum().item()
+    assert np.array_equal(graph.read().cpu().numpy(), oracle.run(g0, rule, 32))
+    graph.close()
+    eager.close()

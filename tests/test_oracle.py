@@ -454,3 +454,113 @@ def test_periodic_c_and_numpy_oracles_agree(seed):
     H, W = int(rng.integers(1, 40)), int(rng.integers(1, 40))
     g = rng.integers(0, max(C, 2), size=(H, W)).astype(np.uint8)
     assert np.array_equal(oracle.run(g, rule, 3, periodic=True), oracle.np_run(g, rule, 3, periodic=True))
+
+
+# ------------------------------------------------------------------ cross neighbourhood (N_N)
+def _cross(rule):
+    return inputs.Rule(*rule.as_tuple(), N="N")
+
+
+@pytest.mark.parametrize("periodic", [False, True])
+@pytest.mark.parametrize("r", [1, 3, 9, 16])
+def test_cross_count_single_cell_is_a_plus_sign(r, periodic):
+    H, W = 50, 64
+    for (ci, cj) in [(25, 30), (0, 0), (H - 1, 5)]:
+        g = np.zeros((H, W), dtype=np.uint8)
+        g[ci, cj] = 1
+        exp = np.zeros((H, W), dtype=np.int32)
+        for d in range(-r, r + 1):
+            for (i, j) in [(ci, cj + d), (ci + d, cj)]:
+                if periodic:
+                    exp[i % H, j % W] = 1
+                elif 0 <= i < H and 0 <= j < W:
+                    exp[i, j] = 1
+        assert np.array_equal(oracle.count(g, r, periodic=periodic, cross=True), exp)
+        assert np.array_equal(oracle.np_count(g, r, periodic=periodic, cross=True), exp)
+
+
+@pytest.mark.parametrize("r", [1, 4, 16])
+@pytest.mark.parametrize("shape", [(1, 1), (7, 40), (33, 29)])
+def test_cross_count_all_alive_closed_form(r, shape):
+    H, W = shape
+    g = np.ones((H, W), dtype=np.uint8)
+    i = np.arange(H)[:, None]
+    j = np.arange(W)[None, :]
+    exp = (np.minimum(j, r) + np.minimum(W - 1 - j, r) + 1) + (np.minimum(i, r) + np.minimum(H - 1 - i, r))
+    assert np.array_equal(oracle.count(g, r, cross=True), exp)
+
+
+@pytest.mark.parametrize("r", [1, 2, 5, 16])
+def test_cross_count_is_eq4_band_products(r):
+    """Eq. 4 on the zero-padded grid: Pi x Lambda + Lambda x Pi (= Pi x Lambda + H) holds the
+    centre twice; minus Lambda once it is the cross count."""
+    rng = np.random.default_rng(r)
+    n = 40
+    lam = (rng.random((n, n)) < 0.4).astype(np.int64)
+    npad = n + 2 * r
+    L = np.zeros((npad, npad), dtype=np.int64)
+    L[r:r + n, r:r + n] = lam
+    idx = np.arange(npad)
+    Pi = (np.abs(idx[:, None] - idx[None, :]) <= r).astype(np.int64)
+    Rvn = Pi @ L + L @ Pi
+    exp = (Rvn - L)[r:r + n, r:r + n]
+    assert np.array_equal(oracle.count(lam.astype(np.uint8), r, cross=True), exp)
+
+
+@pytest.mark.parametrize("r", [1, 2, 3])
+def test_cross_bruteforce_all_neighbourhoods(r):
+    """Every assignment of the 4r + 1 cross cells, each centred in its own (2r+1)^2 block (the
+    centre's cross stays inside its block), against the transition from its popcount."""
+    k = 4 * r + 1
+    offs = [(0, d) for d in range(-r, r + 1)] + [(d, 0) for d in range(-r, r + 1) if d != 0]
+    nb = 1 << k
+    side = 2 * r + 1
+    per_row = 64
+    rows = -(-nb // per_row)
+    g = np.zeros((rows * side, per_row * side), dtype=np.uint8)
+    centres = []
+    for p in range(nb):
+        bi, bj = divmod(p, per_row)
+        ci, cj = bi * side + r, bj * side + r
+        for b, (di, dj) in enumerate(offs):
+            if (p >> b) & 1:
+                g[ci + di, cj + dj] = 1
+        centres.append((ci, cj, p))
+    for rule in [inputs.Rule(r, 0, 1, 2, 2 * r + 1, r + 1, 2 * r), inputs.Rule(r, 0, 0, 1, 3, 2, 2 * r + 1),
+                 inputs.Rule(r, 4, 1, r, 3 * r, 2, 2 * r)]:
+        out = oracle.step(g, _cross(rule))
+        outn = oracle.np_step(g, _cross(rule))
+        for ci, cj, p in centres:
+            pop = bin(p).count("1")
+            s = int(g[ci, cj])
+            c = pop - (1 if (rule.M == 0 and s == 1) else 0)
+            if s == 0:
+                exp = 1 if rule.B1 <= c <= rule.B2 else 0
+            else:
+                exp = 1 if rule.S1 <= c <= rule.S2 else (2 if rule.C >= 3 else 0)
+            assert out[ci, cj] == exp and outn[ci, cj] == exp, (rule.text(), p)
+
+
+def test_cross_step_commutes_with_d4_symmetries():
+    rule = _cross(inputs.Rule(3, 0, 1, 3, 7, 4, 6))
+    rng = np.random.default_rng(11)
+    g = (rng.random((37, 37)) < 0.45).astype(np.uint8)
+    ref = oracle.step(g, rule)
+    for k in range(4):
+        assert np.array_equal(oracle.step(np.rot90(g, k).copy(), rule), np.rot90(ref, k))
+    assert np.array_equal(oracle.step(g.T.copy(), rule), ref.T)
+
+
+@pytest.mark.parametrize("periodic", [False, True])
+@pytest.mark.parametrize("seed", range(4))
+def test_cross_c_and_numpy_oracles_agree(seed, periodic):
+    rng = np.random.default_rng(200 + seed)
+    r = int(rng.integers(1, 17))
+    n = 4 * r + 1
+    C = int(rng.choice([0, 2, 5]))
+    s = sorted(int(x) for x in rng.integers(0, n + 1, size=2))
+    b = sorted(int(x) for x in rng.integers(0, n + 1, size=2))
+    rule = inputs.Rule(r, C, int(rng.integers(0, 2)), s[0], s[1], b[0], b[1], "N")
+    H, W = int(rng.integers(1, 60)), 16 * int(rng.integers(1, 5))
+    g = rng.integers(0, max(C, 2), size=(H, W)).astype(np.uint8)
+    assert np.array_equal(oracle.run(g, rule, 3, periodic=periodic), oracle.np_run(g, rule, 3, periodic=periodic))
