@@ -2,11 +2,12 @@
  * ltl.h -- C ABI of libltl: Larger-than-Life stepping on one MI355X (gfx950).
  *
  * The library advances cellular automata of the Larger-than-Life family,
- * R_r C_c M_m S_{s1..s2} B_{b1..b2} N_M (paper: "Chosen CA tests", rule notation),
- * on a uint8 grid with a dead ghost halo. The Moore neighbourhood count of every
- * cell is the band-matrix reduction of "Formulation of CAT" (Eq. 2-3: H = Lambda Pi,
- * R = Pi H, Pi the band of ones of half-width r), computed per grid tile on int8
- * MFMA with int32 accumulation (exact for r <= 16), followed in the same kernel by
+ * R_r C_c M_m S_{s1..s2} B_{b1..b2} N_n (paper: "Chosen CA tests", rule notation),
+ * on a uint8 grid with a dead ghost halo or on a torus. The Moore neighbourhood count
+ * of every cell is the band-matrix reduction of "Formulation of CAT" (Eq. 2-3:
+ * H = Lambda Pi, R = Pi H, Pi the band of ones of half-width r) and the cross count
+ * its simplified Von Neumann form (Eq. 4: Pi Lambda + H), computed per grid tile on
+ * int8 MFMA with int32 accumulation (exact), followed in the same kernel by
  * the birth / survival / decay transition (Algorithm 1, per-thread rule after the
  * reductions). The ping-pong update of "Pseudocode of CAT's Kernel" is kept: two
  * caller-owned buffers swap roles every step.
@@ -34,15 +35,22 @@ extern "C" {
 enum {
     LTL_OK = 0,
     LTL_ERR_ARG = -1,         /* null pointer, size < 1, pitch < width, bad tuning value */
-    LTL_ERR_RULE = -2,        /* R outside 1..16, C == 1 or > 255, M not 0/1, threshold < 0 or > (2R+1)^2 */
-    LTL_ERR_UNSUPPORTED = -3, /* neighbourhood other than Moore ('M') */
+    LTL_ERR_RULE = -2,        /* R outside 1..32, C == 1 or > 255, M not 0/1, threshold < 0 or > (2R+1)^2 */
+    LTL_ERR_UNSUPPORTED = -3, /* N not 'M'/'N'; a method/radius/neighbourhood combination not built
+                                 (fp16 above R = 16, cross on fp16/fp8 or above R = 16 for CAT,
+                                 batched CAT above R = 16 or with the cross); periodic W % 16 != 0 */
     LTL_ERR_INEXACT = -4,     /* FP8 method with 2R+1 > 16: counts would not be exact in e4m3 */
     LTL_ERR_SIZE = -5,        /* buffer smaller than ltl_buffer_bytes(), or grid over 2^31 - 1 bytes */
     LTL_ERR_HIP = -6,         /* HIP runtime error (message in ltl_last_error) */
     LTL_ERR_STATE = -7        /* an initial cell holds a state >= max(C, 2) */
 };
 
-/* An LTL rule (paper, "Chosen CA tests"). N is the character 'M' (77) for Moore.
+/* An LTL rule (paper, "Chosen CA tests"). N is the character 'M' (77) for the Moore box
+ * of (2R+1)^2 cells or 'N' (78) for the paper's simplified Von Neumann neighbourhood (Eq. 4):
+ * the cross of the cell's row and column, 4R+1 cells. The diamond-shaped Von Neumann
+ * neighbourhood is not offered (the paper's CAT does not support it either).
+ * Radii: int8 CAT and the direct stencil 1..32 (cross: CAT 1..16, direct 1..32), fp16 1..16,
+ * fp8 1..7.
  * C = 0 or 2: two states. C >= 3: states 2..C-1 are decay states (a surviving-range
  * miss sends an alive cell to 2, decay advances by one per step and wraps to 0;
  * decaying cells are neither alive nor born). M = 1 counts the centre cell itself.
@@ -53,10 +61,10 @@ typedef struct {
 
 /* How the neighbourhood count is computed; all give bit-identical grids. */
 typedef enum {
-    LTL_CAT_I8 = 0,  /* band products on int8 MFMA (v_mfma_i32_16x16x64_i8), int32 accumulate */
+    LTL_CAT_I8 = 0,  /* band products on int8 MFMA (v_mfma_i32_16x16x64_i8; R > 16 adds 16x16x32), int32 accumulate */
     LTL_CAT_F16 = 1, /* band products on fp16 MFMA, fp32 accumulate (exact: counts <= 1089 < 2^11) */
     LTL_CAT_F8 = 2,  /* band products on fp8-e4m3 MFMA, fp32 accumulate; only 2R+1 <= 16 */
-    LTL_DIRECT = 3   /* comparison method: LDS tile + direct (2R+1)^2 sum per cell */
+    LTL_DIRECT = 3   /* comparison method: LDS tile + direct sum over the neighbourhood per cell */
 } ltl_method_t;
 
 /* Launch shape. Zero fields mean "library default". The result never depends on it. */

@@ -145,6 +145,9 @@ __device__ __forceinline__ uint32_t alive_of(uint32_t s) {
 template <int ELEM> struct ElemT;
 template <> struct ElemT<ELEM_I8> { static constexpr int CELL = 1, MAXC = CAT_MAXC_I8, NOPS = 4; };
 template <> struct ElemT<ELEM_I8W> { static constexpr int CELL = 1, MAXC = CAT_MAXC_I8W, NOPS = 8; };
+template <> struct ElemT<ELEM_I8X> { static constexpr int CELL = 1, MAXC = CAT_MAXC_I8X, NOPS = 8; };
+// int8 element types (0/1 bytes, the state tile is the alive map for two-state rules)
+template <int ELEM> constexpr bool kIsI8 = (ELEM == ELEM_I8 || ELEM == ELEM_I8W || ELEM == ELEM_I8X);
 template <> struct ElemT<ELEM_F8> { static constexpr int CELL = 1, MAXC = CAT_MAXC_F8, NOPS = 8; };
 template <> struct ElemT<ELEM_F16> { static constexpr int CELL = 2, MAXC = CAT_MAXC_F16, NOPS = 6; };
 
@@ -233,7 +236,39 @@ __device__ __forceinline__ uint32_t pack_f16(float a, float b) {
 // the A chunks of the next pair are read from LDS before the MFMAs of this pair run.
 template <int ELEM>
 __device__ __forceinline__ void phase_a(const uint8_t *At, uint32_t a_off, uint32_t a_off2, uint32_t PA, int rb0,
-                                        int count, const Bands &bd, v16i &Ha, v16i &Hb) {
+                                        int count, const Bands &bd, v16i &Ha, v16i &Hb, v16i &La, v16i &Lb) {
+    if constexpr (ELEM == ELEM_I8X) {
+        // cross: per 16-row block and half, H (horizontal arm) and the alive map itself in the
+        // same register layout (identity band), both from the one A chunk
+        const int nh = count + 2;
+        const v4i zero = {0, 0, 0, 0};
+        v4i a[4];
+#define CAT_LDA(K) a[(K) & 3] = *reinterpret_cast<const v4i *>(At + (a_off + (uint32_t)(16 * (rb0 - 1 + (K))) * PA));
+#define CAT_HB(K)                                                                                  \
+        {                                                                                          \
+            Ha[(K)] = (int32_t)pack_bytes(__builtin_amdgcn_mfma_i32_16x16x64_i8(a[(K) & 3], bd.op[0], zero, 0, 0, 0)); \
+            Hb[(K)] = (int32_t)pack_bytes(__builtin_amdgcn_mfma_i32_16x16x64_i8(a[(K) & 3], bd.op[1], zero, 0, 0, 0)); \
+            La[(K)] = (int32_t)pack_bytes(__builtin_amdgcn_mfma_i32_16x16x64_i8(a[(K) & 3], bd.op[2], zero, 0, 0, 0)); \
+            Lb[(K)] = (int32_t)pack_bytes(__builtin_amdgcn_mfma_i32_16x16x64_i8(a[(K) & 3], bd.op[3], zero, 0, 0, 0)); \
+        }
+#define CAT_APAIR(P)                                                                               \
+        if (2 * (P) < nh) {                                                                        \
+            if (2 * (P) + 2 < nh) {                                                                \
+                CAT_LDA(2 * (P) + 2)                                                               \
+                if (2 * (P) + 3 < nh) CAT_LDA(2 * (P) + 3)                                         \
+            }                                                                                      \
+            CAT_HB(2 * (P))                                                                        \
+            if (2 * (P) + 1 < nh) CAT_HB(2 * (P) + 1)                                              \
+        }
+        CAT_LDA(0) CAT_LDA(1)
+        CAT_APAIR(0) CAT_APAIR(1) CAT_APAIR(2) CAT_APAIR(3)   // at most CAT_MAXC_I8X + 2 = 8 blocks
+#undef CAT_APAIR
+#undef CAT_HB
+#undef CAT_LDA
+        return;
+    }
+    (void)La;
+    (void)Lb;
     if constexpr (ELEM == ELEM_I8W) {
         // radius 17..32: H blocks rb0 - 2 .. rb0 + count + 2; per half a K = 64 product on the
         // chunk at a_off and a K = 32 product on the 8 bytes at a_off2, summed. The two products
@@ -375,8 +410,15 @@ __device__ __forceinline__ void phase_a(const uint8_t *At, uint32_t a_off, uint3
 
 // Vertical band product of output block M for one half (counts as int32 or biased fp32 bits).
 template <int ELEM, int M>
-__device__ __forceinline__ v4i vproduct(const v16i &H, const Bands &bd) {
-    if constexpr (ELEM == ELEM_I8W) {
+__device__ __forceinline__ v4i vproduct(const v16i &H, const v16i &L, const Bands &bd) {
+    if constexpr (ELEM == ELEM_I8X) {
+        // cross: H at the centre row (identity window) plus the vertical arm of the alive map
+        // (centre excluded), same window of blocks, same instruction, one accumulator
+        const v4i zero = {0, 0, 0, 0};
+        constexpr int W0 = (M & 1) ? M - 1 : M;
+        v4i c = __builtin_amdgcn_mfma_i32_16x16x64_i8(window4<W0>(H), (M & 1) ? bd.op[7] : bd.op[6], zero, 0, 0, 0);
+        return __builtin_amdgcn_mfma_i32_16x16x64_i8(window4<W0>(L), (M & 1) ? bd.op[5] : bd.op[4], c, 0, 0, 0);
+    } else if constexpr (ELEM == ELEM_I8W) {
         // tuple element k holds block rb0 - 2 + k; output block rb0 + M needs elements M .. M+4
         const v4i zero = {0, 0, 0, 0};
         if constexpr ((M & 1) == 0) {
@@ -420,7 +462,8 @@ struct LaneOff {
 template <int ELEM, int EPI, bool MASKED, bool LAST>
 __device__ __forceinline__ void phase_b(const CatParams &p, uint8_t *Qt, uint8_t *At, LaneOff lo, int rb0, int count,
                                         int gr0, uint32_t goff0, int gca, uint32_t cma, uint32_t cmb, const Bands &bd,
-                                        const Codec &cd, const v16i &Ha, const v16i &Hb) {
+                                        const Codec &cd, const v16i &Ha, const v16i &Hb, const v16i &La,
+                                        const v16i &Lb) {
     constexpr int CELL = ElemT<ELEM>::CELL;
     constexpr bool SEPARATE = (EPI == EPI_DECAY) || (ELEM == ELEM_F16);   // Q and A are distinct tiles
     const uint32_t PS = (uint32_t)p.PS, PA = (uint32_t)p.PA;
@@ -429,9 +472,9 @@ __device__ __forceinline__ void phase_b(const CatParams &p, uint8_t *Qt, uint8_t
     // counts and centre states of block M (slot M & 3)
 #define CAT_ISSUE(M)                                                                               \
     {                                                                                              \
-        ca[(M) & 3] = vproduct<ELEM, (M)>(Ha, bd);                                                 \
-        cb[(M) & 3] = vproduct<ELEM, (M)>(Hb, bd);                                                 \
-        if constexpr (EPI == EPI_DECAY || ELEM == ELEM_I8 || ELEM == ELEM_I8W) {                   \
+        ca[(M) & 3] = vproduct<ELEM, (M)>(Ha, La, bd);                                             \
+        cb[(M) & 3] = vproduct<ELEM, (M)>(Hb, Lb, bd);                                             \
+        if constexpr (EPI == EPI_DECAY || kIsI8<ELEM>) {                                           \
             const uint32_t qo = lo.q + (uint32_t)(16 * (rb0 + (M))) * PS;                          \
             sa[(M) & 3] = *reinterpret_cast<const uint32_t *>(Qt + qo);                            \
             sb[(M) & 3] = *reinterpret_cast<const uint32_t *>(Qt + qo + 16);                       \
@@ -470,7 +513,7 @@ __device__ __forceinline__ void phase_b(const CatParams &p, uint8_t *Qt, uint8_t
                 *reinterpret_cast<uint32_t *>(Qt + qo) = na;                                       \
                 *reinterpret_cast<uint32_t *>(Qt + qo + 16) = nb;                                  \
             }                                                                                      \
-            if constexpr (ELEM == ELEM_I8 || ELEM == ELEM_I8W) {                                   \
+            if constexpr (kIsI8<ELEM>) {                                                           \
                 *reinterpret_cast<uint32_t *>(At + ao) = ala;                                      \
                 *reinterpret_cast<uint32_t *>(At + ao + 16) = alb;                                 \
             } else if constexpr (ELEM == ELEM_F8) {                                                \
@@ -493,6 +536,10 @@ __device__ __forceinline__ void phase_b(const CatParams &p, uint8_t *Qt, uint8_t
     (void)CELL;
     (void)SEPARATE;
     if constexpr (ELEM == ELEM_F16) {
+        CAT_ISSUE(0) CAT_ISSUE(1)
+        CAT_BPAIR(0, 1) CAT_BPAIR(1, 1)
+        CAT_BPAIR(2, 0)
+    } else if constexpr (ELEM == ELEM_I8X) {   // at most CAT_MAXC_I8X = 6 blocks
         CAT_ISSUE(0) CAT_ISSUE(1)
         CAT_BPAIR(0, 1) CAT_BPAIR(1, 1)
         CAT_BPAIR(2, 0)
@@ -534,7 +581,8 @@ __device__ __forceinline__ void cat_steps(const CatParams &p, uint8_t *Qt, uint8
             count = max(0, mb_hi - mb_lo);
         }
         v16i Ha, Hb;
-        if constexpr (ELEM != ELEM_I8 && ELEM != ELEM_I8W) {
+        v16i La, Lb;   // cross only: the packed alive map
+        if constexpr (!kIsI8<ELEM>) {
             // slots no block fills may enter a window with zero weight; keep them finite
             Ha = (v16i)0;
             Hb = (v16i)0;
@@ -542,14 +590,14 @@ __device__ __forceinline__ void cat_steps(const CatParams &p, uint8_t *Qt, uint8
         // this lane's A chunk (row li of a block, from column j0 - 16 + 16 lg, or + 8 lg for the
         // K = 32 element types) and its first centre cell (row li, column j0 + 4 lg)
         const int chunk_col = (ELEM == ELEM_I8W) ? (L + j0 - 32 + 16 * lg)
-                              : (ELEM == ELEM_I8) ? (L + j0 - 16 + 16 * lg) : (L + j0 - 16 + 8 * lg);
+                              : kIsI8<ELEM> ? (L + j0 - 16 + 16 * lg) : (L + j0 - 16 + 8 * lg);
         const uint32_t a_off = (uint32_t)((L + li) * (int)PA + chunk_col * CELL);
         // int8 wide: the K = 32 chunk, columns j0 + 32 + 8 lg .. + 7
         const uint32_t a_off2 = (uint32_t)((L + li) * (int)PA + (L + j0 + 32 + 8 * lg) * CELL);
         LaneOff lo;
         lo.q = (uint32_t)((L + li) * (int)PS + (L + j0 + 4 * lg));
         lo.a = (uint32_t)((L + li) * (int)PA + (L + j0 + 4 * lg) * CELL);
-        if (count > 0) phase_a<ELEM>(At, a_off, a_off2, PA, rb0, count, bd, Ha, Hb);
+        if (count > 0) phase_a<ELEM>(At, a_off, a_off2, PA, rb0, count, bd, Ha, Hb, La, Lb);
         if (!last) __syncthreads();   // every read of the old states precedes any in-place write
         if (count > 0) {
             const int gca = gj0 + j0 + 4 * lg;
@@ -563,9 +611,11 @@ __device__ __forceinline__ void cat_steps(const CatParams &p, uint8_t *Qt, uint8
             const int gr0 = gi0 + 16 * rb0 + li;
             const uint32_t goff0 = (uint32_t)(gr0 * p.pitch + gca);
             if (last)
-                phase_b<ELEM, EPI, MASKED, true>(p, Qt, At, lo, rb0, count, gr0, goff0, gca, cma, cmb, bd, cd, Ha, Hb);
+                phase_b<ELEM, EPI, MASKED, true>(p, Qt, At, lo, rb0, count, gr0, goff0, gca, cma, cmb, bd, cd, Ha, Hb,
+                                                 La, Lb);
             else
-                phase_b<ELEM, EPI, MASKED, false>(p, Qt, At, lo, rb0, count, gr0, goff0, gca, cma, cmb, bd, cd, Ha, Hb);
+                phase_b<ELEM, EPI, MASKED, false>(p, Qt, At, lo, rb0, count, gr0, goff0, gca, cma, cmb, bd, cd, Ha, Hb,
+                                                  La, Lb);
         }
         if (!last) __syncthreads();   // new states complete before the next step reads them
     }
@@ -642,7 +692,7 @@ __device__ __forceinline__ void cat_tile(const CatParams &p, int tile, uint8_t *
     __syncthreads();
 
     // alive map from the loaded states (int8 without decay reads the states directly)
-    if constexpr (!((ELEM == ELEM_I8 || ELEM == ELEM_I8W) && EPI != EPI_DECAY)) {
+    if constexpr (!(kIsI8<ELEM> && EPI != EPI_DECAY)) {
         const int W2 = p.TW + 2 * p.L;          // window columns (the PS - W2 pad is never read)
         const int vpr = W2 >> 4;
         const int nvec = (p.TH + 2 * p.L) * vpr;
@@ -653,7 +703,7 @@ __device__ __forceinline__ void cat_tile(const CatParams &p, int tile, uint8_t *
             uint4 al = q;
             if constexpr (EPI == EPI_DECAY)
                 al = make_uint4(alive_of(q.x), alive_of(q.y), alive_of(q.z), alive_of(q.w));
-            if constexpr (ELEM == ELEM_I8 || ELEM == ELEM_I8W) {
+            if constexpr (kIsI8<ELEM>) {
                 *reinterpret_cast<uint4 *>(At + row * p.PA + col) = al;
             } else if constexpr (ELEM == ELEM_F8) {
                 *reinterpret_cast<uint4 *>(At + row * p.PA + col) =

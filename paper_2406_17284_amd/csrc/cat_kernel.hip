@@ -34,6 +34,8 @@ static const void *cat_func(int elem, int epi) {
                                                                              : (const void *)&cat_step<E, EPI_DECAY>)
     if (elem == ELEM_F16) return CAT_F(ELEM_F16);
     if (elem == ELEM_F8) return CAT_F(ELEM_F8);
+    if (elem == ELEM_I8X)   // cross counts are at most 4r + 1 <= 65: no 16-bit epilogue
+        return epi == EPI_DECAY ? (const void *)&cat_step<ELEM_I8X, EPI_DECAY> : (const void *)&cat_step<ELEM_I8X, EPI_BYTE>;
     if (elem == ELEM_I8W)   // radii 17..32 always have counts > 126: no 8-bit epilogue
         return epi == EPI_DECAY ? (const void *)&cat_step<ELEM_I8W, EPI_DECAY> : (const void *)&cat_step<ELEM_I8W, EPI_HALF>;
     return CAT_F(ELEM_I8);

@@ -53,7 +53,8 @@ __device__ __forceinline__ void direct_tile(const DirectParams &p, int gi0, int 
     for (int ly = ty; ly < DIRECT_TH; ly += 16) {
         const int lx = 4 * tx;
         int acc0 = 0, acc1 = 0, acc2 = 0, acc3 = 0;
-        for (int di = 0; di <= w; ++di) {
+        // Moore: every row of the box; cross: the centre row only, plus the centre column
+        for (int di = p.cross ? r : 0; di <= (p.cross ? r : w); ++di) {
             const uint8_t *row = lds + (ly + di) * p.LP + lx;
             for (int dj = 0; dj <= w + 3; ++dj) {
                 int b = row[dj];
@@ -61,6 +62,16 @@ __device__ __forceinline__ void direct_tile(const DirectParams &p, int gi0, int 
                 acc1 += (dj >= 1 && dj <= w + 1) ? b : 0;
                 acc2 += (dj >= 2 && dj <= w + 2) ? b : 0;
                 acc3 += (dj >= 3) ? b : 0;
+            }
+        }
+        if (p.cross) {
+            for (int di = 0; di <= w; ++di) {
+                if (di == r) continue;
+                const uint8_t *col = lds + (ly + di) * p.LP + lx + r;
+                acc0 += col[0];
+                acc1 += col[1];
+                acc2 += col[2];
+                acc3 += col[3];
             }
         }
         const int gr = gi0 + ly;

@@ -41,7 +41,8 @@ int32_t hip_fail(hipError_t e, const char *what) {
 
 int32_t validate_rule(const ltl_rule_t *r, int method) {
     if (!r) return fail(LTL_ERR_ARG, "rule is NULL");
-    if (r->N != 'M') return fail(LTL_ERR_UNSUPPORTED, "only the Moore neighbourhood (N = 'M') is supported");
+    if (r->N != 'M' && r->N != 'N')
+        return fail(LTL_ERR_UNSUPPORTED, "neighbourhood N must be 'M' (Moore) or 'N' (cross, simplified Von Neumann)");
     if (r->R < 1 || r->R > 32) return fail(LTL_ERR_RULE, "radius R must be in 1..32");
     if (r->C < 0 || r->C == 1 || r->C > 255) return fail(LTL_ERR_RULE, "C must be 0 or in 2..255");
     if (r->M != 0 && r->M != 1) return fail(LTL_ERR_RULE, "M must be 0 or 1");
@@ -54,13 +55,19 @@ int32_t validate_rule(const ltl_rule_t *r, int method) {
         return fail(LTL_ERR_INEXACT, "FP8 (e4m3) counts are exact only for 2R+1 <= 16");
     if (method == LTL_CAT_F16 && r->R > 16)
         return fail(LTL_ERR_UNSUPPORTED, "the FP16 method covers radii 1..16 (int8 covers 1..32)");
+    if (r->N == 'N' && (method == LTL_CAT_F16 || method == LTL_CAT_F8))
+        return fail(LTL_ERR_UNSUPPORTED, "the cross neighbourhood runs on the int8 CAT and direct methods");
+    if (r->N == 'N' && method == LTL_CAT_I8 && r->R > 16)
+        return fail(LTL_ERR_UNSUPPORTED, "the int8 CAT cross neighbourhood covers radii 1..16");
     return LTL_OK;
 }
 
+// Largest count of the rule's neighbourhood (centre included).
+int max_count(const ltl_rule_t &r) { return r.N == 'N' ? 4 * r.R + 1 : (2 * r.R + 1) * (2 * r.R + 1); }
+
 int epi_of(const ltl_rule_t &r) {
     if (r.C >= 3) return EPI_DECAY;
-    int nmax = (2 * r.R + 1) * (2 * r.R + 1);
-    return nmax <= 126 ? EPI_BYTE : EPI_HALF;
+    return max_count(r) <= 126 ? EPI_BYTE : EPI_HALF;
 }
 
 // Thresholds on the box count n (centre included) and the SWAR constants of the two-state
@@ -71,7 +78,7 @@ RuleConsts make_consts(const ltl_rule_t &r, int epi) {
     c.C = r.C >= 3 ? r.C : 2;
     c.M = r.M;
     c.s1 = r.S1; c.s2 = r.S2; c.b1 = r.B1; c.b2 = r.B2;
-    const int nmax = (2 * r.R + 1) * (2 * r.R + 1);
+    const int nmax = max_count(r);
     const int shift = (r.M == 0) ? 1 : 0;
     auto norm = [&](int lo, int hi, int cap, int &olo, int &ohi) {
         if (lo > hi || lo > nmax || hi < 0) { olo = cap; ohi = 0; return; }  // empty range
@@ -146,7 +153,8 @@ struct ltl_sim {
 
 namespace {
 
-int elem_of(int method, int R) {
+int elem_of(int method, int R, int N) {
+    if (method == LTL_CAT_I8 && N == 'N') return ELEM_I8X;
     if (method == LTL_CAT_I8 && R > 16) return ELEM_I8W;
     return method == LTL_CAT_F16 ? ELEM_F16 : method == LTL_CAT_F8 ? ELEM_F8 : ELEM_I8;
 }
@@ -169,7 +177,7 @@ ltl_tuning_t default_tuning(const ltl_sim &s) {
     t.tile_cols = 64;
     t.waves = 4;
     // grow the wave count until the widest step fits (one strip segment per wave)
-    while (t.waves < 8 && !cat_shape_fits(elem_of(s.method, s.rule.R), s.rule.R, t.steps_per_launch, t.tile_rows, t.tile_cols,
+    while (t.waves < 8 && !cat_shape_fits(elem_of(s.method, s.rule.R, s.rule.N), s.rule.R, t.steps_per_launch, t.tile_rows, t.tile_cols,
                                           t.waves))
         t.waves *= 2;
     t.use_graph = 1;
@@ -187,9 +195,9 @@ CatParams cat_params(const ltl_sim &s, const ltl_tuning_t &t, int T, const uint8
     p.T = T;
     p.TH = t.tile_rows;
     p.TW = t.tile_cols;
-    p.L = cat_margin(elem_of(s.method, s.rule.R), p.r, T);
+    p.L = cat_margin(elem_of(s.method, s.rule.R, s.rule.N), p.r, T);
     p.lds_rows = p.TH + 2 * p.L;
-    cat_lds_layout(elem_of(s.method, s.rule.R), s.epi, p.TH, p.TW, p.L, &p.PS, &p.PA, &p.lds_tile, &p.a_tile, &p.lds_total);
+    cat_lds_layout(elem_of(s.method, s.rule.R, s.rule.N), s.epi, p.TH, p.TW, p.L, &p.PS, &p.PA, &p.lds_tile, &p.a_tile, &p.lds_total);
     p.ntx = (s.W + p.TW - 1) / p.TW;
     p.nty = (s.H + p.TH - 1) / p.TH;
     p.bands = reinterpret_cast<const int32_t *>(s.dconst);
@@ -212,6 +220,7 @@ DirectParams direct_params(const ltl_sim &s, const uint8_t *src, uint8_t *dst) {
     p.TW = 64;
     p.LP = 64 + 2 * p.r;
     p.periodic = s.periodic;
+    p.cross = (s.rule.N == 'N') ? 1 : 0;
     p.rc = s.rc;
     return p;
 }
@@ -223,11 +232,11 @@ int32_t check_tuning(const ltl_sim &s, const ltl_tuning_t &t) {
     if (t.waves < 1 || t.waves > (s.method == LTL_DIRECT ? 16 : 8)) return fail(LTL_ERR_ARG, "waves must be in 1..8");
     if (s.method != LTL_DIRECT) {
         CatParams p = cat_params(s, t, t.steps_per_launch, nullptr, nullptr);
-        size_t lds = cat_lds_bytes(p, elem_of(s.method, s.rule.R), s.epi);
+        size_t lds = cat_lds_bytes(p, elem_of(s.method, s.rule.R, s.rule.N), s.epi);
         if (lds > max_lds_bytes()) return fail(LTL_ERR_ARG, "launch shape needs " + std::to_string(lds) + " bytes of LDS");
-        if (s.dconst && cat_occupancy(p, elem_of(s.method, s.rule.R), s.epi, t.waves) < 1)
+        if (s.dconst && cat_occupancy(p, elem_of(s.method, s.rule.R, s.rule.N), s.epi, t.waves) < 1)
             return fail(LTL_ERR_ARG, "launch shape does not fit on a compute unit (registers or LDS)");
-        if (!cat_shape_fits(elem_of(s.method, s.rule.R), s.rule.R, t.steps_per_launch, t.tile_rows, t.tile_cols, t.waves))
+        if (!cat_shape_fits(elem_of(s.method, s.rule.R, s.rule.N), s.rule.R, t.steps_per_launch, t.tile_rows, t.tile_cols, t.waves))
             return fail(LTL_ERR_ARG, "launch shape has more strip segments than waves in some step");
     } else if (t.steps_per_launch != 1) {
         return fail(LTL_ERR_ARG, "the direct method takes one step per launch");
@@ -254,7 +263,7 @@ PlannedLaunch plan(const ltl_sim &s, int steps_in_launch, int from) {
         pl.k = direct_launch_shape(pl.dp);
     } else {
         pl.cp = cat_params(s, s.tuning, steps_in_launch, src, dst);
-        pl.k = cat_launch_shape(pl.cp, elem_of(s.method, s.rule.R), s.epi, s.tuning.waves);
+        pl.k = cat_launch_shape(pl.cp, elem_of(s.method, s.rule.R, s.rule.N), s.epi, s.tuning.waves);
     }
     return pl;
 }
@@ -430,9 +439,9 @@ CatParams batch_cat_params(const ltl_batch &b, int i, const ltl_tuning_t &t, int
     p.r = b.rule[i].R;
     p.T = T;
     instance_tile(p.H, p.W, t.tile_rows, t.tile_cols, &p.TH, &p.TW);
-    p.L = cat_margin(elem_of(b.method, 16), p.r, T);
+    p.L = cat_margin(elem_of(b.method, 16, 'M'), p.r, T);
     p.lds_rows = p.TH + 2 * p.L;
-    cat_lds_layout(elem_of(b.method, 16), b.epi[i], p.TH, p.TW, p.L, &p.PS, &p.PA, &p.lds_tile, &p.a_tile, &p.lds_total);
+    cat_lds_layout(elem_of(b.method, 16, 'M'), b.epi[i], p.TH, p.TW, p.L, &p.PS, &p.PA, &p.lds_tile, &p.a_tile, &p.lds_total);
     p.ntx = (p.W + p.TW - 1) / p.TW;
     p.nty = (p.H + p.TH - 1) / p.TH;
     p.bands = reinterpret_cast<const int32_t *>(b.dconst + (p.r - 1) * kBandBytes);
@@ -455,6 +464,7 @@ DirectParams batch_direct_params(const ltl_batch &b, int i, int from) {
     p.TH = direct_tile_rows();
     p.TW = direct_tile_cols();
     p.LP = p.TW + 2 * p.r;
+    p.cross = (b.rule[i].N == 'N') ? 1 : 0;
     p.rc = b.rc[i];
     return p;
 }
@@ -463,7 +473,7 @@ bool batch_fits(const ltl_batch &b, const ltl_tuning_t &t) {
     for (int i = 0; i < b.count; ++i) {
         int th, tw;
         instance_tile(b.H[i], b.W[i], t.tile_rows, t.tile_cols, &th, &tw);
-        if (!cat_shape_fits(elem_of(b.method, 16), b.rule[i].R, t.steps_per_launch, th, tw, t.waves)) return false;
+        if (!cat_shape_fits(elem_of(b.method, 16, 'M'), b.rule[i].R, t.steps_per_launch, th, tw, t.waves)) return false;
     }
     return true;
 }
@@ -520,7 +530,7 @@ int32_t batch_check_tuning(const ltl_batch &b, const ltl_tuning_t &t) {
     int32_t slot;
     size_t lds = batch_cat_lds(b, t, t.steps_per_launch, &slot);
     if (lds > max_lds_bytes()) return fail(LTL_ERR_ARG, "launch shape needs " + std::to_string(lds) + " bytes of LDS");
-    if (b.dconst && cat_batch_occupancy(elem_of(b.method, 16), t.waves, lds) < 1)
+    if (b.dconst && cat_batch_occupancy(elem_of(b.method, 16, 'M'), t.waves, lds) < 1)
         return fail(LTL_ERR_ARG, "launch shape does not fit on a compute unit (registers or LDS)");
     return LTL_OK;
 }
@@ -648,7 +658,7 @@ int32_t batch_plan(ltl_batch &b, int T, BatchLaunchPlan **out) {
                     x.p = batch_cat_params(b, i, b.tuning, T, par);
                 }
             pl.lds = batch_cat_lds(b, b.tuning, T, &pl.slot);
-            const int occ = cat_batch_occupancy(elem_of(b.method, 16), b.tuning.waves, pl.lds);
+            const int occ = cat_batch_occupancy(elem_of(b.method, 16, 'M'), b.tuning.waves, pl.lds);
             if (occ < 1) return fail(LTL_ERR_ARG, "batched launch does not fit on a compute unit");
             pl.grid = std::max(1, std::min(occ * device_cus(), b.nitems));
             int32_t rc = upload(h, b.stream, &pl.dinst);
@@ -685,7 +695,7 @@ int32_t batch_launch(ltl_batch &b, int T, int from, BatchLaunch *l) {
         l->dp.items = b.ditems;
         l->dp.nitems = b.nitems;
     } else {
-        l->func = cat_batch_func(elem_of(b.method, 16));
+        l->func = cat_batch_func(elem_of(b.method, 16, 'M'));
         l->block = dim3((unsigned)(64 * b.tuning.waves), 1, 1);
         l->bp.inst = (const BatchInst *)pl->dinst + from * b.count;
         l->bp.items = b.ditems;
@@ -899,7 +909,7 @@ int32_t ltl_create(ltl_sim_t **out, int32_t H, int32_t W, const ltl_rule_t *rule
     if ((e = hipMalloc(&s->dflag, sizeof(uint32_t))) != hipSuccess) { s->dflag = nullptr; return bail(hip_fail(e, "hipMalloc")); }
     if ((e = hipMalloc(&s->dconst, kConstBytes)) != hipSuccess) { s->dconst = nullptr; return bail(hip_fail(e, "hipMalloc")); }
     {
-        std::vector<uint8_t> hc = host_constants(elem_of(method, rule->R), rule->R);
+        std::vector<uint8_t> hc = host_constants(elem_of(method, rule->R, rule->N), rule->R);
         if ((e = hipMemcpyAsync(s->dconst, hc.data(), kConstBytes, hipMemcpyHostToDevice, stream)) != hipSuccess)
             return bail(hip_fail(e, "hipMemcpyAsync"));
         if ((e = hipStreamSynchronize(stream)) != hipSuccess) return bail(hip_fail(e, "hipStreamSynchronize"));
@@ -949,7 +959,7 @@ int32_t ltl_get_tuning(ltl_sim_t *sim, ltl_tuning_t *tuning) {
 
 static bool s_fits(const ltl_sim &s, const ltl_tuning_t &t) {
     return s.method != LTL_DIRECT &&
-           !cat_shape_fits(elem_of(s.method, s.rule.R), s.rule.R, t.steps_per_launch, t.tile_rows, t.tile_cols, t.waves);
+           !cat_shape_fits(elem_of(s.method, s.rule.R, s.rule.N), s.rule.R, t.steps_per_launch, t.tile_rows, t.tile_cols, t.waves);
 }
 
 int32_t ltl_set_tuning(ltl_sim_t *sim, const ltl_tuning_t *tuning) {
@@ -1093,6 +1103,8 @@ int32_t ltl_batch_create(ltl_batch_t **out, int32_t count, const int32_t *H, con
         if ((rc = validate_rule(rules + i, method)) != LTL_OK) return fail(rc, "instance " + std::to_string(i) + ": " + g_err);
         if (method != LTL_DIRECT && rules[i].R > 16)
             return fail(LTL_ERR_UNSUPPORTED, "instance " + std::to_string(i) + ": batched CAT covers radii 1..16");
+        if (method != LTL_DIRECT && rules[i].N != 'M')
+            return fail(LTL_ERR_UNSUPPORTED, "instance " + std::to_string(i) + ": batched CAT covers the Moore neighbourhood");
         if (!init[i]) return fail(LTL_ERR_ARG, "instance " + std::to_string(i) + ": NULL initial grid");
         if (init_pitch[i] < (size_t)W[i]) return fail(LTL_ERR_ARG, "instance " + std::to_string(i) + ": init_pitch < W");
         if (grid_too_large(H[i], W[i]))
@@ -1134,7 +1146,7 @@ int32_t ltl_batch_create(ltl_batch_t **out, int32_t count, const int32_t *H, con
         std::vector<uint8_t> hc(cbytes, 0);
         if (method != LTL_DIRECT)
             for (int r = 1; r <= kMaxR; ++r)
-                band_table(elem_of(method, 16), r, reinterpret_cast<int32_t *>(hc.data() + (r - 1) * kBandBytes));
+                band_table(elem_of(method, 16, 'M'), r, reinterpret_cast<int32_t *>(hc.data() + (r - 1) * kBandBytes));
         if ((e = hipMemcpyAsync(b->dconst, hc.data(), cbytes, hipMemcpyHostToDevice, stream)) != hipSuccess)
             return bail(hip_fail(e, "hipMemcpyAsync"));
         if ((e = hipStreamSynchronize(stream)) != hipSuccess) return bail(hip_fail(e, "hipStreamSynchronize"));

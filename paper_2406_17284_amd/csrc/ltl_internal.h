@@ -14,8 +14,10 @@ enum Epi { EPI_BYTE = 0, EPI_HALF = 1, EPI_DECAY = 2 };
 // Element type of the band-product operands. ELEM_I8W is int8 for radii 17..32: every
 // 16-column half needs 16 + 2r <= 80 columns (a K = 64 and a K = 32 product) and every
 // output block the H blocks two above to two below it (a 4-block and a 2-block window).
-enum Elem { ELEM_I8 = 0, ELEM_F16 = 1, ELEM_F8 = 2, ELEM_I8W = 3 };
-inline bool elem_is_i8(int elem) { return elem == ELEM_I8 || elem == ELEM_I8W; }
+// ELEM_I8X is int8 for the cross neighbourhood (rule code N_N, r <= 16): besides H it packs
+// the alive map itself into the H register layout, for the vertical arm of the cross.
+enum Elem { ELEM_I8 = 0, ELEM_F16 = 1, ELEM_F8 = 2, ELEM_I8W = 3, ELEM_I8X = 4 };
+inline bool elem_is_i8(int elem) { return elem == ELEM_I8 || elem == ELEM_I8W || elem == ELEM_I8X; }
 
 // Rule constants prepared on the host (thresholds on the box count n that includes
 // the centre: for an alive centre with M = 0 the survival range is shifted by one).
@@ -69,6 +71,12 @@ struct CatParams {
 //               strip start (8 bytes, K = 8 g + j)
 //         4, 5  MFMA #2 for an even block offset: 4-block window m-2..m+1, pair m+2, m+3
 //         6, 7  odd offset: 4-block window m-3..m, pair m+1, m+2
+//  int8 cross (N_N): 0, 1  MFMA #1 halves as int8 (H = horizontal arm, centre included)
+//         2, 3  MFMA #1 identity for halves 0/1: weight 1 iff k - 16 - 16 h == n (packs the
+//               alive map itself into the H layout)
+//         4, 5  MFMA #2 on the alive map, windows from block m-1 / m-2: vertical arm without
+//               the centre (1 iff 0 < |row - n| <= r)
+//         6, 7  MFMA #2 on H, windows from block m-1 / m-2: identity (1 iff row == n)
 // MFMA #2 rows: block at distance delta from the output block, row 4 g + e of it, weight 1 iff
 // |16 delta + 4 g + e - n| <= r. int8 and fp8 tables hold 0/1 bytes (fp8 is encoded on the
 // device with the hardware's 1.0); fp16 holds 0x3C00 halves.
@@ -87,7 +95,21 @@ inline void band_table(int elem, int r, int32_t *out) {
         auto put_half = [&](int op, int j, bool on) {
             if (on) out[(op * 64 + lane) * 4 + j / 2] |= 0x3C00 << (16 * (j & 1));
         };
-        if (elem == ELEM_I8W) {
+        if (elem == ELEM_I8X) {
+            for (int d = 0; d < 4; ++d)
+                for (int e = 0; e < 4; ++e) {
+                    const int k = 16 * g + 4 * d + e;
+                    put_byte(0, d, e, band_hit(k - 16 - n, r));
+                    put_byte(1, d, e, band_hit(k - 32 - n, r));
+                    put_byte(2, d, e, k - 16 == n);
+                    put_byte(3, d, e, k - 32 == n);
+                    const int row1 = 16 * (d - 1) + 4 * g + e - n, row2 = 16 * (d - 2) + 4 * g + e - n;
+                    put_byte(4, d, e, row1 != 0 && band_hit(row1, r));
+                    put_byte(5, d, e, row2 != 0 && band_hit(row2, r));
+                    put_byte(6, d, e, row1 == 0);
+                    put_byte(7, d, e, row2 == 0);
+                }
+        } else if (elem == ELEM_I8W) {
             for (int h = 0; h < 2; ++h) {
                 for (int d = 0; d < 4; ++d)
                     for (int e = 0; e < 4; ++e)
@@ -146,6 +168,7 @@ struct DirectParams {
     int32_t TH, TW;       // output tile of the direct kernel
     int32_t LP;           // LDS row pitch
     int32_t periodic;     // 1: the grid is a torus; 0: dead ghost halo
+    int32_t cross;        // 1: cross neighbourhood (N_N); 0: Moore box
     RuleConsts rc;
 };
 
@@ -163,8 +186,10 @@ inline int cat_margin(int elem, int r, int T) { return roundup(r * (T - 1), 16) 
 #define CAT_MAXC_F8 14
 #define CAT_MAXC_F16 5
 #define CAT_MAXC_I8W 11
+#define CAT_MAXC_I8X 6
 inline int cat_maxc(int elem) {
-    return elem == ELEM_F16 ? CAT_MAXC_F16 : elem == ELEM_F8 ? CAT_MAXC_F8 : elem == ELEM_I8W ? CAT_MAXC_I8W : CAT_MAXC_I8;
+    return elem == ELEM_F16 ? CAT_MAXC_F16 : elem == ELEM_F8 ? CAT_MAXC_F8 : elem == ELEM_I8W ? CAT_MAXC_I8W
+         : elem == ELEM_I8X ? CAT_MAXC_I8X : CAT_MAXC_I8;
 }
 inline int cat_cell_bytes(int elem) { return elem == ELEM_F16 ? 2 : 1; }
 

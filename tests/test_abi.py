@@ -57,7 +57,9 @@ def _create(H=8, W=8, rule=(1, 0, 1, 3, 4, 3, 3), method=ltl.LTL_CAT_I8, a=256, 
     (dict(rule=(1, 0, 2, 3, 4, 3, 3)), ltl.LTL_ERR_RULE),
     (dict(rule=(1, 0, 1, -1, 4, 3, 3)), ltl.LTL_ERR_RULE),
     (dict(rule=(1, 0, 1, 3, 10, 3, 3)), ltl.LTL_ERR_RULE),
-    (dict(rule=(2, 0, 1, 3, 4, 3, 3, "N")), ltl.LTL_ERR_UNSUPPORTED),
+    (dict(rule=(2, 0, 1, 3, 4, 3, 3, "X")), ltl.LTL_ERR_UNSUPPORTED),
+    (dict(rule=(2, 0, 1, 3, 4, 3, 3, "N"), method=ltl.LTL_CAT_F16), ltl.LTL_ERR_UNSUPPORTED),
+    (dict(rule=(17, 0, 1, 3, 4, 3, 3, "N")), ltl.LTL_ERR_UNSUPPORTED),
     (dict(rule=(8, 0, 1, 3, 4, 3, 3), method=ltl.LTL_CAT_F8), ltl.LTL_ERR_INEXACT),
     (dict(method=7), ltl.LTL_ERR_ARG),
     (dict(nbytes=63), ltl.LTL_ERR_SIZE),
@@ -105,6 +107,7 @@ def _batch_create(H=(8, 8), W=(8, 8), rules=((1, 0, 1, 3, 4, 3, 3), (2, 3, 0, 5,
     (dict(H=(8, 0)), ltl.LTL_ERR_ARG),
     (dict(rules=((1, 0, 1, 3, 4, 3, 3), (33, 0, 1, 3, 4, 3, 3))), ltl.LTL_ERR_RULE),
     (dict(rules=((1, 0, 1, 3, 4, 3, 3), (17, 0, 1, 3, 4, 3, 3))), ltl.LTL_ERR_UNSUPPORTED),
+    (dict(rules=((1, 0, 1, 3, 4, 3, 3), (1, 0, 1, 3, 4, 3, 3, "X"))), ltl.LTL_ERR_UNSUPPORTED),
     (dict(rules=((1, 0, 1, 3, 4, 3, 3), (1, 0, 1, 3, 4, 3, 3, "N"))), ltl.LTL_ERR_UNSUPPORTED),
     (dict(rules=((7, 0, 1, 3, 4, 3, 3), (8, 0, 1, 3, 4, 3, 3)), method=ltl.LTL_CAT_F8), ltl.LTL_ERR_INEXACT),
     (dict(method=9), ltl.LTL_ERR_ARG),

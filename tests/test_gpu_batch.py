@@ -232,3 +232,15 @@ def test_batch_graph_replays_match_eager(ltl):
     check_batch(graph, [oracle.run(g, r, 18) for g, r in zip(grids, rules)], "graph replays")
     graph.close()
     eager.close()
+
+
+def test_batch_cross_rules(ltl):
+    grids, rules = small_batch(7, max_r=12, decay=False)
+    rules = [inputs.Rule(*r.as_tuple(), N="N") for r in rules]
+    with pytest.raises(ltl.LtlError) as e:
+        ltl.Batch([gpu_grid(g) for g in grids], rules, "cat_i8")
+    assert e.value.code == ltl.LTL_ERR_UNSUPPORTED
+    batch = ltl.Batch([gpu_grid(g) for g in grids], rules, "direct")
+    batch.step(3)
+    check_batch(batch, [oracle.run(g, r, 3) for g, r in zip(grids, rules)], "direct cross batch")
+    batch.close()

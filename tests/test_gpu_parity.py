@@ -358,3 +358,54 @@ def test_graph_replays_match_eager(ltl):
     assert np.array_equal(graph.read().cpu().numpy(), oracle.run(g0, rule, 32))
     graph.close()
     eager.close()
+
+
+# ------------------------------------------------------------------ cross neighbourhood (N_N)
+CROSS_RULES = [inputs.Rule(1, 0, 1, 2, 3, 3, 3, "N"), inputs.Rule(2, 0, 0, 2, 5, 3, 4, "N"),
+               inputs.Rule(5, 4, 1, 5, 12, 6, 9, "N"), inputs.Rule(9, 0, 1, 10, 22, 12, 17, "N"),
+               inputs.Rule(16, 0, 1, 17, 40, 20, 30, "N"), inputs.Rule(7, 0, 1, 20, 10, 8, 14, "N")]
+
+
+@pytest.mark.parametrize("method", ["cat_i8", "direct"])
+@pytest.mark.parametrize("rule", CROSS_RULES, ids=lambda r: r.text())
+def test_cross_every_step(ltl, method, rule):
+    g0 = (inputs.state_grid(83, 151, rule.C, seed=rule.R + 40) if rule.C >= 3
+          else inputs.bernoulli_grid(83, 151, 0.5, seed=rule.R + 40))
+    run_and_compare_each_step(ltl, g0, rule, method, 4)
+
+
+@pytest.mark.parametrize("T", [2, 3, 5])
+@pytest.mark.parametrize("tile", [(64, 64), (96, 128), (32, 192)], ids=lambda t: f"{t[0]}x{t[1]}")
+@pytest.mark.parametrize("r", [1, 5, 16])
+def test_cross_launch_shapes(ltl, T, tile, r):
+    rule = inputs.Rule(r, 0, 1, r, 3 * r, r + 1, 2 * r, "N")
+    g0 = inputs.bernoulli_grid(200, 333, 0.5, seed=700 + r)
+    tuning = dict(steps_per_launch=T, tile_rows=tile[0], tile_cols=tile[1], waves=0)
+    if not shape_feasible(r, T, tile[0], tile[1], maxc=6):
+        with pytest.raises(ltl.LtlError) as e:
+            run_and_compare(ltl, g0, rule, "cat_i8", 7, tuning=tuning)
+        assert e.value.code == ltl.LTL_ERR_ARG
+        return
+    run_and_compare(ltl, g0, rule, "cat_i8", 7, tuning=tuning)
+
+
+def test_cross_periodic(ltl):
+    rule = inputs.Rule(4, 0, 1, 4, 9, 5, 7, "N")
+    for method in ("cat_i8", "direct"):
+        run_periodic(ltl, inputs.bernoulli_grid(64, 80, 0.5, seed=81), rule, method, 4)
+    run_periodic(ltl, inputs.bernoulli_grid(130, 224, 0.5, seed=82), rule, "cat_i8", 6,
+                 tuning=dict(steps_per_launch=3, tile_rows=64, tile_cols=64), every_step=False)
+
+
+def test_cross_refusals_and_direct_range(ltl):
+    g = gpu_grid(np.zeros((8, 8), dtype=np.uint8))
+    for method in ("cat_f16", "cat_f8"):
+        with pytest.raises(ltl.LtlError) as e:
+            ltl.Simulation(g, inputs.Rule(3, 0, 1, 3, 6, 4, 5, "N"), method)
+        assert e.value.code == ltl.LTL_ERR_UNSUPPORTED
+    with pytest.raises(ltl.LtlError) as e:
+        ltl.Simulation(g, inputs.Rule(17, 0, 1, 20, 40, 25, 30, "N"), "cat_i8")
+    assert e.value.code == ltl.LTL_ERR_UNSUPPORTED
+    # the direct stencil covers the cross up to r = 32
+    rule = inputs.Rule(24, 0, 1, 25, 60, 30, 45, "N")
+    run_and_compare_each_step(ltl, inputs.bernoulli_grid(90, 140, 0.5, seed=24), rule, "direct", 3)
