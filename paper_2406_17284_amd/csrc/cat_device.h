@@ -271,10 +271,11 @@ __device__ __forceinline__ void phase_a(const uint8_t *At, uint32_t a_off, uint3
     (void)Lb;
     if constexpr (ELEM == ELEM_I8W) {
         // radius 17..32: H blocks rb0 - 2 .. rb0 + count + 2; per half a K = 64 product on the
-        // chunk at a_off and a K = 32 product on the 8 bytes at a_off2, summed. The two products
-        // get separate zero accumulators and a VALU add: feeding the 16x16x64 result to the
-        // 16x16x32 instruction as its accumulator input gave wrong sums on gfx950 with this
-        // toolchain (the dependency between MFMAs of different shapes is not waited for).
+        // chunk at a_off plus a product on the 8 bytes at a_off2 (32 columns). The second product
+        // also runs as 16x16x64: its band has zero weight in the upper 8 bytes of every lane, so
+        // the A operand's upper half is left undefined, and the two products chain through the
+        // accumulator of one instruction shape (a 16x16x64 result fed as the accumulator of a
+        // 16x16x32 instruction gave wrong sums on gfx950 with this toolchain).
         const int nh = count + 5;
         const v4i zero = {0, 0, 0, 0};
         v4i a[4];
@@ -287,12 +288,14 @@ __device__ __forceinline__ void phase_a(const uint8_t *At, uint32_t a_off, uint3
         }
 #define CAT_HB(K)                                                                                  \
         {                                                                                          \
+            const v2i b2 = __builtin_bit_cast(v2i, b[(K) & 3]);                                    \
+            const v4i b4 = __builtin_shufflevector(b2, b2, 0, 1, -1, -1);                          \
             v4i da = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[(K) & 3], bd.op[0], zero, 0, 0, 0);   \
-            v4i ea = __builtin_amdgcn_mfma_i32_16x16x32_i8(b[(K) & 3], lo8(bd.op[1]), zero, 0, 0, 0); \
+            da = __builtin_amdgcn_mfma_i32_16x16x64_i8(b4, bd.op[1], da, 0, 0, 0);                 \
             v4i db = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[(K) & 3], bd.op[2], zero, 0, 0, 0);   \
-            v4i eb = __builtin_amdgcn_mfma_i32_16x16x32_i8(b[(K) & 3], lo8(bd.op[3]), zero, 0, 0, 0); \
-            Ha[(K)] = (int32_t)pack_bytes(da + ea);                                                \
-            Hb[(K)] = (int32_t)pack_bytes(db + eb);                                                \
+            db = __builtin_amdgcn_mfma_i32_16x16x64_i8(b4, bd.op[3], db, 0, 0, 0);                 \
+            Ha[(K)] = (int32_t)pack_bytes(da);                                                     \
+            Hb[(K)] = (int32_t)pack_bytes(db);                                                     \
         }
 #define CAT_APAIR(P)                                                                               \
         if (2 * (P) < nh) {                                                                        \
@@ -419,14 +422,16 @@ __device__ __forceinline__ v4i vproduct(const v16i &H, const v16i &L, const Band
         v4i c = __builtin_amdgcn_mfma_i32_16x16x64_i8(window4<W0>(H), (M & 1) ? bd.op[7] : bd.op[6], zero, 0, 0, 0);
         return __builtin_amdgcn_mfma_i32_16x16x64_i8(window4<W0>(L), (M & 1) ? bd.op[5] : bd.op[4], c, 0, 0, 0);
     } else if constexpr (ELEM == ELEM_I8W) {
-        // tuple element k holds block rb0 - 2 + k; output block rb0 + M needs elements M .. M+4
+        // tuple element k holds block rb0 - 2 + k; output block rb0 + M needs elements M .. M+4.
+        // The pair window is the 4-element window from M + 4 (M + 3) whose upper two elements
+        // have zero weight (the band's upper 8 bytes per lane are 0).
         const v4i zero = {0, 0, 0, 0};
         if constexpr ((M & 1) == 0) {
             v4i c = __builtin_amdgcn_mfma_i32_16x16x64_i8(window4<M>(H), bd.op[4], zero, 0, 0, 0);
-            return c + __builtin_amdgcn_mfma_i32_16x16x32_i8(window2<M + 4>(H), lo8(bd.op[5]), zero, 0, 0, 0);
+            return __builtin_amdgcn_mfma_i32_16x16x64_i8(window4<M + 4>(H), bd.op[5], c, 0, 0, 0);
         } else {
             v4i c = __builtin_amdgcn_mfma_i32_16x16x64_i8(window4<M - 1>(H), bd.op[6], zero, 0, 0, 0);
-            return c + __builtin_amdgcn_mfma_i32_16x16x32_i8(window2<M + 3>(H), lo8(bd.op[7]), zero, 0, 0, 0);
+            return __builtin_amdgcn_mfma_i32_16x16x64_i8(window4<M + 3>(H), bd.op[7], c, 0, 0, 0);
         }
     } else if constexpr (ELEM == ELEM_I8) {
         const v4i zero = {0, 0, 0, 0};
@@ -543,10 +548,10 @@ __device__ __forceinline__ void phase_b(const CatParams &p, uint8_t *Qt, uint8_t
         CAT_ISSUE(0) CAT_ISSUE(1)
         CAT_BPAIR(0, 1) CAT_BPAIR(1, 1)
         CAT_BPAIR(2, 0)
-    } else if constexpr (ELEM == ELEM_I8W) {   // at most CAT_MAXC_I8W = 11 blocks
+    } else if constexpr (ELEM == ELEM_I8W) {   // at most CAT_MAXC_I8W = 9 blocks
         CAT_ISSUE(0) CAT_ISSUE(1)
-        CAT_BPAIR(0, 1) CAT_BPAIR(1, 1) CAT_BPAIR(2, 1) CAT_BPAIR(3, 1) CAT_BPAIR(4, 1)
-        CAT_BPAIR(5, 0)
+        CAT_BPAIR(0, 1) CAT_BPAIR(1, 1) CAT_BPAIR(2, 1) CAT_BPAIR(3, 1)
+        CAT_BPAIR(4, 0)
     } else {
         CAT_ISSUE(0) CAT_ISSUE(1)
         CAT_BPAIR(0, 1) CAT_BPAIR(1, 1) CAT_BPAIR(2, 1) CAT_BPAIR(3, 1) CAT_BPAIR(4, 1) CAT_BPAIR(5, 1)

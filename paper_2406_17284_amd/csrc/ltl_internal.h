@@ -185,7 +185,7 @@ inline int cat_margin(int elem, int r, int T) { return roundup(r * (T - 1), 16) 
 #define CAT_MAXC_I8 14
 #define CAT_MAXC_F8 14
 #define CAT_MAXC_F16 5
-#define CAT_MAXC_I8W 11
+#define CAT_MAXC_I8W 9    // the pair window of the last block (one past included) ends at element 15
 #define CAT_MAXC_I8X 6
 inline int cat_maxc(int elem) {
     return elem == ELEM_F16 ? CAT_MAXC_F16 : elem == ELEM_F8 ? CAT_MAXC_F8 : elem == ELEM_I8W ? CAT_MAXC_I8W

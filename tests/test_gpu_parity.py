@@ -113,7 +113,7 @@ def shape_feasible(r, T, TH, TW, waves=8, maxc=14, cell=1, lds_max=160 * 1024):
     int8 above r = 16 reads two more H blocks per segment (11 output blocks, margin + 32)."""
     wide = r > 16 and cell == 1 and maxc == 14
     if wide:
-        maxc = 11
+        maxc = 9
     margin = -(-r * (T - 1) // 16) * 16 + (48 if wide else 16)
     rows, cols = TH + 2 * margin, TW + 2 * margin
     lds = -(-rows * (cols + 16) // 1024) * 1024
