@@ -614,7 +614,8 @@ __device__ __forceinline__ void cat_steps(const CatParams &p, uint8_t *Qt, uint8
                 }
             }
             const int gr0 = gi0 + 16 * rb0 + li;
-            const uint32_t goff0 = (uint32_t)(gr0 * p.pitch + gca);
+            // modular 32-bit offset: rows outside the grid (never stored) may wrap
+            const uint32_t goff0 = (uint32_t)gr0 * (uint32_t)p.pitch + (uint32_t)gca;
             if (last)
                 phase_b<ELEM, EPI, MASKED, true>(p, Qt, At, lo, rb0, count, gr0, goff0, gca, cma, cmb, bd, cd, Ha, Hb,
                                                  La, Lb);

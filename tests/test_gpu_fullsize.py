@@ -118,3 +118,27 @@ def test_decay_c8_32768(ltl):
     assert not cat.current_padded()[:, w.W:].any()
     cat.close()
     direct.close()
+
+
+def test_largest_grid(ltl):
+    """The largest grid the 32-bit row offsets allow: 46336 x 46336 (2 147 024 896 bytes, just
+    under 2^31). Windows at the four corners and the centre against the oracle; CAT equals the
+    direct stencil everywhere."""
+    n = 46336
+    rule = inputs.BOSCO_M1
+    g = inputs.bernoulli_grid_torch(n, n, 0.5, 9, device="cuda")
+    cat = ltl.Simulation(g, rule, "cat_i8", tuning=dict(steps_per_launch=2, tile_rows=176, tile_cols=224))
+    cat.step(2)
+    state = cat.read()
+    for (i, j) in [(0, 0), (0, n - 1), (n - 1, 0), (n - 1, n - 1), (n // 2, n // 2)]:
+        ref = oracle.cone_run(lambda rr, cc: inputs.bernoulli_grid(n, n, 0.5, 9, rows=rr, cols=cc),
+                              n, n, rule, 2, i, j, radius=6)
+        a0, b0 = max(0, i - 6), max(0, j - 6)
+        assert np.array_equal(state[a0:a0 + ref.shape[0], b0:b0 + ref.shape[1]].cpu().numpy(), ref), (i, j)
+    assert not cat.current_padded()[:, n:].any()
+    cat.close()
+    d = ltl.Simulation(g, rule, "direct")
+    del g
+    d.step(2)
+    assert torch.equal(d.read(), state)
+    d.close()
