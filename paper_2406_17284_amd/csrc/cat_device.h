@@ -671,12 +671,9 @@ __device__ __forceinline__ void issue_tile_load(const CatParams &p, int gi0, int
 // One tile: load the window with direct LDS loads, derive the alive map in the element
 // encoding, then T steps in place (the last one writes the output grid). Ends without a
 // barrier: a caller that reuses the LDS for another tile synchronizes first.
-// `slot`, if not null: thread 0 stores `next` there once the tile's loads have completed
-// (the batched kernel passes a work-list index that was taken before the loads were issued).
 template <int ELEM, int EPI>
 __device__ __forceinline__ void cat_tile(const CatParams &p, int tile, uint8_t *lds, int tid, int lane, int wave,
-                                         int nwaves, const Codec &cd, uint32_t *slot = nullptr,
-                                         uint32_t next = 0) {
+                                         int nwaves, const Codec &cd) {
     const int gi0 = (tile / p.ntx) * p.TH;
     const int gj0 = (tile % p.ntx) * p.TW;
 
@@ -694,7 +691,6 @@ __device__ __forceinline__ void cat_tile(const CatParams &p, int tile, uint8_t *
         }
     }
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-    if (slot != nullptr && tid == 0) *slot = next;
     __syncthreads();
 
     // alive map from the loaded states (int8 without decay reads the states directly)

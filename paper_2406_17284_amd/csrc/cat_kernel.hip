@@ -14,10 +14,12 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) c
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform: keeps item code scalar
     const int nwaves = blockDim.x >> 6;
 
+    // The grid is the tile count rounded up to a multiple of 8: workgroup b runs on XCD b mod 8,
+    // which takes the contiguous block of tiles (b mod 8) * nb/8 ...; surplus workgroups exit.
     const int ntiles = p.ntx * p.nty;
     const int nb = gridDim.x;
     const int bid = blockIdx.x;
-    const int tile = (nb & 7) ? bid : (bid & 7) * (nb >> 3) + (bid >> 3);
+    const int tile = (bid & 7) * (nb >> 3) + (bid >> 3);
     if (tile >= ntiles) return;
     const Codec cd = make_codec();
     cat_tile<ELEM, EPI>(p, tile, lds, tid, lane, wave, nwaves, cd);
@@ -56,7 +58,7 @@ KernelLaunch cat_launch_shape(const CatParams &p, int elem, int epi, int waves) 
     KernelLaunch k;
     k.func = cat_func(elem, epi);
     k.lds = cat_lds_bytes(p, elem, epi);
-    k.grid = dim3((unsigned)((long)p.ntx * p.nty), 1, 1);
+    k.grid = dim3((unsigned)roundup(p.ntx * p.nty, 8), 1, 1);
     k.block = dim3(64 * waves, 1, 1);
     return k;
 }

@@ -365,8 +365,7 @@ int32_t do_steps(ltl_sim &s, int32_t n) {
 struct BatchLaunchPlan {
     void *dinst = nullptr;       // BatchInst[2][count] (CAT) or DirectBatchInst[2][count], by source arena
     size_t lds = 0;              // dynamic LDS bytes
-    int32_t slot = 0;            // LDS offset of the work-list hand-off dwords (CAT)
-    int32_t grid = 0;            // workgroups
+    int32_t grid = 0;            // workgroups (one per work-list entry)
 };
 
 } // namespace
@@ -387,12 +386,9 @@ struct ltl_batch {
     ltl_tuning_t tuning{};
     bool owns_shared = true;         // false for the autotuner's probe, which borrows the below
     uint8_t *dconst = nullptr;       // band tables for r = 1..16 of the method's element type, zero page
-    uint32_t *dqueue = nullptr;      // work-list counters (all 0 between launches)
     uint32_t *dflag = nullptr;
     BatchItem *ditems = nullptr;     // work list of the tuning
     int32_t nitems = 0;
-    int32_t cls_start[3] = {0, 0, 0};  // CAT: entries of epilogue class c (Epi) in the work list
-    int32_t cls_count[3] = {0, 0, 0};
     std::vector<BatchLaunchPlan> plans;
     std::map<std::pair<int32_t, int>, hipGraphExec_t> graphs;
 };
@@ -510,11 +506,10 @@ ltl_tuning_t batch_default_tuning(const ltl_batch &b) {
     return t;
 }
 
-size_t batch_cat_lds(const ltl_batch &b, const ltl_tuning_t &t, int T, int32_t *slot) {
+size_t batch_cat_lds(const ltl_batch &b, const ltl_tuning_t &t, int T) {
     int32_t m = 0;
     for (int i = 0; i < b.count; ++i) m = std::max(m, batch_cat_params(b, i, t, T).lds_total);
-    *slot = roundup(m, 16);
-    return (size_t)*slot + 16;
+    return (size_t)m;
 }
 
 int32_t batch_check_tuning(const ltl_batch &b, const ltl_tuning_t &t) {
@@ -527,8 +522,7 @@ int32_t batch_check_tuning(const ltl_batch &b, const ltl_tuning_t &t) {
     }
     if (t.waves < 1 || t.waves > 8) return fail(LTL_ERR_ARG, "waves must be in 1..8");
     if (!batch_fits(b, t)) return fail(LTL_ERR_ARG, "launch shape has more strip segments than waves for some instance");
-    int32_t slot;
-    size_t lds = batch_cat_lds(b, t, t.steps_per_launch, &slot);
+    size_t lds = batch_cat_lds(b, t, t.steps_per_launch);
     if (lds > max_lds_bytes()) return fail(LTL_ERR_ARG, "launch shape needs " + std::to_string(lds) + " bytes of LDS");
     if (b.dconst && cat_batch_occupancy(elem_of(b.method, 16, 'M'), t.waves, lds) < 1)
         return fail(LTL_ERR_ARG, "launch shape does not fit on a compute unit (registers or LDS)");
@@ -554,11 +548,9 @@ void batch_release(ltl_batch &b) {
     batch_free_plans(b);
     if (b.owns_shared) {
         if (b.dconst) (void)hipFree(b.dconst);
-        if (b.dqueue) (void)hipFree(b.dqueue);
         if (b.dflag) (void)hipFree(b.dflag);
     }
     b.dconst = nullptr;
-    b.dqueue = nullptr;
     b.dflag = nullptr;
 }
 
@@ -578,15 +570,14 @@ int32_t upload(const std::vector<X> &h, hipStream_t s, void **out) {
     return LTL_OK;
 }
 
-// Work list of the current tuning: every (instance, tile), grouped by the epilogue class of
-// the instance's rule (CAT) and most expensive first within a class. The cost model counts
-// the cells each step of a launch recomputes (tile plus its shrinking margin) and a quarter of
+// Work list of the current tuning: every (instance, tile), most expensive first (workgroups are
+// dispatched in entry order). The cost model counts the cells each step of a launch recomputes
+// (tile plus its shrinking margin; 16-bit and decay epilogues a little dearer) and a quarter of
 // the loaded window.
 int32_t batch_prepare(ltl_batch &b) {
     batch_free_plans(b);
     const ltl_tuning_t &t = b.tuning;
     struct Entry {
-        int cls;
         double cost;
         BatchItem it;
     };
@@ -604,24 +595,30 @@ int32_t batch_prepare(ltl_batch &b) {
             cost = 0.25 * (double)(p.TH + 2 * p.L) * (p.TW + 2 * p.L);
             for (int st = 1; st <= p.T; ++st) {
                 const int E = roundup(r * (p.T - st), 16);
-                cost += (double)(p.TH + 2 * E) * (p.TW + 2 * E);
+                cost += (double)(p.TH + 2 * E) * (p.TW + 2 * E) * (b.epi[i] == EPI_BYTE ? 1.0 : 1.15);
             }
         }
-        const int cls = (b.method == LTL_DIRECT) ? 0 : b.epi[i];
-        for (int k = 0; k < ntiles; ++k) list.push_back({cls, cost, {i, k}});
+        for (int k = 0; k < ntiles; ++k) list.push_back({cost, {i, k, b.epi[i], 0}});
     }
-    std::stable_sort(list.begin(), list.end(), [](const Entry &x, const Entry &y) {
-        return x.cls != y.cls ? x.cls < y.cls : x.cost > y.cost;
-    });
+    std::stable_sort(list.begin(), list.end(), [](const Entry &x, const Entry &y) { return x.cost > y.cost; });
     std::vector<BatchItem> items;
     items.reserve(list.size());
-    for (int c = 0; c < 3; ++c) b.cls_count[c] = 0;
-    for (auto &e : list) {
-        items.push_back(e.it);
-        b.cls_count[e.cls] += 1;
+    for (auto &e : list) items.push_back(e.it);
+    // Workgroup k runs on XCD k mod 8. The tiles of one instance are a run of equal cost; within
+    // each run, give every XCD a contiguous block of tiles (row-major), so neighbouring tiles
+    // share that XCD's L2 and their halo re-reads hit it. The cost order is unchanged.
+    for (size_t a = 0; a < items.size();) {
+        size_t e = a;
+        while (e < items.size() && items[e].inst == items[a].inst) ++e;
+        std::vector<size_t> pos;
+        for (size_t x = 0; x < 8; ++x)
+            for (size_t q = a; q < e; ++q)
+                if (q % 8 == (a + x) % 8) pos.push_back(q);
+        std::vector<BatchItem> run(items.begin() + a, items.begin() + e);
+        std::sort(run.begin(), run.end(), [](const BatchItem &x, const BatchItem &y) { return x.tile < y.tile; });
+        for (size_t t = 0; t < run.size(); ++t) items[pos[t]] = run[t];
+        a = e;
     }
-    b.cls_start[0] = 0;
-    for (int c = 1; c < 3; ++c) b.cls_start[c] = b.cls_start[c - 1] + b.cls_count[c - 1];
     void *d = nullptr;
     int32_t rc = upload(items, b.stream, &d);
     if (rc != LTL_OK) return rc;
@@ -657,10 +654,10 @@ int32_t batch_plan(ltl_batch &b, int T, BatchLaunchPlan **out) {
                     std::memset(&x, 0, sizeof(x));
                     x.p = batch_cat_params(b, i, b.tuning, T, par);
                 }
-            pl.lds = batch_cat_lds(b, b.tuning, T, &pl.slot);
-            const int occ = cat_batch_occupancy(elem_of(b.method, 16, 'M'), b.tuning.waves, pl.lds);
-            if (occ < 1) return fail(LTL_ERR_ARG, "batched launch does not fit on a compute unit");
-            pl.grid = std::max(1, std::min(occ * device_cus(), b.nitems));
+            pl.lds = batch_cat_lds(b, b.tuning, T);
+            if (cat_batch_occupancy(elem_of(b.method, 16, 'M'), b.tuning.waves, pl.lds) < 1)
+                return fail(LTL_ERR_ARG, "batched launch does not fit on a compute unit");
+            pl.grid = b.nitems;
             int32_t rc = upload(h, b.stream, &pl.dinst);
             if (rc != LTL_OK) return rc;
         }
@@ -699,12 +696,7 @@ int32_t batch_launch(ltl_batch &b, int T, int from, BatchLaunch *l) {
         l->block = dim3((unsigned)(64 * b.tuning.waves), 1, 1);
         l->bp.inst = (const BatchInst *)pl->dinst + from * b.count;
         l->bp.items = b.ditems;
-        l->bp.queue = b.dqueue;
-        for (int c = 0; c < 3; ++c) {
-            l->bp.start[c] = b.cls_start[c];
-            l->bp.count[c] = b.cls_count[c];
-        }
-        l->bp.slot = pl->slot;
+        l->bp.nitems = b.nitems;
     }
     if (l->lds > 65536)
         HIP_TRY(hipFuncSetAttribute(l->func, hipFuncAttributeMaxDynamicSharedMemorySize, (int)l->lds), "hipFuncSetAttribute");
@@ -795,7 +787,7 @@ int32_t batch_autotune(ltl_batch &b, int probe_steps, ltl_tuning_t *best) {
     probe.count = b.count; probe.method = b.method; probe.H = b.H; probe.W = b.W; probe.pitch = b.pitch;
     probe.rule = b.rule; probe.epi = b.epi; probe.rc = b.rc; probe.off = b.off; probe.arena_bytes = b.arena_bytes;
     probe.stream = b.stream; probe.owns_shared = false;
-    probe.dconst = b.dconst; probe.dqueue = b.dqueue; probe.dflag = b.dflag;
+    probe.dconst = b.dconst; probe.dflag = b.dflag;
     for (int a = 0; a < 2; ++a) {
         hipError_t e = hipMalloc(&probe.arena[a], b.arena_bytes);
         if (e != hipSuccess) {
@@ -807,7 +799,8 @@ int32_t batch_autotune(ltl_batch &b, int probe_steps, ltl_tuning_t *best) {
     (void)hipEventCreate(&ev0);
     (void)hipEventCreate(&ev1);
     const int Ts[] = {1, 2, 3, 4};
-    const int tiles[][2] = {{64, 64}, {64, 128}, {128, 128}, {128, 192}, {192, 128}, {128, 224}, {160, 160}, {192, 192}};
+    const int tiles[][2] = {{64, 64}, {64, 128}, {128, 128}, {128, 192}, {192, 128}, {128, 224}, {160, 160},
+                            {192, 192}, {160, 224}, {176, 224}};
     const int wavess[] = {0, 8};
     float best_ms = 1e30f;
     ltl_tuning_t best_t = b.tuning;
@@ -1008,8 +1001,8 @@ int32_t ltl_autotune(ltl_sim_t *sim, int32_t probe_steps, ltl_tuning_t *best) {
     (void)hipEventCreate(&ev0);
     (void)hipEventCreate(&ev1);
     const int Ts[] = {1, 2, 3, 4, 5, 6, 8};
-    const int tiles[][2] = {{64, 64}, {96, 96}, {128, 128}, {128, 192}, {160, 160}, {192, 128},
-                            {192, 224}, {128, 224}, {224, 224}, {64, 128}};
+    const int tiles[][2] = {{64, 64}, {96, 96}, {128, 128}, {128, 192}, {160, 160}, {192, 128}, {192, 192},
+                            {192, 224}, {128, 224}, {160, 224}, {176, 224}, {224, 224}, {64, 128}, {128, 96}};
     const int wavess[] = {0, 8, 16};  // 0: fewest waves that fit every step
     float best_ms = 1e30f;
     ltl_tuning_t best_t = s.tuning;
@@ -1140,7 +1133,6 @@ int32_t ltl_batch_create(ltl_batch_t **out, int32_t count, const int32_t *H, con
     hipError_t e;
     const size_t cbytes = batch_const_bytes();
     if ((e = hipMalloc(&b->dconst, cbytes)) != hipSuccess) { b->dconst = nullptr; return bail(hip_fail(e, "hipMalloc")); }
-    if ((e = hipMalloc(&b->dqueue, 4 * sizeof(uint32_t))) != hipSuccess) { b->dqueue = nullptr; return bail(hip_fail(e, "hipMalloc")); }
     if ((e = hipMalloc(&b->dflag, sizeof(uint32_t))) != hipSuccess) { b->dflag = nullptr; return bail(hip_fail(e, "hipMalloc")); }
     {
         std::vector<uint8_t> hc(cbytes, 0);
@@ -1151,7 +1143,6 @@ int32_t ltl_batch_create(ltl_batch_t **out, int32_t count, const int32_t *H, con
             return bail(hip_fail(e, "hipMemcpyAsync"));
         if ((e = hipStreamSynchronize(stream)) != hipSuccess) return bail(hip_fail(e, "hipStreamSynchronize"));
     }
-    if ((e = hipMemsetAsync(b->dqueue, 0, 4 * sizeof(uint32_t), stream)) != hipSuccess) return bail(hip_fail(e, "hipMemsetAsync"));
     if ((e = hipMemsetAsync(b->dflag, 0, sizeof(uint32_t), stream)) != hipSuccess) return bail(hip_fail(e, "hipMemsetAsync"));
     for (int i = 0; i < count; ++i)
         if ((e = launch_validate((const uint8_t *)init[i], H[i], W[i], init_pitch[i], b->rc[i].C, b->dflag, stream)) != hipSuccess)

@@ -225,24 +225,24 @@ inline void cat_lds_layout(int elem, int epi, int TH, int TW, int L, int *PS, in
     *lds_total = *lds_tile + (separate ? roundup(rows * *PA, 1024) : 0);
 }
 
-// Batched simulation: one persistent launch advances every instance by T steps. The
-// instances' grids sit at their own offsets of two arenas; the work list holds one entry per
-// (instance, tile), grouped by epilogue class and sorted by decreasing estimated cost within
-// a class; workgroups take entries from a device-wide counter per class.
+// Batched simulation: one launch advances every instance by T steps. The instances' grids sit
+// at their own offsets of two arenas; the work list holds one entry per (instance, tile),
+// sorted by decreasing estimated cost, and the launch has one workgroup per entry.
 struct BatchInst {
     CatParams p;           // launch parameters of the instance (src/dst of the launch's parity)
 };
 
 struct BatchItem {
     int32_t inst, tile;
+    int32_t epi;           // Epi of the instance's rule
+    int32_t pad;
 };
 
 struct BatchParams {
     const BatchInst *inst;     // per instance, for the arena this launch reads
-    const BatchItem *items;    // entries of epilogue class c at items[start[c] .. start[c] + count[c])
-    uint32_t *queue;           // [c] next entry of class c, [3] workgroups done; all 0 between launches
-    int32_t start[3], count[3];
-    int32_t slot;              // LDS byte offset of two dwords that pass the next entry to all waves
+    const BatchItem *items;    // workgroup k takes items[k]
+    int32_t nitems;
+    int32_t pad;
 };
 
 // Direct-stencil comparison method over the same work-list idea (one workgroup per entry).
