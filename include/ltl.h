@@ -145,11 +145,10 @@ const char *ltl_last_error(void);
 
 /* ----------------------------------------------------------------------------------
  * Batched simulation: `count` independent automata, each with its own size and rule,
- * advance together in one kernel launch per T steps (tuning.steps_per_launch). The CAT
- * methods use a persistent kernel over a work list with one entry per (instance, tile),
- * sorted by decreasing estimated cost and taken by workgroups from a device-wide counter;
- * the direct method launches one workgroup per entry. Multi-launch calls are replayed from a
- * cached hipGraph. Each instance follows exactly the semantics of a single simulation of its
+ * advance together in one kernel launch per T steps (tuning.steps_per_launch). The launch
+ * covers a work list with one entry per (instance, tile), sorted by decreasing estimated
+ * cost, one workgroup per entry (dispatched longest first; each XCD takes contiguous blocks
+ * of an instance's tiles). Multi-launch calls are replayed from a cached hipGraph. Each instance follows exactly the semantics of a single simulation of its
  * own (dead ghost halo around each grid; no interaction between instances), so instance i
  * after n batched steps equals ltl_create + ltl_step(n) of that grid and rule, cell for cell.
  *
@@ -164,8 +163,8 @@ const char *ltl_last_error(void);
  *  stream         HIP stream for all work of this handle.
  * Errors as ltl_create, for the first failing instance (its index is in ltl_last_error).
  * The tuning's tile shape is the largest tile; each instance uses that tile grid with its
- * tiles shrunk evenly to cover its grid with the least padding. The work-list counters live
- * in the handle, so two launches of one handle must not run concurrently (one stream). */
+ * tiles shrunk evenly to cover its grid with the least padding. All work of a handle runs on
+ * its one stream. */
 int32_t ltl_batch_buffer_bytes(int32_t count, const int32_t *H, const int32_t *W, size_t *bytes);
 int32_t ltl_batch_create(ltl_batch_t **out, int32_t count, const int32_t *H, const int32_t *W,
                          const ltl_rule_t *rules, int32_t method, void *arena_a, void *arena_b,
