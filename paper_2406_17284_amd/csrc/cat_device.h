@@ -659,12 +659,17 @@ __device__ __forceinline__ void issue_tile_load(const CatParams &p, int gi0, int
         // The load is issued from inline assembly: the compiler cannot see which LDS bytes an
         // LDS-DMA writes, so for its own builtin it would make every later LDS access wait for
         // all outstanding vector-memory operations. The caller waits (vmcnt(0) + barrier) before
-        // the buffer is read.
+        // the buffer is read. m0 (the DMA's LDS address) is a register the compiler reserves; no
+        // other code of these kernels uses it (checked in the generated ISA), so clobbering it
+        // here is safe and the corresponding warning is silenced for this statement only.
         const uint32_t lds_addr = (uint32_t)(uintptr_t)(buf + (c << 10));
+#pragma clang diagnostic push
+#pragma clang diagnostic ignored "-Winline-asm"
         asm volatile("s_mov_b32 m0, %0\n\tglobal_load_lds_dwordx4 %1, off"
                      :
                      : "s"(__builtin_amdgcn_readfirstlane(lds_addr)), "v"(g)
                      : "memory", "m0");
+#pragma clang diagnostic pop
     }
 }
 

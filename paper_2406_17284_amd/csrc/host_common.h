@@ -1,0 +1,47 @@
+// Host-side helpers shared by the single-grid (ltl_api.cpp) and batched (batch_api.cpp) parts
+// of the C ABI: error reporting, rule validation and constants, grid limits, element choice.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <string>
+
+#include "ltl.h"
+#include "ltl_internal.h"
+
+namespace ltl {
+namespace host {
+
+// Message of the last failing call on this thread (ltl_last_error).
+extern thread_local std::string g_err;
+
+int32_t fail(int32_t code, const std::string &msg);
+int32_t hip_fail(hipError_t e, const char *what);
+
+#define HIP_TRY(expr, what)                               \
+    do {                                                  \
+        hipError_t e_ = (expr);                           \
+        if (e_ != hipSuccess) return ltl::host::hip_fail(e_, what); \
+    } while (0)
+
+// Rule checks of ltl_create / ltl_batch_create (LTL_OK or an LTL_ERR_* code with a message).
+int32_t validate_rule(const ltl_rule_t *r, int method);
+// Largest count of the rule's neighbourhood (centre included).
+int max_count(const ltl_rule_t &r);
+// Epilogue flavour (Epi) of a rule.
+int epi_of(const ltl_rule_t &r);
+// Thresholds and SWAR constants of a rule for an epilogue flavour.
+RuleConsts make_consts(const ltl_rule_t &r, int epi);
+// Row pitch of the library layout: W rounded up to 64 bytes.
+int pitch_of(int W);
+// Whether an H x W grid exceeds the 2^31 - 1 bytes the kernels' 32-bit row offsets address.
+bool grid_too_large(int H, int W);
+// Largest dynamic LDS allocation of a workgroup on the current device.
+size_t max_lds_bytes();
+// Element type of the band products for a method, radius and neighbourhood code.
+int elem_of(int method, int R, int N);
+
+// Bytes of one band table (LTL_BAND_OPS operands x 64 lanes x 16 bytes).
+constexpr size_t kBandBytes = LTL_BAND_TABLE_INTS * sizeof(int32_t);
+
+}  // namespace host
+}  // namespace ltl
