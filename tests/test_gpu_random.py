@@ -1,0 +1,88 @@
+"""Randomized GPU parity: seeded cases drawn over every dimension at once (grid size, radius,
+method, neighbourhood, boundary, states, M, ranges, launch shape, graph use), each checked
+cell for cell against the oracle. A combination the library does not offer must be refused
+with its documented error code; a launch shape it cannot run with LTL_ERR_ARG."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2406_17284_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+N_CASES = 120
+
+
+@pytest.fixture(scope="module")
+def ltl():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2406_17284_amd import ltl as mod
+    mod.load()
+    oracle.set_threads(0)
+    return mod
+
+
+def draw_case(k):
+    rng = np.random.default_rng(10_000 + k)
+    method = str(rng.choice(["cat_i8", "cat_i8", "cat_i8", "cat_f16", "cat_f8", "direct"]))
+    cross = rng.random() < 0.25
+    periodic = rng.random() < 0.3
+    r = int(rng.integers(1, 33 if method in ("cat_i8", "direct") else 17))
+    if method == "cat_f8":
+        r = int(rng.integers(1, 8))
+    if cross and method == "cat_i8":
+        r = min(r, 16)
+    nmax = 4 * r + 1 if cross else (2 * r + 1) ** 2
+    C = int(rng.choice([0, 0, 2, 3, 6]))
+    M = int(rng.integers(0, 2))
+    s = sorted(int(x) for x in rng.integers(0, nmax + 1, size=2))
+    b = sorted(int(x) for x in rng.integers(0, nmax + 1, size=2))
+    rule = inputs.Rule(r, C, M, s[0], s[1], b[0], b[1], "N" if cross else "M")
+    H = int(rng.integers(1, 160))
+    W = 16 * int(rng.integers(1, 12)) if periodic else int(rng.integers(1, 200))
+    steps = int(rng.integers(1, 7))
+    tuning = None
+    if method != "direct" and rng.random() < 0.7:
+        tuning = dict(steps_per_launch=int(rng.integers(1, 6)), tile_rows=16 * int(rng.integers(1, 12)),
+                      tile_cols=32 * int(rng.integers(1, 8)), waves=int(rng.choice([0, 0, 8, 16])),
+                      use_graph=int(rng.integers(0, 2)))
+    return method, rule, periodic, H, W, steps, tuning
+
+
+def expected_refusal(ltl, method, rule):
+    if rule.N == "N" and method in ("cat_f16", "cat_f8"):
+        return ltl.LTL_ERR_UNSUPPORTED
+    if method == "cat_f16" and rule.R > 16:
+        return ltl.LTL_ERR_UNSUPPORTED
+    return None
+
+
+@pytest.mark.parametrize("k", range(N_CASES))
+def test_random_case(ltl, k):
+    method, rule, periodic, H, W, steps, tuning = draw_case(k)
+    g0 = (inputs.state_grid(H, W, rule.C, seed=k) if rule.C >= 3 else inputs.bernoulli_grid(H, W, 0.5, seed=k))
+    what = f"case {k}: {method} {rule.text()} {'torus' if periodic else 'dead'} {H}x{W} steps={steps} tuning={tuning}"
+    code = expected_refusal(ltl, method, rule)
+    if code is not None:
+        with pytest.raises(ltl.LtlError) as e:
+            ltl.Simulation(torch.from_numpy(g0).cuda(), rule, method)
+        assert e.value.code == code, what
+        return
+    sim = ltl.Simulation(torch.from_numpy(g0).cuda(), rule, method, boundary="periodic" if periodic else "dead")
+    if tuning is not None:
+        try:
+            sim.set_tuning(**tuning)
+        except ltl.LtlError as e:
+            assert e.code == ltl.LTL_ERR_ARG, what
+            tuning = None
+    sim.step(steps)
+    got = sim.read().cpu().numpy()
+    assert not sim.current_padded()[:, W:].any(), what
+    sim.close()
+    ref = oracle.run(g0, rule, steps, periodic=periodic)
+    if not np.array_equal(got, ref):
+        bad = np.argwhere(got != ref)
+        raise AssertionError(f"{what}: {len(bad)} cells differ, first {bad[:5].tolist()}")
