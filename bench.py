@@ -125,6 +125,26 @@ def bench_batch(args, ltl, inputs, torch):
     return res
 
 
+def bench_decay(args, ltl, inputs, torch):
+    """The multi-state workload: R16 C8 M0 S300..500 B330..420, 32768^2, 20 steps per bench step
+    (the CAT step time does not depend on the grid's contents)."""
+    w = inputs.WORKLOADS["decay32768"]
+    g = inputs.bernoulli_grid_torch(w.H, w.W, w.p, w.seed, device="cuda")
+    res = {"workload": "decay32768: R16 C8 M0 S300..500 B330..420 N_M, 32768x32768, Bernoulli(0.5), 20 steps"}
+    for method in ("cat_i8", "direct"):
+        s = ltl.Simulation(g, w.rule, method)
+        if method == "cat_i8":
+            s.autotune(probe_steps=4)
+            res["tuning"] = s.tuning()
+        s.step(w.steps)
+        secs, _ = timed_runs(s, w.steps, 1 if method == "direct" else max(1, min(args.steps, 3)), torch)
+        runs = 1 if method == "direct" else max(1, min(args.steps, 3))
+        res[method] = w.H * w.W * w.steps * runs / secs
+        s.close()
+    res["unit"] = "cell-updates/s"
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -135,6 +155,7 @@ def main():
     ap.add_argument("--sweep-rmax", type=int, default=16, help="largest radius of the sweep (int8 and direct reach 32)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the 512-instance batched workload")
+    ap.add_argument("--decay", action="store_true", help="also time the C=8 R16 decay workload on 32768^2")
     ap.add_argument("--batch-tuning", type=str, default=BATCH_TUNING, help="T,tile_rows,tile_cols,waves of the batch")
     ap.add_argument("--autotune", action="store_true", help="pick the launch shape with ltl_autotune")
     ap.add_argument("--tuning", type=str, default=DEFAULT_TUNING,
@@ -291,6 +312,9 @@ def main():
 
     if not args.no_batch:
         out["batched"] = bench_batch(args, ltl, inputs, torch)
+
+    if args.decay:
+        out["decay"] = bench_decay(args, ltl, inputs, torch)
 
     if not args.no_cpu:
         import oracle
