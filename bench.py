@@ -43,6 +43,15 @@ def kernel_hash() -> str:
     return h.hexdigest()
 
 
+SHAPE_KEYS = ("steps_per_launch", "tile_rows", "tile_cols", "waves", "persistent")
+
+
+def parse_tuning(text):
+    """'T,tile_rows,tile_cols,waves[,persistent]' -> keyword arguments of set_tuning."""
+    vals = [int(x) for x in text.split(",")]
+    return dict(zip(SHAPE_KEYS, vals))
+
+
 def recorded_traffic(tuning):
     """HBM bytes per launch from the committed FETCH_SIZE / WRITE_SIZE counter record, if it was
     taken on this kernel source and launch shape; else None."""
@@ -51,7 +60,7 @@ def recorded_traffic(tuning):
             rec = json.load(f)
     except (OSError, ValueError):
         return None
-    shape = [tuning[k] for k in ("steps_per_launch", "tile_rows", "tile_cols", "waves")]
+    shape = [tuning[k] for k in SHAPE_KEYS]
     if rec.get("kernel_sha256") != kernel_hash() or rec.get("tuning") != shape:
         return None
     return rec["hbm_bytes_per_launch"]
@@ -159,7 +168,7 @@ def main():
     ap.add_argument("--batch-tuning", type=str, default=BATCH_TUNING, help="T,tile_rows,tile_cols,waves of the batch")
     ap.add_argument("--autotune", action="store_true", help="pick the launch shape with ltl_autotune")
     ap.add_argument("--tuning", type=str, default=DEFAULT_TUNING,
-                    help="T,tile_rows,tile_cols,waves (default: the autotuner's pick on MI355X)")
+                    help="T,tile_rows,tile_cols,waves[,persistent] (default: the autotuner's pick on MI355X)")
     ap.add_argument("--calib-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (HBM counter calibration) and exit")
     args = ap.parse_args()
@@ -194,8 +203,7 @@ def main():
     if args.autotune:
         sim.autotune(probe_steps=20)
     else:
-        T, th, tw, wv = (int(x) for x in args.tuning.split(","))
-        sim.set_tuning(steps_per_launch=T, tile_rows=th, tile_cols=tw, waves=wv)
+        sim.set_tuning(**parse_tuning(args.tuning))
     tuning = sim.tuning()
     for _ in range(args.warmup):
         sim.step(w.steps)
@@ -217,7 +225,7 @@ def main():
 
     # ---- parity at the workload's own length: CAT vs direct on the GPU (and the oracle below)
     a = ltl.Simulation(g0, w.rule, "cat_i8")
-    a.set_tuning(**{k: tuning[k] for k in ("steps_per_launch", "tile_rows", "tile_cols", "waves")})
+    a.set_tuning(**{k: tuning[k] for k in SHAPE_KEYS})
     a.step(w.steps)
     b = ltl.Simulation(g0, w.rule, "direct")
     b.step(w.steps)
@@ -296,12 +304,12 @@ def main():
 
     # ---- the same workload on a torus (the paper's experimental boundary condition)
     sp = ltl.Simulation(g0, w.rule, "cat_i8", boundary="periodic")
-    sp.set_tuning(**{k: tuning[k] for k in ("steps_per_launch", "tile_rows", "tile_cols", "waves")})
+    sp.set_tuning(**{k: tuning[k] for k in SHAPE_KEYS})
     sp.step(w.steps)
     psecs, _ = timed_runs(sp, w.steps, max(1, min(args.steps, 5)), torch)
     pd = ltl.Simulation(g0, w.rule, "direct", boundary="periodic")
     pc = ltl.Simulation(g0, w.rule, "cat_i8", boundary="periodic")
-    pc.set_tuning(**{k: tuning[k] for k in ("steps_per_launch", "tile_rows", "tile_cols", "waves")})
+    pc.set_tuning(**{k: tuning[k] for k in SHAPE_KEYS})
     pd.step(w.steps)
     pc.step(w.steps)
     out["periodic"] = {"workload": "bosco4096 on a torus (periodic boundary)",

@@ -74,6 +74,10 @@ typedef struct {
     int32_t tile_cols;        /* output columns per workgroup: multiple of 32, 32..512 */
     int32_t waves;            /* 64-lane waves per workgroup: 1..16 */
     int32_t use_graph;        /* 1: replay multi-launch loops from a cached hipGraph */
+    int32_t persistent;       /* CAT methods, single grid: 1 = persistent workgroups (about one per
+                                 CU slot) that each walk a contiguous run of tiles, loading tile
+                                 i+1 into a second LDS buffer while tile i computes (pays off when
+                                 tiles stream from HBM); 0 = one workgroup per tile. Batches take 0. */
 } ltl_tuning_t;
 
 typedef enum {

@@ -165,6 +165,7 @@ int32_t batch_check_tuning(const ltl_batch &b, const ltl_tuning_t &t) {
     if (t.steps_per_launch < 1 || t.steps_per_launch > 64) return fail(LTL_ERR_ARG, "steps_per_launch must be in 1..64");
     if (t.tile_rows < 16 || t.tile_rows > 512 || t.tile_rows % 16) return fail(LTL_ERR_ARG, "tile_rows must be a multiple of 16 in 16..512");
     if (t.tile_cols < 32 || t.tile_cols > 512 || t.tile_cols % 32) return fail(LTL_ERR_ARG, "tile_cols must be a multiple of 32 in 32..512");
+    if (t.persistent) return fail(LTL_ERR_ARG, "batches have no persistent form (persistent must be 0)");
     if (b.method == LTL_DIRECT) {
         if (t.steps_per_launch != 1) return fail(LTL_ERR_ARG, "the direct method takes one step per launch");
         return LTL_OK;

@@ -673,31 +673,28 @@ __device__ __forceinline__ void issue_tile_load(const CatParams &p, int gi0, int
     }
 }
 
-// One tile: load the window with direct LDS loads, derive the alive map in the element
-// encoding, then T steps in place (the last one writes the output grid). Ends without a
-// barrier: a caller that reuses the LDS for another tile synchronizes first.
-template <int ELEM, int EPI>
-__device__ __forceinline__ void cat_tile(const CatParams &p, int tile, uint8_t *lds, int tid, int lane, int wave,
-                                         int nwaves, const Codec &cd) {
-    const int gi0 = (tile / p.ntx) * p.TH;
-    const int gj0 = (tile % p.ntx) * p.TW;
-
-    uint8_t *Qt = lds;                 // loaded window: states, one byte per cell
-    uint8_t *At = lds + p.a_tile;      // alive map in the element encoding (== Qt when shared)
-    issue_tile_load(p, gi0, gj0, Qt, wave, nwaves, lane, 1.0f / (float)p.PS);
+// Band operands of a launch, per lane (the fp8 table holds 0/1 bytes and is encoded here).
+template <int ELEM>
+__device__ __forceinline__ Bands load_bands(const CatParams &p, int lane, const Codec &cd) {
     Bands bd;
     const v4i *bt = reinterpret_cast<const v4i *>(p.bands);
 #pragma unroll
     for (int k = 0; k < ElemT<ELEM>::NOPS; ++k) {
         bd.op[k] = bt[k * 64 + lane];
-        if constexpr (ELEM == ELEM_F8) {   // the table holds 0/1 bytes
+        if constexpr (ELEM == ELEM_F8) {
             bd.op[k][0] = (int32_t)enc8((uint32_t)bd.op[k][0], cd);
             bd.op[k][1] = (int32_t)enc8((uint32_t)bd.op[k][1], cd);
         }
     }
-    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-    __syncthreads();
+    return bd;
+}
 
+// The window of the tile at (gi0, gj0) is in LDS at Qt (visible to every wave): derive the
+// alive map in the element encoding at At, then run T steps in place (the last one writes the
+// output grid). Ends without a barrier.
+template <int ELEM, int EPI>
+__device__ __forceinline__ void tile_steps(const CatParams &p, int gi0, int gj0, uint8_t *Qt, uint8_t *At, int tid,
+                                           int lane, int wave, int nwaves, const Bands &bd, const Codec &cd) {
     // alive map from the loaded states (int8 without decay reads the states directly)
     if constexpr (!(kIsI8<ELEM> && EPI != EPI_DECAY)) {
         const int W2 = p.TW + 2 * p.L;          // window columns (the PS - W2 pad is never read)
@@ -731,6 +728,22 @@ __device__ __forceinline__ void cat_tile(const CatParams &p, int tile, uint8_t *
         cat_steps<ELEM, EPI, false>(p, Qt, At, gi0, gj0, wave, lane, bd, cd);
     else
         cat_steps<ELEM, EPI, true>(p, Qt, At, gi0, gj0, wave, lane, bd, cd);
+}
+
+// One tile: load the window with direct LDS loads, then the alive map and T steps in place.
+// Ends without a barrier: a caller that reuses the LDS for another tile synchronizes first.
+template <int ELEM, int EPI>
+__device__ __forceinline__ void cat_tile(const CatParams &p, int tile, uint8_t *lds, int tid, int lane, int wave,
+                                         int nwaves, const Codec &cd) {
+    const int gi0 = (tile / p.ntx) * p.TH;
+    const int gj0 = (tile % p.ntx) * p.TW;
+    uint8_t *Qt = lds;                 // loaded window: states, one byte per cell
+    uint8_t *At = lds + p.a_tile;      // alive map in the element encoding (== Qt when shared)
+    issue_tile_load(p, gi0, gj0, Qt, wave, nwaves, lane, 1.0f / (float)p.PS);
+    const Bands bd = load_bands<ELEM>(p, lane, cd);
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+    tile_steps<ELEM, EPI>(p, gi0, gj0, Qt, At, tid, lane, wave, nwaves, bd, cd);
 }
 
 }  // namespace ltl

@@ -1,5 +1,7 @@
 // Single-grid CAT step kernel and its launchers; the per-tile device code (method, operand
 // layouts, precision variants, temporal blocking) is in cat_device.h.
+#include <algorithm>
+
 #include "cat_device.h"
 
 namespace ltl {
@@ -24,29 +26,79 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) c
     const Codec cd = make_codec();
     cat_tile<ELEM, EPI>(p, tile, lds, tid, lane, wave, nwaves, cd);
 }
-size_t cat_lds_bytes(const CatParams &p, int elem, int epi) {
+// Streaming form, for grids larger than the caches: one persistent workgroup per CU slot walks
+// a static sequence of tiles with two LDS buffers, so the next tile's direct loads are in
+// flight while the current tile computes. Workgroup b runs on XCD b mod 8 and takes every gx-th
+// tile (gx = workgroups per XCD) of that XCD's contiguous block of tiles, so the tiles one XCD
+// processes at a time are neighbours and share its L2.
+template <int ELEM, int EPI>
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2))) cat_persist(CatParams p) {
+    extern __shared__ __attribute__((aligned(1024))) uint8_t lds[];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int nwaves = blockDim.x >> 6;
+    const int ntiles = p.ntx * p.nty;
+    const int gx = gridDim.x >> 3;                 // the grid is a multiple of 8 workgroups
+    const int chunk = (ntiles + 7) >> 3;
+    const int t_hi = min(ntiles, ((int)blockIdx.x & 7) * chunk + chunk);
+    int tile = ((int)blockIdx.x & 7) * chunk + ((int)blockIdx.x >> 3);
+    const float inv_ps = 1.0f / (float)p.PS;
+    const Codec cd = make_codec();
+    const Bands bd = load_bands<ELEM>(p, lane, cd);
+    const uint32_t bufsz = (uint32_t)p.lds_total;  // one buffer: state tile (+ alive tile)
+    if (tile < t_hi)
+        issue_tile_load(p, (tile / p.ntx) * p.TH, (tile % p.ntx) * p.TW, lds, wave, nwaves, lane, inv_ps);
+    uint32_t buf = 0;
+    while (tile < t_hi) {
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        __syncthreads();   // this tile's window landed; every wave is done with the other buffer
+        const int next = tile + gx;
+        if (next < t_hi)
+            issue_tile_load(p, (next / p.ntx) * p.TH, (next % p.ntx) * p.TW, lds + (buf ^ bufsz), wave, nwaves,
+                            lane, inv_ps);
+        uint8_t *Qt = lds + buf;
+        tile_steps<ELEM, EPI>(p, (tile / p.ntx) * p.TH, (tile % p.ntx) * p.TW, Qt, Qt + p.a_tile, tid, lane, wave,
+                              nwaves, bd, cd);
+        tile = next;
+        buf ^= bufsz;
+    }
+}
+
+size_t cat_lds_bytes(const CatParams &p, int elem, int epi, int persistent) {
     (void)elem;
     (void)epi;
-    return (size_t)p.lds_total;
+    return (size_t)p.lds_total * (persistent ? 2 : 1);
 }
 
-static const void *cat_func(int elem, int epi) {
-#define CAT_F(E) \
-    (epi == EPI_BYTE ? (const void *)&cat_step<E, EPI_BYTE> : epi == EPI_HALF ? (const void *)&cat_step<E, EPI_HALF> \
-                                                                             : (const void *)&cat_step<E, EPI_DECAY>)
-    if (elem == ELEM_F16) return CAT_F(ELEM_F16);
-    if (elem == ELEM_F8) return CAT_F(ELEM_F8);
-    if (elem == ELEM_I8X)   // cross counts are at most 4r + 1 <= 65: no 16-bit epilogue
-        return epi == EPI_DECAY ? (const void *)&cat_step<ELEM_I8X, EPI_DECAY> : (const void *)&cat_step<ELEM_I8X, EPI_BYTE>;
-    if (elem == ELEM_I8W)   // radii 17..32 always have counts > 126: no 8-bit epilogue
-        return epi == EPI_DECAY ? (const void *)&cat_step<ELEM_I8W, EPI_DECAY> : (const void *)&cat_step<ELEM_I8W, EPI_HALF>;
-    return CAT_F(ELEM_I8);
-#undef CAT_F
+// Kernel symbol of an (element, epilogue) pair; KERNEL is cat_step or cat_persist.
+#define CAT_PICK(KERNEL)                                                                                           \
+    static const void *KERNEL##_func(int elem, int epi) {                                                          \
+        const bool dec = (epi == EPI_DECAY);                                                                       \
+        if (elem == ELEM_F16)                                                                                      \
+            return dec ? (const void *)&KERNEL<ELEM_F16, EPI_DECAY>                                                \
+                       : epi == EPI_HALF ? (const void *)&KERNEL<ELEM_F16, EPI_HALF> : (const void *)&KERNEL<ELEM_F16, EPI_BYTE>; \
+        if (elem == ELEM_F8)                                                                                       \
+            return dec ? (const void *)&KERNEL<ELEM_F8, EPI_DECAY>                                                 \
+                       : epi == EPI_HALF ? (const void *)&KERNEL<ELEM_F8, EPI_HALF> : (const void *)&KERNEL<ELEM_F8, EPI_BYTE>; \
+        if (elem == ELEM_I8X)   /* cross counts are at most 4r + 1 <= 65: no 16-bit epilogue */                   \
+            return dec ? (const void *)&KERNEL<ELEM_I8X, EPI_DECAY> : (const void *)&KERNEL<ELEM_I8X, EPI_BYTE>;   \
+        if (elem == ELEM_I8W)   /* radii 17..32 always have counts > 126: no 8-bit epilogue */                     \
+            return dec ? (const void *)&KERNEL<ELEM_I8W, EPI_DECAY> : (const void *)&KERNEL<ELEM_I8W, EPI_HALF>;   \
+        return dec ? (const void *)&KERNEL<ELEM_I8, EPI_DECAY>                                                     \
+                   : epi == EPI_HALF ? (const void *)&KERNEL<ELEM_I8, EPI_HALF> : (const void *)&KERNEL<ELEM_I8, EPI_BYTE>; \
+    }
+CAT_PICK(cat_step)
+CAT_PICK(cat_persist)
+#undef CAT_PICK
+
+static const void *cat_func(int elem, int epi, int persistent) {
+    return persistent ? cat_persist_func(elem, epi) : cat_step_func(elem, epi);
 }
 
-int cat_occupancy(const CatParams &p, int elem, int epi, int waves) {
-    const void *f = cat_func(elem, epi);
-    size_t lds = cat_lds_bytes(p, elem, epi);
+int cat_occupancy(const CatParams &p, int elem, int epi, int waves, int persistent) {
+    const void *f = cat_func(elem, epi, persistent);
+    size_t lds = cat_lds_bytes(p, elem, epi, persistent);
     if (lds > 65536 && hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
         return 0;
     int nb = 0;
@@ -54,23 +106,28 @@ int cat_occupancy(const CatParams &p, int elem, int epi, int waves) {
     return nb;
 }
 
-KernelLaunch cat_launch_shape(const CatParams &p, int elem, int epi, int waves) {
-    KernelLaunch k;
-    k.func = cat_func(elem, epi);
-    k.lds = cat_lds_bytes(p, elem, epi);
-    k.grid = dim3((unsigned)roundup(p.ntx * p.nty, 8), 1, 1);
-    k.block = dim3(64 * waves, 1, 1);
-    return k;
+static int device_cus() {
+    int dev = 0, x = 0;
+    if (hipGetDevice(&dev) == hipSuccess && hipDeviceGetAttribute(&x, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+        x > 0)
+        return x;
+    return 8;
 }
 
-hipError_t launch_cat(const CatParams &p, int elem, int epi, int waves, hipStream_t s) {
-    KernelLaunch k = cat_launch_shape(p, elem, epi, waves);
-    if (k.lds > 65536) {
-        hipError_t e = hipFuncSetAttribute(k.func, hipFuncAttributeMaxDynamicSharedMemorySize, (int)k.lds);
-        if (e != hipSuccess) return e;
+KernelLaunch cat_launch_shape(const CatParams &p, int elem, int epi, int waves, int persistent) {
+    KernelLaunch k;
+    k.func = cat_func(elem, epi, persistent);
+    k.lds = cat_lds_bytes(p, elem, epi, persistent);
+    const int ntiles = p.ntx * p.nty;
+    if (persistent) {
+        // resident workgroups, 8 x (per XCD), no more per XCD than that XCD has tiles
+        const int per_xcd = std::max(1, std::min((ntiles + 7) / 8, std::max(1, cat_occupancy(p, elem, epi, waves, 1)) * device_cus() / 8));
+        k.grid = dim3((unsigned)(8 * per_xcd), 1, 1);
+    } else {
+        k.grid = dim3((unsigned)roundup(ntiles, 8), 1, 1);
     }
-    void *args[] = {(void *)&p};
-    return hipLaunchKernel(k.func, k.grid, k.block, args, k.lds, s);
+    k.block = dim3(64 * waves, 1, 1);
+    return k;
 }
 
 }  // namespace ltl

@@ -179,6 +179,7 @@ ltl_tuning_t default_tuning(const ltl_sim &s) {
                                           t.waves))
         t.waves *= 2;
     t.use_graph = 1;
+    t.persistent = 0;
     return t;
 }
 
@@ -230,14 +231,16 @@ int32_t check_tuning(const ltl_sim &s, const ltl_tuning_t &t) {
     if (t.waves < 1 || t.waves > (s.method == LTL_DIRECT ? 16 : 8)) return fail(LTL_ERR_ARG, "waves must be in 1..8");
     if (s.method != LTL_DIRECT) {
         CatParams p = cat_params(s, t, t.steps_per_launch, nullptr, nullptr);
-        size_t lds = cat_lds_bytes(p, elem_of(s.method, s.rule.R, s.rule.N), s.epi);
+        size_t lds = cat_lds_bytes(p, elem_of(s.method, s.rule.R, s.rule.N), s.epi, t.persistent);
         if (lds > max_lds_bytes()) return fail(LTL_ERR_ARG, "launch shape needs " + std::to_string(lds) + " bytes of LDS");
-        if (s.dconst && cat_occupancy(p, elem_of(s.method, s.rule.R, s.rule.N), s.epi, t.waves) < 1)
+        if (s.dconst && cat_occupancy(p, elem_of(s.method, s.rule.R, s.rule.N), s.epi, t.waves, t.persistent) < 1)
             return fail(LTL_ERR_ARG, "launch shape does not fit on a compute unit (registers or LDS)");
         if (!cat_shape_fits(elem_of(s.method, s.rule.R, s.rule.N), s.rule.R, t.steps_per_launch, t.tile_rows, t.tile_cols, t.waves))
             return fail(LTL_ERR_ARG, "launch shape has more strip segments than waves in some step");
     } else if (t.steps_per_launch != 1) {
         return fail(LTL_ERR_ARG, "the direct method takes one step per launch");
+    } else if (t.persistent) {
+        return fail(LTL_ERR_ARG, "the direct method has no persistent form");
     }
     return LTL_OK;
 }
@@ -261,7 +264,7 @@ PlannedLaunch plan(const ltl_sim &s, int steps_in_launch, int from) {
         pl.k = direct_launch_shape(pl.dp);
     } else {
         pl.cp = cat_params(s, s.tuning, steps_in_launch, src, dst);
-        pl.k = cat_launch_shape(pl.cp, elem_of(s.method, s.rule.R, s.rule.N), s.epi, s.tuning.waves);
+        pl.k = cat_launch_shape(pl.cp, elem_of(s.method, s.rule.R, s.rule.N), s.epi, s.tuning.waves, s.tuning.persistent);
     }
     return pl;
 }
@@ -479,6 +482,7 @@ int32_t ltl_set_tuning(ltl_sim_t *sim, const ltl_tuning_t *tuning) {
         while (t.waves < 8 && s_fits(*sim, t)) t.waves *= 2;
     }
     t.use_graph = t.use_graph ? 1 : 0;
+    t.persistent = t.persistent ? 1 : 0;
     int32_t rc = check_tuning(*sim, t);
     if (rc != LTL_OK) return rc;
     clear_graphs(*sim);
@@ -523,8 +527,10 @@ int32_t ltl_autotune(ltl_sim_t *sim, int32_t probe_steps, ltl_tuning_t *best) {
         if (T > probe_steps) continue;
         for (auto &tl : tiles) {
             for (int wv : wavess) {
+              for (int pers = 0; pers < (s.method == LTL_DIRECT ? 1 : 2); ++pers) {
                 ltl_tuning_t t;
                 t.steps_per_launch = T; t.tile_rows = tl[0]; t.tile_cols = tl[1]; t.waves = wv; t.use_graph = 1;
+                t.persistent = pers;
                 if (wv == 0) {
                     t.waves = 1;
                     while (t.waves < 8 && s_fits(s, t)) t.waves *= 2;
@@ -543,6 +549,7 @@ int32_t ltl_autotune(ltl_sim_t *sim, int32_t probe_steps, ltl_tuning_t *best) {
                 float ms = 0;
                 (void)hipEventElapsedTime(&ms, ev0, ev1);
                 if (ms < best_ms) { best_ms = ms; best_t = t; }
+              }
             }
         }
     }

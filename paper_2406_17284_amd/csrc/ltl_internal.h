@@ -260,7 +260,6 @@ struct DirectBatchParams {
 };
 
 // Launchers (return the HIP status of the launch).
-hipError_t launch_cat(const CatParams &p, int elem, int epi, int waves, hipStream_t s);
 hipError_t launch_direct(const DirectParams &p, hipStream_t s);
 hipError_t launch_validate(const uint8_t *src, int H, int W, size_t pitch, int states,
                            uint32_t *flag, hipStream_t s);
@@ -271,11 +270,12 @@ struct KernelLaunch {
     dim3 grid, block;
     size_t lds;
 };
-KernelLaunch cat_launch_shape(const CatParams &p, int elem, int epi, int waves);
+// persistent = 1: the persistent double-buffered form (one workgroup per CU slot walking tiles).
+KernelLaunch cat_launch_shape(const CatParams &p, int elem, int epi, int waves, int persistent);
 // Resident workgroups of the CAT kernel per compute unit for this shape (0 if it cannot run).
-int cat_occupancy(const CatParams &p, int elem, int epi, int waves);
+int cat_occupancy(const CatParams &p, int elem, int epi, int waves, int persistent);
 KernelLaunch direct_launch_shape(const DirectParams &p);
-size_t cat_lds_bytes(const CatParams &p, int elem, int epi);
+size_t cat_lds_bytes(const CatParams &p, int elem, int epi, int persistent);
 // Batched launches. cat_batch_func: the persistent kernel of an element type (launched with
 // `grid` workgroups of 64 * waves threads and `lds` bytes of dynamic LDS).
 const void *cat_batch_func(int elem);

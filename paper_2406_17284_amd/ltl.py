@@ -46,7 +46,8 @@ class ltl_rule_t(ctypes.Structure):
 
 
 class ltl_tuning_t(ctypes.Structure):
-    _fields_ = [(n, ctypes.c_int32) for n in ("steps_per_launch", "tile_rows", "tile_cols", "waves", "use_graph")]
+    _fields_ = [(n, ctypes.c_int32) for n in ("steps_per_launch", "tile_rows", "tile_cols", "waves", "use_graph",
+                                                   "persistent")]
 
     def as_dict(self):
         return {n: int(getattr(self, n)) for n, _ in self._fields_}
@@ -178,8 +179,9 @@ def ltl_get_tuning(sim: int) -> ltl_tuning_t:
     return t
 
 
-def ltl_set_tuning(sim: int, steps_per_launch=0, tile_rows=0, tile_cols=0, waves=0, use_graph=1) -> None:
-    t = ltl_tuning_t(steps_per_launch, tile_rows, tile_cols, waves, use_graph)
+def ltl_set_tuning(sim: int, steps_per_launch=0, tile_rows=0, tile_cols=0, waves=0, use_graph=1,
+                   persistent=0) -> None:
+    t = ltl_tuning_t(steps_per_launch, tile_rows, tile_cols, waves, use_graph, persistent)
     _check(load().ltl_set_tuning(ctypes.c_void_p(sim), ctypes.byref(t)))
 
 
@@ -244,8 +246,9 @@ def ltl_batch_get_tuning(batch: int) -> ltl_tuning_t:
     return t
 
 
-def ltl_batch_set_tuning(batch: int, steps_per_launch=0, tile_rows=0, tile_cols=0, waves=0, use_graph=1) -> None:
-    t = ltl_tuning_t(steps_per_launch, tile_rows, tile_cols, waves, use_graph)
+def ltl_batch_set_tuning(batch: int, steps_per_launch=0, tile_rows=0, tile_cols=0, waves=0, use_graph=1,
+                   persistent=0) -> None:
+    t = ltl_tuning_t(steps_per_launch, tile_rows, tile_cols, waves, use_graph, persistent)
     _check(load().ltl_batch_set_tuning(ctypes.c_void_p(batch), ctypes.byref(t)))
 
 

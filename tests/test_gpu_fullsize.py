@@ -142,3 +142,27 @@ def test_largest_grid(ltl):
     d.step(2)
     assert torch.equal(d.read(), state)
     d.close()
+
+
+@pytest.mark.parametrize("tuning", [dict(steps_per_launch=1, tile_rows=160, tile_cols=224, waves=8),
+                                    dict(steps_per_launch=4, tile_rows=160, tile_cols=224, waves=8),
+                                    dict(steps_per_launch=2, tile_rows=64, tile_cols=128, waves=0)],
+                         ids=lambda t: f"T{t['steps_per_launch']}_{t['tile_rows']}x{t['tile_cols']}")
+def test_persistent_form_16384(ltl, sweep_grid, tuning):
+    """At 16384^2 the persistent form walks hundreds of tiles per XCD: windows against the
+    oracle, and the whole grid equal to the one-workgroup-per-tile form."""
+    rule = inputs.BOSCO_M1
+    side = SWEEP_SIDE
+    pers = ltl.Simulation(sweep_grid, rule, "cat_i8", tuning=dict(tuning, persistent=1))
+    plain = ltl.Simulation(sweep_grid, rule, "cat_i8", tuning=dict(tuning, persistent=0))
+    pers.step(EARLY)
+    plain.step(EARLY)
+    state = pers.read()
+    assert cone_checks(state, side, side, rule, EARLY, seed=3) >= 4
+    assert torch.equal(state, plain.read())
+    pers.step(SWEEP_STEPS - EARLY)
+    plain.step(SWEEP_STEPS - EARLY)
+    assert torch.equal(pers.read(), plain.read())
+    assert not pers.current_padded()[:, side:].any()
+    pers.close()
+    plain.close()

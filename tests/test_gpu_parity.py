@@ -409,3 +409,79 @@ def test_cross_refusals_and_direct_range(ltl):
     # the direct stencil covers the cross up to r = 32
     rule = inputs.Rule(24, 0, 1, 25, 60, 30, 45, "N")
     run_and_compare_each_step(ltl, inputs.bernoulli_grid(90, 140, 0.5, seed=24), rule, "direct", 3)
+
+
+# ------------------------------------------------------------------ persistent (double-buffered) form
+# The persistent form launches about one 8-wave workgroup per compute unit; with small tiles on
+# a grid of ~1000 tiles every workgroup walks several tiles, so the double-buffered hand-over
+# (load of tile i+1 while tile i computes) is exercised at every position of the walk.
+PERSIST_GRID = (1000, 1008)     # ragged against 32-row / 32-column tiles; W % 16 == 0 for the torus
+
+
+@pytest.mark.parametrize("boundary", ["dead", "periodic"])
+@pytest.mark.parametrize("T", [1, 3])
+@pytest.mark.parametrize("method", ["cat_i8", "cat_f16", "cat_f8"])
+def test_persistent_many_tiles(ltl, method, T, boundary):
+    rule = inputs.BOSCO_M1
+    g0 = inputs.bernoulli_grid(*PERSIST_GRID, 0.5, seed=41 + T)
+    tuning = dict(steps_per_launch=T, tile_rows=32, tile_cols=32, waves=8, persistent=1)
+    sim = ltl.Simulation(gpu_grid(g0), rule, method, tuning=tuning, boundary=boundary)
+    assert sim.tuning()["persistent"] == 1
+    for n in (3, 4):
+        sim.step(n)
+    got = sim.read().cpu().numpy()
+    assert not sim.current_padded()[:, g0.shape[1]:].any()
+    sim.close()
+    ref = oracle.run(g0, rule, 7, periodic=(boundary == "periodic"))
+    if not np.array_equal(got, ref):
+        bad = np.argwhere(got != ref)
+        raise AssertionError(f"persistent {method} T={T} {boundary}: {len(bad)} cells differ, first {bad[:5].tolist()}")
+
+
+PERSIST_RULES = [inputs.Rule(3, 5, 0, 9, 20, 10, 14),            # decay states
+                 inputs.Rule(24, 0, 0, 600, 1100, 650, 900),     # wide radius
+                 inputs.Rule(5, 0, 1, 5, 12, 6, 9, "N"),         # cross neighbourhood
+                 inputs.Rule(1, 0, 1, 3, 4, 3, 3)]               # Life: the smallest window
+
+
+@pytest.mark.parametrize("rule", PERSIST_RULES, ids=lambda r: r.text())
+@pytest.mark.parametrize("T", [1, 2])
+def test_persistent_rules(ltl, rule, T):
+    g0 = (inputs.state_grid(700, 704, rule.C, seed=rule.R) if rule.C >= 3
+          else inputs.bernoulli_grid(700, 704, 0.5, seed=rule.R))
+    tuning = dict(steps_per_launch=T, tile_rows=32, tile_cols=32, waves=8, persistent=1)
+    run_and_compare(ltl, g0, rule, "cat_i8", 5, tuning=tuning, chunks=[2, 3])
+
+
+@pytest.mark.parametrize("tile", [(16, 32), (64, 64), (96, 128), (160, 224)], ids=lambda t: f"{t[0]}x{t[1]}")
+@pytest.mark.parametrize("T", [1, 4])
+def test_persistent_tile_shapes(ltl, tile, T):
+    """Few tiles (one per workgroup, some XCDs idle) up to many per workgroup."""
+    rule = inputs.Rule(7, 0, 1, 56, 101, 60, 76)
+    g0 = inputs.bernoulli_grid(301, 299, 0.5, seed=6)
+    tuning = dict(steps_per_launch=T, tile_rows=tile[0], tile_cols=tile[1], waves=0, persistent=1)
+    if not shape_feasible(7, T, tile[0], tile[1], lds_max=80 * 1024):
+        with pytest.raises(ltl.LtlError) as e:
+            run_and_compare(ltl, g0, rule, "cat_i8", 8, tuning=tuning)
+        assert e.value.code == ltl.LTL_ERR_ARG
+        return
+    run_and_compare(ltl, g0, rule, "cat_i8", 8, tuning=tuning)
+
+
+def test_persistent_tiny_grids(ltl):
+    """Fewer tiles than XCDs: the surplus workgroups have no tile and exit."""
+    rule = inputs.BOSCO_M1
+    for shape in [(1, 1), (17, 33), (40, 100)]:
+        g0 = inputs.bernoulli_grid(*shape, 0.5, seed=shape[1])
+        run_and_compare(ltl, g0, rule, "cat_i8", 4, tuning=dict(steps_per_launch=2, tile_rows=16, tile_cols=32,
+                                                                 waves=0, persistent=1))
+
+
+def test_persistent_refused_where_absent(ltl):
+    g = gpu_grid(np.zeros((64, 64), dtype=np.uint8))
+    with pytest.raises(ltl.LtlError) as e:
+        ltl.Simulation(g, inputs.LIFE, "direct", tuning=dict(steps_per_launch=1, persistent=1))
+    assert e.value.code == ltl.LTL_ERR_ARG
+    with pytest.raises(ltl.LtlError) as e:
+        ltl.Batch([g, g], [inputs.LIFE, inputs.LIFE], "cat_i8", tuning=dict(persistent=1))
+    assert e.value.code == ltl.LTL_ERR_ARG

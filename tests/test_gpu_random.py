@@ -1,5 +1,5 @@
 """Randomized GPU parity: seeded cases drawn over every dimension at once (grid size, radius,
-method, neighbourhood, boundary, states, M, ranges, launch shape, graph use), each checked
+method, neighbourhood, boundary, states, M, ranges, launch shape and form, graph use), each checked
 cell for cell against the oracle. A combination the library does not offer must be refused
 with its documented error code; a launch shape it cannot run with LTL_ERR_ARG."""
 import numpy as np
@@ -12,7 +12,7 @@ pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
 
-N_CASES = 120
+N_CASES = 160
 
 
 @pytest.fixture(scope="module")
@@ -49,6 +49,7 @@ def draw_case(k):
         tuning = dict(steps_per_launch=int(rng.integers(1, 6)), tile_rows=16 * int(rng.integers(1, 12)),
                       tile_cols=32 * int(rng.integers(1, 8)), waves=int(rng.choice([0, 0, 8, 16])),
                       use_graph=int(rng.integers(0, 2)))
+        tuning["persistent"] = int(rng.random() < 0.5)
     return method, rule, periodic, H, W, steps, tuning
 
 
