@@ -79,16 +79,17 @@ __device__ __forceinline__ uint32_t col_mask(int gc, int W) {
 // Returns the state dword; *alive receives the alive-indicator dword (state == 1).
 //
 // Two-state rules test lo(s) <= n <= hi(s) on 8-bit (BYTE) or 16-bit (HALF) SWAR lanes:
-// a = 0x80 + n - lo has its top bit set iff n >= lo, b = 0x80 + hi - n iff n <= hi, and the
-// per-lane offsets come from the centre state in one 3-input bitwise op each.
+// a = 0x80 + n - lo has its top bit set iff n >= lo, b = 0x80 + hi - n iff n <= hi (no lane
+// carries or borrows: n, lo, hi <= 127, resp. 2047). BYTE takes the per-lane offsets from the
+// centre states (0 or 1 per byte) with one byte permute each, the states acting as byte
+// selectors into a two-entry table; HALF derives them with 3-input bitwise ops.
 template <int EPI>
 __device__ __forceinline__ uint32_t transition4(v4i n, uint32_t s, uint32_t m, const RuleConsts &rc,
                                                 uint32_t *alive) {
     if constexpr (EPI == EPI_BYTE) {
         uint32_t N = pack_bytes(n);
-        uint32_t sm = 0x80808080u - s;                 // 0x80 per dead lane, 0x7F per alive lane
-        uint32_t a = N + (rc.Klo ^ (sm & rc.Dlo));
-        uint32_t b = (rc.Khi ^ (sm & rc.Dhi)) - N;
+        uint32_t a = N + __builtin_amdgcn_perm(rc.Tlo, rc.Tlo, s);
+        uint32_t b = __builtin_amdgcn_perm(rc.Thi, rc.Thi, s) - N;
         uint32_t x = (a & b & (m & 0x80808080u)) >> 7;
         *alive = x;
         return x;

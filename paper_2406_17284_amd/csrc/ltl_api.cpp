@@ -106,6 +106,10 @@ RuleConsts make_consts(const ltl_rule_t &r, int epi) {
     c.Klo = klo_b ^ ((top * rep) & c.Dlo);
     c.Dhi = khi_s ^ khi_b;
     c.Khi = khi_b ^ ((top * rep) & c.Dhi);
+    if (epi == EPI_BYTE) {
+        c.Tlo = (klo_b & 0xFFu) | ((klo_s & 0xFFu) << 8);
+        c.Thi = (khi_b & 0xFFu) | ((khi_s & 0xFFu) << 8);
+    }
     return c;
 }
 

@@ -32,6 +32,10 @@ struct RuleConsts {
     // (0x8000-based for HALF), lo/hi being the birth range for s = 0 and the survival range
     // for s = 1.
     uint32_t Klo, Dlo, Khi, Dhi;
+    // BYTE lookup tables of the same offsets, indexed by the centre state (0 or 1) with one
+    // byte permute per dword of four cells: byte 0 holds the dead-centre offset, byte 1 the
+    // alive-centre offset (Tlo: 0x80 - lo(s), Thi: 0x80 + hi(s)).
+    uint32_t Tlo, Thi;
 };
 
 struct CatParams {
