@@ -245,7 +245,7 @@ int32_t batch_prepare(ltl_batch &b) {
             cost = 0.25 * (double)(p.TH + 2 * p.L) * (p.TW + 2 * p.L);
             for (int st = 1; st <= p.T; ++st) {
                 const int E = roundup(r * (p.T - st), 16);
-                cost += (double)(p.TH + 2 * E) * (p.TW + 2 * E) * (b.epi[i] == EPI_BYTE ? 1.0 : 1.15);
+                cost += (double)(p.TH + 2 * E) * (p.TW + 2 * E) * ((b.epi[i] == EPI_BYTE || b.epi[i] == EPI_WIN) ? 1.0 : 1.15);
             }
         }
         for (int k = 0; k < ntiles; ++k) list.push_back({cost, {i, k, b.epi[i], 0}});
@@ -549,7 +549,7 @@ int32_t ltl_batch_create(ltl_batch_t **out, int32_t count, const int32_t *H, con
         b->W.push_back(W[i]);
         b->pitch.push_back(pitch_of(W[i]));
         b->rule.push_back(rules[i]);
-        b->epi.push_back(epi_of(rules[i]));
+        b->epi.push_back(epi_of(rules[i], elem_of(b->method, rules[i].R, rules[i].N)));
         b->rc.push_back(make_consts(rules[i], b->epi.back()));
         b->off.push_back(off);
         off += arena_slot_bytes(H[i], W[i]);

@@ -30,7 +30,9 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) c
     const Codec cd = make_codec();
     if (item.epi == EPI_BYTE)
         cat_tile<ELEM, EPI_BYTE>(p, item.tile, lds, tid, lane, wave, nwaves, cd);
-    else if (item.epi == EPI_HALF)
+    else if (item.epi == EPI_WIN) {
+        if constexpr (ELEM == ELEM_I8) cat_tile<ELEM, EPI_WIN>(p, item.tile, lds, tid, lane, wave, nwaves, cd);
+    } else if (item.epi == EPI_HALF)
         cat_tile<ELEM, EPI_HALF>(p, item.tile, lds, tid, lane, wave, nwaves, cd);
     else
         cat_tile<ELEM, EPI_DECAY>(p, item.tile, lds, tid, lane, wave, nwaves, cd);

@@ -50,6 +50,7 @@ typedef int32_t v2i __attribute__((ext_vector_type(2)));
 typedef int32_t v16i __attribute__((ext_vector_type(16)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef _Float16 v8h __attribute__((ext_vector_type(8)));
+typedef uint16_t us2 __attribute__((ext_vector_type(2)));
 // global-memory dword (explicit address space: global_store_*, not flat_* which would also
 // count against the LDS wait counter)
 typedef __attribute__((address_space(1))) uint32_t gdword;
@@ -86,8 +87,21 @@ __device__ __forceinline__ uint32_t col_mask(int gc, int W) {
 template <int EPI>
 __device__ __forceinline__ uint32_t transition4(v4i n, uint32_t s, uint32_t m, const RuleConsts &rc,
                                                 uint32_t *alive) {
-    if constexpr (EPI == EPI_BYTE) {
-        uint32_t N = pack_bytes(n);
+    if constexpr (EPI == EPI_BYTE || EPI == EPI_WIN) {
+        uint32_t N;
+        if constexpr (EPI == EPI_BYTE) {
+            N = pack_bytes(n);
+        } else {
+            // counts arrive as n - c: low 16 bits clamped to 127 (values above the window and
+            // negative ones both become 127, outside every shifted range), then one byte each
+            const us2 cap = {127, 127};
+            const us2 p01 = __builtin_elementwise_min(
+                __builtin_bit_cast(us2, __builtin_amdgcn_perm((uint32_t)n[1], (uint32_t)n[0], 0x05040100u)), cap);
+            const us2 p23 = __builtin_elementwise_min(
+                __builtin_bit_cast(us2, __builtin_amdgcn_perm((uint32_t)n[3], (uint32_t)n[2], 0x05040100u)), cap);
+            N = __builtin_amdgcn_perm(__builtin_bit_cast(uint32_t, p23), __builtin_bit_cast(uint32_t, p01),
+                                      0x06040200u);
+        }
         uint32_t a = N + __builtin_amdgcn_perm(rc.Tlo, rc.Tlo, s);
         uint32_t b = __builtin_amdgcn_perm(rc.Thi, rc.Thi, s) - N;
         uint32_t x = (a & b & (m & 0x80808080u)) >> 7;
@@ -413,8 +427,9 @@ __device__ __forceinline__ void phase_a(const uint8_t *At, uint32_t a_off, uint3
 }
 
 // Vertical band product of output block M for one half (counts as int32 or biased fp32 bits).
+// `acc` is the int8 product's starting accumulator (0, or -c for the windowed epilogue).
 template <int ELEM, int M>
-__device__ __forceinline__ v4i vproduct(const v16i &H, const v16i &L, const Bands &bd) {
+__device__ __forceinline__ v4i vproduct(const v16i &H, const v16i &L, const Bands &bd, const v4i &acc) {
     if constexpr (ELEM == ELEM_I8X) {
         // cross: H at the centre row (identity window) plus the vertical arm of the alive map
         // (centre excluded), same window of blocks, same instruction, one accumulator
@@ -435,9 +450,8 @@ __device__ __forceinline__ v4i vproduct(const v16i &H, const v16i &L, const Band
             return __builtin_amdgcn_mfma_i32_16x16x64_i8(window4<M + 3>(H), bd.op[7], c, 0, 0, 0);
         }
     } else if constexpr (ELEM == ELEM_I8) {
-        const v4i zero = {0, 0, 0, 0};
         constexpr int W0 = (M & 1) ? M - 1 : M;
-        return __builtin_amdgcn_mfma_i32_16x16x64_i8(window4<W0>(H), (M & 1) ? bd.op[3] : bd.op[2], zero, 0, 0, 0);
+        return __builtin_amdgcn_mfma_i32_16x16x64_i8(window4<W0>(H), (M & 1) ? bd.op[3] : bd.op[2], acc, 0, 0, 0);
     } else if constexpr (ELEM == ELEM_F8) {
         const v4f bias = {8388608.f, 8388608.f, 8388608.f, 8388608.f};
         constexpr int W0 = (M & 1) ? M - 1 : M;
@@ -475,11 +489,13 @@ __device__ __forceinline__ void phase_b(const CatParams &p, uint8_t *Qt, uint8_t
     const uint32_t PS = (uint32_t)p.PS, PA = (uint32_t)p.PA;
     v4i ca[4], cb[4];
     uint32_t sa[4], sb[4];
+    const int cw = (EPI == EPI_WIN) ? -p.rc.cwin : 0;
+    const v4i acc0 = {cw, cw, cw, cw};
     // counts and centre states of block M (slot M & 3)
 #define CAT_ISSUE(M)                                                                               \
     {                                                                                              \
-        ca[(M) & 3] = vproduct<ELEM, (M)>(Ha, La, bd);                                             \
-        cb[(M) & 3] = vproduct<ELEM, (M)>(Hb, Lb, bd);                                             \
+        ca[(M) & 3] = vproduct<ELEM, (M)>(Ha, La, bd, acc0);                                       \
+        cb[(M) & 3] = vproduct<ELEM, (M)>(Hb, Lb, bd, acc0);                                       \
         if constexpr (EPI == EPI_DECAY || kIsI8<ELEM>) {                                           \
             const uint32_t qo = lo.q + (uint32_t)(16 * (rb0 + (M))) * PS;                          \
             sa[(M) & 3] = *reinterpret_cast<const uint32_t *>(Qt + qo);                            \

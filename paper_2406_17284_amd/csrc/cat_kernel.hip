@@ -85,6 +85,7 @@ size_t cat_lds_bytes(const CatParams &p, int elem, int epi, int persistent) {
             return dec ? (const void *)&KERNEL<ELEM_I8X, EPI_DECAY> : (const void *)&KERNEL<ELEM_I8X, EPI_BYTE>;   \
         if (elem == ELEM_I8W)   /* radii 17..32 always have counts > 126: no 8-bit epilogue */                     \
             return dec ? (const void *)&KERNEL<ELEM_I8W, EPI_DECAY> : (const void *)&KERNEL<ELEM_I8W, EPI_HALF>;   \
+        if (epi == EPI_WIN) return (const void *)&KERNEL<ELEM_I8, EPI_WIN>;                                        \
         return dec ? (const void *)&KERNEL<ELEM_I8, EPI_DECAY>                                                     \
                    : epi == EPI_HALF ? (const void *)&KERNEL<ELEM_I8, EPI_HALF> : (const void *)&KERNEL<ELEM_I8, EPI_BYTE>; \
     }

@@ -28,7 +28,7 @@ int32_t validate_rule(const ltl_rule_t *r, int method);
 // Largest count of the rule's neighbourhood (centre included).
 int max_count(const ltl_rule_t &r);
 // Epilogue flavour (Epi) of a rule.
-int epi_of(const ltl_rule_t &r);
+int epi_of(const ltl_rule_t &r, int elem);
 // Thresholds and SWAR constants of a rule for an epilogue flavour.
 RuleConsts make_consts(const ltl_rule_t &r, int epi);
 // Row pitch of the library layout: W rounded up to 64 bytes.

@@ -61,9 +61,46 @@ int32_t validate_rule(const ltl_rule_t *r, int method) {
 
 int max_count(const ltl_rule_t &r) { return r.N == 'N' ? 4 * r.R + 1 : (2 * r.R + 1) * (2 * r.R + 1); }
 
-int epi_of(const ltl_rule_t &r) {
+// Survival (alive centre) and birth ranges on the box count n (centre included), clipped to
+// 0..nmax; an alive centre with M = 0 sees n - 1, so its survival range moves up by one. An
+// empty range is returned as lo = `cap`, hi = 0 (no count satisfies both tests).
+struct Ranges {
+    int ls, hs, lb, hb;
+    bool s_empty, b_empty;
+};
+static Ranges rule_ranges(const ltl_rule_t &r, int cap) {
+    const int nmax = max_count(r);
+    const int shift = (r.M == 0) ? 1 : 0;
+    Ranges g;
+    auto norm = [&](int lo, int hi, int &olo, int &ohi, bool &empty) {
+        empty = (lo > hi || lo > nmax || hi < 0);
+        if (empty) { olo = cap; ohi = 0; return; }
+        olo = std::max(lo, 0);
+        ohi = std::min(hi, nmax);
+    };
+    norm(r.S1 + shift, r.S2 + shift, g.ls, g.hs, g.s_empty);
+    norm(r.B1, r.B2, g.lb, g.hb, g.b_empty);
+    return g;
+}
+
+// Window offset of EPI_WIN: c = (smallest lower bound) - 1, valid when every upper bound is
+// at most c + 126. Returns false when the ranges span more than that.
+static bool window_of(const ltl_rule_t &r, int *c) {
+    const Ranges g = rule_ranges(r, 127);
+    int lo = 1 << 30, hi = -(1 << 30);
+    if (!g.s_empty) { lo = std::min(lo, g.ls); hi = std::max(hi, g.hs); }
+    if (!g.b_empty) { lo = std::min(lo, g.lb); hi = std::max(hi, g.hb); }
+    if (g.s_empty && g.b_empty) { *c = 0; return true; }
+    *c = lo - 1;
+    return hi - *c <= 126;
+}
+
+int epi_of(const ltl_rule_t &r, int elem) {
     if (r.C >= 3) return EPI_DECAY;
-    return max_count(r) <= 126 ? EPI_BYTE : EPI_HALF;
+    if (max_count(r) <= 126) return EPI_BYTE;
+    int c = 0;
+    if (elem == ELEM_I8 && window_of(r, &c)) return EPI_WIN;
+    return EPI_HALF;
 }
 
 // Thresholds on the box count n (centre included) and the SWAR constants of the two-state
@@ -74,23 +111,21 @@ RuleConsts make_consts(const ltl_rule_t &r, int epi) {
     c.C = r.C >= 3 ? r.C : 2;
     c.M = r.M;
     c.s1 = r.S1; c.s2 = r.S2; c.b1 = r.B1; c.b2 = r.B2;
-    const int nmax = max_count(r);
-    const int shift = (r.M == 0) ? 1 : 0;
-    auto norm = [&](int lo, int hi, int cap, int &olo, int &ohi) {
-        if (lo > hi || lo > nmax || hi < 0) { olo = cap; ohi = 0; return; }  // empty range
-        olo = std::max(lo, 0);
-        ohi = std::min(hi, nmax);
-    };
     int ls, hs, lb, hb;
     uint32_t rep, top, klo_s, klo_b, khi_s, khi_b;
-    if (epi == EPI_BYTE) {
-        norm(r.S1 + shift, r.S2 + shift, 127, ls, hs);
-        norm(r.B1, r.B2, 127, lb, hb);
+    if (epi == EPI_BYTE || epi == EPI_WIN) {
+        Ranges g = rule_ranges(r, 127);
+        if (epi == EPI_WIN) {   // thresholds relative to the window offset (non-empty ranges)
+            (void)window_of(r, &c.cwin);
+            if (!g.s_empty) { g.ls -= c.cwin; g.hs -= c.cwin; }
+            if (!g.b_empty) { g.lb -= c.cwin; g.hb -= c.cwin; }
+        }
+        ls = g.ls; hs = g.hs; lb = g.lb; hb = g.hb;
         rep = 0x01010101u;
         top = 0x80u;
     } else if (epi == EPI_HALF) {
-        norm(r.S1 + shift, r.S2 + shift, 2047, ls, hs);
-        norm(r.B1, r.B2, 2047, lb, hb);
+        const Ranges g = rule_ranges(r, 2047);
+        ls = g.ls; hs = g.hs; lb = g.lb; hb = g.hb;
         rep = 0x00010001u;
         top = 0x8000u;
     } else {
@@ -106,7 +141,7 @@ RuleConsts make_consts(const ltl_rule_t &r, int epi) {
     c.Klo = klo_b ^ ((top * rep) & c.Dlo);
     c.Dhi = khi_s ^ khi_b;
     c.Khi = khi_b ^ ((top * rep) & c.Dhi);
-    if (epi == EPI_BYTE) {
+    if (epi == EPI_BYTE || epi == EPI_WIN) {
         c.Tlo = (klo_b & 0xFFu) | ((klo_s & 0xFFu) << 8);
         c.Thi = (khi_b & 0xFFu) | ((khi_s & 0xFFu) << 8);
     }
@@ -404,7 +439,7 @@ int32_t ltl_create(ltl_sim_t **out, int32_t H, int32_t W, const ltl_rule_t *rule
     s->pitch = pitch_of(W);
     s->rule = *rule;
     s->method = method;
-    s->epi = epi_of(*rule);
+    s->epi = epi_of(*rule, elem_of(method, rule->R, rule->N));
     s->rc = make_consts(*rule, s->epi);
     s->buf[0] = (uint8_t *)buf_a;
     s->buf[1] = (uint8_t *)buf_b;

@@ -9,7 +9,11 @@ namespace ltl {
 //  EPI_BYTE  two states, every count fits in 7 bits ((2r+1)^2 <= 126): 4 cells per dword SWAR
 //  EPI_HALF  two states, counts up to 1089: 2 cells per dword SWAR on 16-bit lanes
 //  EPI_DECAY C >= 3 states: per-cell transition with decay
-enum Epi { EPI_BYTE = 0, EPI_HALF = 1, EPI_DECAY = 2 };
+//  EPI_WIN   two states, counts above 126, int8 element, every finite range bound within a
+//            window c+1..c+126: the vertical product starts from -c, the counts n - c are
+//            clamped to 127 (all values outside the window land there, outside every range)
+//            and the EPI_BYTE transition runs on them
+enum Epi { EPI_BYTE = 0, EPI_HALF = 1, EPI_DECAY = 2, EPI_WIN = 3 };
 
 // Element type of the band-product operands. ELEM_I8W is int8 for radii 17..32: every
 // 16-column half needs 16 + 2r <= 80 columns (a K = 64 and a K = 32 product) and every
@@ -36,6 +40,7 @@ struct RuleConsts {
     // byte permute per dword of four cells: byte 0 holds the dead-centre offset, byte 1 the
     // alive-centre offset (Tlo: 0x80 - lo(s), Thi: 0x80 + hi(s)).
     uint32_t Tlo, Thi;
+    int32_t cwin;          // EPI_WIN: window offset c (the vertical product starts from -c)
 };
 
 struct CatParams {

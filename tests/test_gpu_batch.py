@@ -244,3 +244,29 @@ def test_batch_cross_rules(ltl):
     batch.step(3)
     check_batch(batch, [oracle.run(g, r, 3) for g, r in zip(grids, rules)], "direct cross batch")
     batch.close()
+
+
+def test_batch_mixes_every_epilogue(ltl):
+    """One launch holding byte (r <= 5), windowed byte (counts above 126, narrow ranges),
+    16-bit lane and decay instances, on density-striped grids, every step against the oracle."""
+    rules = [inputs.BOSCO_M1, inputs.sweep_rule(6), inputs.Rule(8, 0, 1, 100, 225, 150, 160),
+             inputs.Rule(8, 0, 1, 100, 226, 150, 160), inputs.Rule(9, 0, 0, 200, 250, 190, 260),
+             inputs.sweep_rule(16), inputs.Rule(6, 0, 1, 10, 100, 0, 50), inputs.Rule(4, 5, 1, 20, 40, 25, 30)]
+    shapes = [(140, 150), (200, 96), (97, 333), (256, 256), (64, 500), (300, 130), (50, 50), (180, 210)]
+    ps = [0.1, 0.35, 0.5, 0.78, 0.9]
+    grids = []
+    for k, ((H, W), rule) in enumerate(zip(shapes, rules)):
+        if rule.C >= 3:
+            grids.append(inputs.state_grid(H, W, rule.C, seed=300 + k))
+            continue
+        band = -(-H // len(ps))
+        grids.append(np.vstack([inputs.bernoulli_grid(min(band, H - j * band), W, p, 300 + 10 * k + j)
+                                for j, p in enumerate(ps) if j * band < H]))
+    for tuning in (None, dict(steps_per_launch=3, tile_rows=64, tile_cols=64)):
+        batch = ltl.Batch([gpu_grid(g) for g in grids], rules, "cat_i8", tuning=tuning)
+        refs = [g.copy() for g in grids]
+        for t in range(4):
+            batch.step(1 if tuning is None else 3)
+            refs = [oracle.run(ref, rule, 1 if tuning is None else 3) for ref, rule in zip(refs, rules)]
+            check_batch(batch, refs, f"tuning={tuning} step {t + 1}")
+        batch.close()

@@ -485,3 +485,66 @@ def test_persistent_refused_where_absent(ltl):
     with pytest.raises(ltl.LtlError) as e:
         ltl.Batch([g, g], [inputs.LIFE, inputs.LIFE], "cat_i8", tuning=dict(persistent=1))
     assert e.value.code == ltl.LTL_ERR_ARG
+
+
+# ------------------------------------------------------------------ windowed byte epilogue
+# Two-state rules whose counts exceed 126 but whose finite range bounds all lie in a window
+# c+1..c+126 run the byte epilogue on n - c clamped to 127 (int8 method); the others keep
+# 16-bit lanes. Each rule below sits on one side of that choice or at an edge of it; the
+# grids are striped in density so that the counts sweep across the window bounds.
+WINDOW_RULES = [
+    inputs.Rule(6, 0, 1, 42, 76, 45, 57),            # sweep rule r = 6 (window 41..167)
+    inputs.Rule(8, 0, 1, 100, 225, 150, 160),        # span exactly 126: windowed
+    inputs.Rule(8, 0, 1, 100, 226, 150, 160),        # span 127: 16-bit lanes
+    inputs.Rule(6, 0, 1, 10, 100, 0, 50),            # lower bound 0 (c = -1)
+    inputs.Rule(6, 0, 1, 150, 169, 140, 160),        # upper bound at the largest count
+    inputs.Rule(7, 0, 1, 60, 120, 9, 8),             # empty birth range
+    inputs.Rule(6, 0, 1, 5, 4, 9, 8),                # both ranges empty
+    inputs.Rule(9, 0, 0, 200, 250, 190, 260),        # M = 0: survival range moves up by one
+    inputs.Rule(12, 0, 1, 156, 281, 168, 212),       # sweep rule r = 12 (span 126)
+    inputs.Rule(16, 0, 1, 500, 560, 480, 600),       # r = 16, narrow window
+]
+
+
+def striped_grid(H, W, seed):
+    """Horizontal bands of Bernoulli densities 0.1 .. 0.9 (counts from low to high)."""
+    ps = [0.1, 0.3, 0.35, 0.5, 0.65, 0.78, 0.9]
+    band = -(-H // len(ps))
+    parts = [inputs.bernoulli_grid(min(band, H - k * band), W, p, seed + k) for k, p in enumerate(ps) if k * band < H]
+    return np.vstack(parts)
+
+
+@pytest.mark.parametrize("rule", WINDOW_RULES, ids=lambda r: r.text())
+def test_window_epilogue_every_step(ltl, rule):
+    g0 = striped_grid(161, 203, seed=rule.R * 7 + rule.S2)
+    run_and_compare_each_step(ltl, g0, rule, "cat_i8", 6)
+
+
+@pytest.mark.parametrize("rule", WINDOW_RULES, ids=lambda r: r.text())
+@pytest.mark.parametrize("form", ["T3", "persistent", "torus"])
+def test_window_epilogue_launch_forms(ltl, rule, form):
+    g0 = striped_grid(300, 336, seed=rule.R)
+    if form == "torus":
+        run_periodic(ltl, g0, rule, "cat_i8", 5, tuning=dict(steps_per_launch=2, tile_rows=64, tile_cols=64, waves=0),
+                     every_step=False)
+        return
+    tuning = dict(steps_per_launch=3, tile_rows=64, tile_cols=96, waves=8, persistent=int(form == "persistent"))
+    if not shape_feasible(rule.R, 3, 64, 96, lds_max=(80 if form == "persistent" else 160) * 1024):
+        tuning["steps_per_launch"] = 1
+    run_and_compare(ltl, g0, rule, "cat_i8", 7, tuning=tuning, chunks=[3, 4])
+
+
+def test_window_epilogue_matches_half_lanes(ltl):
+    """The same windowed rules through fp16 and fp8 (16-bit lanes) and the direct stencil."""
+    g0 = striped_grid(257, 300, seed=77)
+    for rule in WINDOW_RULES[:6]:
+        ref = None
+        for method in ["cat_i8", "cat_f16", "direct"] + (["cat_f8"] if rule.R <= 7 else []):
+            sim = ltl.Simulation(gpu_grid(g0), rule, method)
+            sim.step(9)
+            got = sim.read().cpu().numpy()
+            sim.close()
+            if ref is None:
+                ref = got
+                assert np.array_equal(ref, oracle.run(g0, rule, 9)), rule.text()
+            assert np.array_equal(got, ref), f"{method} {rule.text()}"
