@@ -75,6 +75,30 @@ __device__ __forceinline__ uint32_t col_mask(int gc, int W) {
     return m;
 }
 
+// alive indicator (byte == 1) of a dword of states, any byte values
+__device__ __forceinline__ uint32_t alive_of(uint32_t s) {
+    uint32_t x = s ^ 0x01010101u;                              // zero byte iff state == 1
+    uint32_t y = ((x & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | x;         // bit 7 iff byte != 0
+    return (~y & 0x80808080u) >> 7;
+}
+
+// Range test of 4 cells on 16-bit SWAR lanes (counts up to 32767): byte v of the result is 1
+// iff lo(a) <= n[v] <= hi(a), a = byte v of `a` (0: birth range, 1: survival range), with
+// a = 0x8000 + n - lo and b = 0x8000 + hi - n as for the byte lanes. Only the low 16 bits of
+// each count are used, which also strips the 2^23 bias of the fp32 accumulators.
+__device__ __forceinline__ uint32_t inrange16(v4i n, uint32_t a, const RuleConsts &rc) {
+    const uint32_t p01 = __builtin_amdgcn_perm((uint32_t)n[1], (uint32_t)n[0], 0x05040100u);
+    const uint32_t p23 = __builtin_amdgcn_perm((uint32_t)n[3], (uint32_t)n[2], 0x05040100u);
+    const uint32_t s01 = __builtin_amdgcn_perm(0u, a, 0x0c010c00u);  // bytes 0, 1 -> 16-bit lanes
+    const uint32_t s23 = __builtin_amdgcn_perm(0u, a, 0x0c030c02u);
+    const uint32_t sm01 = 0x80008000u - s01;
+    const uint32_t sm23 = 0x80008000u - s23;
+    const uint32_t x01 = (p01 + (rc.Klo ^ (sm01 & rc.Dlo))) & ((rc.Khi ^ (sm01 & rc.Dhi)) - p01) & 0x80008000u;
+    const uint32_t x23 = (p23 + (rc.Klo ^ (sm23 & rc.Dlo))) & ((rc.Khi ^ (sm23 & rc.Dhi)) - p23) & 0x80008000u;
+    // bits 15 and 31 of x01, x23 -> bit 7 of bytes 0..3, then down to bit 0
+    return __builtin_amdgcn_perm(x23, x01, 0x07050301u) >> 7;
+}
+
 // Next states of 4 adjacent cells from their box counts n (centre included) and states s.
 // `m` is the validity mask of the 4 cells (0xFF per byte inside the grid); cells outside get 0.
 // Returns the state dword; *alive receives the alive-indicator dword (state == 1).
@@ -108,50 +132,26 @@ __device__ __forceinline__ uint32_t transition4(v4i n, uint32_t s, uint32_t m, c
         *alive = x;
         return x;
     } else if constexpr (EPI == EPI_HALF) {
-        // low 16 bits of each count (also correct for the 2^23-biased fp32 accumulators)
-        uint32_t p01 = __builtin_amdgcn_perm((uint32_t)n[1], (uint32_t)n[0], 0x05040100u);
-        uint32_t p23 = __builtin_amdgcn_perm((uint32_t)n[3], (uint32_t)n[2], 0x05040100u);
-        uint32_t s01 = __builtin_amdgcn_perm(0u, s, 0x0c010c00u);  // bytes 0, 1 -> 16-bit lanes
-        uint32_t s23 = __builtin_amdgcn_perm(0u, s, 0x0c030c02u);
-        uint32_t m01 = __builtin_amdgcn_perm(0u, m, 0x010c000cu);  // mask bytes 0, 1 -> lane top bytes
-        uint32_t m23 = __builtin_amdgcn_perm(0u, m, 0x030c020cu);
-        uint32_t sm01 = 0x80008000u - s01;
-        uint32_t sm23 = 0x80008000u - s23;
-        uint32_t x01 = (p01 + (rc.Klo ^ (sm01 & rc.Dlo))) & ((rc.Khi ^ (sm01 & rc.Dhi)) - p01) & (m01 & 0x80008000u);
-        uint32_t x23 = (p23 + (rc.Klo ^ (sm23 & rc.Dlo))) & ((rc.Khi ^ (sm23 & rc.Dhi)) - p23) & (m23 & 0x80008000u);
-        // bits 15 and 31 of x01, x23 -> bit 7 of bytes 0..3, then down to bit 0
-        uint32_t x = __builtin_amdgcn_perm(x23, x01, 0x07050301u) >> 7;
+        const uint32_t x = inrange16(n, s, rc) & m;
         *alive = x;
         return x;
     } else {
-        uint32_t out = 0, al = 0;
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            int sv = (int)((s >> (8 * v)) & 0xFFu);
-            int c = n[v] & 0xFFFF;   // counts <= 1089; also strips the bias of fp32 accumulators
-            int nx;
-            if (sv == 0) {
-                nx = (rc.b1 <= c && c <= rc.b2) ? 1 : 0;
-            } else if (sv == 1) {
-                int k = c - (rc.M == 0 ? 1 : 0);
-                nx = (rc.s1 <= k && k <= rc.s2) ? 1 : 2;
-            } else {
-                nx = (sv + 1 < rc.C) ? sv + 1 : 0;
-            }
-            out |= (uint32_t)nx << (8 * v);
-            al |= (uint32_t)(nx == 1) << (8 * v);
-        }
-        *alive = al & m;
-        return out & m;
+        // C >= 3. Per byte, g = 1 where the cell leaves its state: birth (s = 0, n in the birth
+        // range), death (s = 1, n outside the survival range) or decay (s >= 2); the next state
+        // is s + g, and a byte that reaches C wraps to 0 (only decaying cells get there).
+        const uint32_t a1 = alive_of(s);
+        const uint32_t x = inrange16(n, a1, rc);                     // range of the s in {0, 1} case
+        const uint32_t d = ((((s & 0x7E7E7E7Eu) + 0x7E7E7E7Eu) | s) >> 7) & 0x01010101u;   // s >= 2
+        const uint32_t nx = s + ((x ^ a1) | d);
+        const uint32_t e = nx ^ rc.Crep;                             // zero byte where nx == C
+        const uint32_t keep = (((e & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | e) & 0x80808080u;
+        const uint32_t km = keep | (keep - (keep >> 7));             // 0xFF per byte to keep
+        *alive = x & ~d & m;                                         // next state == 1
+        return nx & km & m;
     }
 }
 
-// alive indicator (byte == 1) of a dword of states, any byte values
-__device__ __forceinline__ uint32_t alive_of(uint32_t s) {
-    uint32_t x = s ^ 0x01010101u;                              // zero byte iff state == 1
-    uint32_t y = ((x & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | x;         // bit 7 iff byte != 0
-    return (~y & 0x80808080u) >> 7;
-}
+
 
 // ---------------------------------------------------------------- element encodings
 // Per element type: bytes per cell of the alive map in LDS, the longest run of output blocks a

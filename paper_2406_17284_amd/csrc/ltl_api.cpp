@@ -123,8 +123,9 @@ RuleConsts make_consts(const ltl_rule_t &r, int epi) {
         ls = g.ls; hs = g.hs; lb = g.lb; hb = g.hb;
         rep = 0x01010101u;
         top = 0x80u;
-    } else if (epi == EPI_HALF) {
+    } else if (epi == EPI_HALF || epi == EPI_DECAY) {   // decay: the range test of the s in {0, 1} case
         const Ranges g = rule_ranges(r, 2047);
+        c.Crep = (uint32_t)c.C * 0x01010101u;
         ls = g.ls; hs = g.hs; lb = g.lb; hb = g.hb;
         rep = 0x00010001u;
         top = 0x8000u;

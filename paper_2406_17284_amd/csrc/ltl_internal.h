@@ -41,6 +41,7 @@ struct RuleConsts {
     // alive-centre offset (Tlo: 0x80 - lo(s), Thi: 0x80 + hi(s)).
     uint32_t Tlo, Thi;
     int32_t cwin;          // EPI_WIN: window offset c (the vertical product starts from -c)
+    uint32_t Crep;         // EPI_DECAY: C in every byte (a state reaching C wraps to 0)
 };
 
 struct CatParams {
