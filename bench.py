@@ -31,6 +31,7 @@ DEFAULT_TUNING = "4,160,224,8"   # steps per launch, tile rows, tile cols, waves
 KERNEL_SRC = [os.path.join(ROOT, "paper_2406_17284_amd", "csrc", f) for f in ("cat_device.h", "cat_kernel.hip")]
 BATCH_TUNING = "2,176,224,8"   # the autotuner's pick for the 512-instance batch on MI355X
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "cat_step_i8_bosco4096_traffic.json")
+MFMA_RECORD = os.path.join(ROOT, "profiles", "cat_step_i8_bosco4096_sq.json")
 
 
 def kernel_hash() -> str:
@@ -64,6 +65,20 @@ def recorded_traffic(tuning):
     if rec.get("kernel_sha256") != kernel_hash() or rec.get("tuning") != shape:
         return None
     return rec["hbm_bytes_per_launch"]
+
+
+def recorded_mfma_ops(tuning):
+    """int8 MFMA ops issued per launch (SQ_INSTS_VALU_MFMA_MOPS_I8 x 512) from the committed
+    counter record, if it was taken on this kernel source and launch shape; else None."""
+    try:
+        with open(MFMA_RECORD) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    shape = [tuning[k] for k in SHAPE_KEYS]
+    if rec.get("kernel_sha256") != kernel_hash() or rec.get("tuning") != shape:
+        return None
+    return rec["mfma_ops_per_launch"]
 
 
 def timed_runs(sim, n_per_run, runs, torch):
@@ -154,17 +169,96 @@ def bench_decay(args, ltl, inputs, torch):
     return res
 
 
+def mfma_issued(tuning, avg_launch_s, cells, r):
+    """Counter-measured MFMA utilisation of the timed kernel: int8 ops the MFMAs issue per
+    launch (committed SQ counter record) over launch time x peak, and the useful fraction:
+    the band non-zeros, 4(2r+1) ops per cell-update, over the ops issued per cell-update."""
+    ops = recorded_mfma_ops(tuning)
+    if ops is None:
+        return None
+    steps = tuning["steps_per_launch"]
+    issued_per_cell = ops / (cells * steps)
+    return {"ops_per_launch": ops, "frac_of_peak": ops / avg_launch_s / (INT8_PEAK_TOPS * 1e12),
+            "issued_ops_per_cell_update": issued_per_cell,
+            "useful_ops_per_cell_update": 4 * (2 * r + 1),
+            "useful_frac": 4 * (2 * r + 1) / issued_per_cell}
+
+
+def gpu_energy_reader(torch):
+    """Returns a function giving the GPU's energy counter in joules (amdsmi), or raises."""
+    import amdsmi
+    amdsmi.amdsmi_init()
+    handles = amdsmi.amdsmi_get_processor_handles()
+    if not handles:
+        raise RuntimeError("amdsmi sees no GPU")
+    handle = handles[0]
+    if len(handles) > 1:   # several visible to amdsmi: pick the one HIP runs on, by PCI bus id
+        props = torch.cuda.get_device_properties(0)
+        bus = getattr(props, "pci_bus_id", None)
+        for h in handles:
+            bdf = amdsmi.amdsmi_get_gpu_device_bdf(h)
+            if bus is not None and int(bdf.split(":")[1], 16) == bus:
+                handle = h
+                break
+
+    def read():
+        e = amdsmi.amdsmi_get_energy_count(handle)
+        return e["energy_accumulator"] * e["counter_resolution"] * 1e-6
+    return read
+
+
+def bench_energy(args, ltl, inputs, torch):
+    """Energy efficiency (cell-updates per joule) at the largest workload grid: Bosco R5 on
+    32768^2, 1000-step runs of CAT int8 and a shorter run of the direct stencil, the GPU's own
+    energy counter read before and after each (idle draw measured over the same kind of span)."""
+    try:
+        energy = gpu_energy_reader(torch)
+        energy()
+    except Exception as e:   # no energy counter on this machine: report why instead
+        return {"error": f"{type(e).__name__}: {e}"}
+    side, rule = 32768, inputs.BOSCO_M1
+    g = inputs.bernoulli_grid_torch(side, side, 0.5, 6, device="cuda")
+    res = {"workload": "Bosco R5 C0 M1 S34..58 B34..45 N_M on 32768x32768, Bernoulli(0.5) seed 6, dead halo",
+           "source": "amdsmi energy accumulator of the GPU (whole board), before/after synchronized runs"}
+    torch.cuda.synchronize()
+    e0, t0 = energy(), time.perf_counter()
+    time.sleep(2.0)
+    e1, t1 = energy(), time.perf_counter()
+    res["idle_W"] = (e1 - e0) / (t1 - t0)
+    for method, steps, reps in (("cat_i8", 1000, 3), ("direct", 100, 2)):
+        s = ltl.Simulation(g, rule, method)
+        if method == "cat_i8":
+            s.set_tuning(**parse_tuning(args.tuning))
+        s.step(steps // 10)
+        torch.cuda.synchronize()
+        e0, t0 = energy(), time.perf_counter()
+        for _ in range(reps):
+            s.step(steps)
+        torch.cuda.synchronize()
+        e1, t1 = energy(), time.perf_counter()
+        joules, secs = e1 - e0, t1 - t0
+        n = side * side * steps * reps
+        res[method] = {"steps": steps * reps, "seconds": secs, "joules": joules, "avg_W": joules / secs,
+                       "cell_updates_per_s": n / secs, "cell_updates_per_J": n / joules,
+                       "cell_updates_per_J_above_idle": n / max(1e-9, joules - res["idle_W"] * secs)}
+        s.close()
+    res["cat_over_direct_per_J"] = res["cat_i8"]["cell_updates_per_J"] / res["direct"]["cell_updates_per_J"]
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=20)   # long enough for the GPU clocks to settle
     ap.add_argument("--sweep", action="store_true", help="also time the radius sweep r=1..16 on 16384^2")
     ap.add_argument("--sweep-side", type=int, default=16384)
     ap.add_argument("--sweep-rmax", type=int, default=16, help="largest radius of the sweep (int8 and direct reach 32)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the 512-instance batched workload")
     ap.add_argument("--decay", action="store_true", help="also time the C=8 R16 decay workload on 32768^2")
+    ap.add_argument("--energy", action="store_true",
+                    help="also measure cell-updates per joule (CAT int8 and direct, Bosco R5 on 32768^2)")
     ap.add_argument("--batch-tuning", type=str, default=BATCH_TUNING, help="T,tile_rows,tile_cols,waves of the batch")
     ap.add_argument("--autotune", action="store_true", help="pick the launch shape with ltl_autotune")
     ap.add_argument("--tuning", type=str, default=DEFAULT_TUNING,
@@ -268,6 +362,7 @@ def main():
             "ops_per_cell_update": OPS_PER_CELL,
             "avg_launch_us": avg_launch_s * 1e6,
             "launches_per_bench_step": launches_per_run,
+            "mfma_issued": mfma_issued(tuning, avg_launch_s, cells, w.rule.R),
         },
         "roofline_hbm": {
             "bound": "hbm",
@@ -323,6 +418,8 @@ def main():
 
     if args.decay:
         out["decay"] = bench_decay(args, ltl, inputs, torch)
+    if args.energy:
+        out["energy"] = bench_energy(args, ltl, inputs, torch)
 
     if not args.no_cpu:
         import oracle
