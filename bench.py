@@ -278,7 +278,7 @@ def main():
         print(json.dumps({"calib_copy_bytes": n, "copies": 3}))
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "this library runs on one GPU per process; --gpus must be 1"}))
         sys.exit(2)
 
     import numpy as np
