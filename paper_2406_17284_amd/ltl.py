@@ -264,7 +264,17 @@ def ltl_batch_destroy(batch: int) -> None:
 
 # ------------------------------------------------------------ torch-owned memory
 class Simulation:
-    """One automaton whose two ping-pong buffers are torch uint8 tensors on the GPU."""
+    """One automaton whose two ping-pong buffers are torch uint8 tensors on the GPU.
+
+    init      2-D uint8 CUDA tensor of states (each < max(C, 2)); copied at creation.
+    rule      an ``inputs.Rule`` or anything with R, C, M, S1, S2, B1, B2 (and N) attributes.
+    method    "cat_i8" | "cat_f16" | "cat_f8" | "direct" (or the ltl_method_t value).
+    stream    torch stream the library enqueues on (default: the current stream).
+    tuning    launch shape, the ltl_tuning_t fields as keywords: steps_per_launch, tile_rows,
+              tile_cols, waves, use_graph, persistent (0 = library default for the first four).
+    boundary  "dead" (ghost halo of dead cells) or "periodic" (torus; W must be a multiple of 16).
+    The results never depend on `tuning`; unsupported or infeasible combinations raise LtlError.
+    """
 
     def __init__(self, init, rule, method="cat_i8", stream=None, tuning: Optional[dict] = None,
                  boundary="dead"):
