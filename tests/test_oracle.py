@@ -564,3 +564,15 @@ def test_cross_c_and_numpy_oracles_agree(seed, periodic):
     H, W = int(rng.integers(1, 60)), 16 * int(rng.integers(1, 5))
     g = rng.integers(0, max(C, 2), size=(H, W)).astype(np.uint8)
     assert np.array_equal(oracle.run(g, rule, 3, periodic=periodic), oracle.np_run(g, rule, 3, periodic=periodic))
+
+
+@pytest.mark.parametrize("r", [1, 2, 6])
+def test_gpu_count_sweep_expectations_match_the_oracle(r):
+    """The exhaustive GPU count sweep states its expected next states from the rule notation;
+    here those expectations are checked against the oracle on the same grids."""
+    from test_gpu_bruteforce import count_sweep, sweep_rules, transition
+    for rule in sweep_rules(r):
+        g, s_arr, n_box, nbj, d = count_sweep(r, rule.C, 1000 + r)
+        nxt = oracle.step(g, rule)
+        idx = np.arange(len(s_arr))
+        assert np.array_equal(nxt[(idx // nbj) * d + r, (idx % nbj) * d + r], transition(rule, s_arr, n_box)), rule.text()
