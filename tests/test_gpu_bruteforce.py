@@ -137,3 +137,56 @@ def test_every_count_through_every_epilogue(ltl, r):
                 assert len(bad) == 0, (f"{method} {rule.text()} {'torus' if periodic else 'dead'}: {len(bad)} of "
                                        f"{len(want)} (state, count) blocks wrong, e.g. state {s_arr[bad[0]]} "
                                        f"count {n_box[bad[0]]}: got {got[bad[0]]}, want {want[bad[0]]}")
+
+
+@functools.lru_cache(maxsize=None)
+def cross_sweep(r, C, seed):
+    """Blocks (s, k) for the cross neighbourhood: exactly k alive cells on the 4r arm cells of
+    the centre's row and column, and random alive (or decaying) cells off the cross, which must
+    not count."""
+    d = 2 * r + 1
+    mid = r * d + r
+    arm = np.array([r * d + j for j in range(d) if j != r] + [i * d + r for i in range(d) if i != r])
+    off = np.setdiff1d(np.arange(d * d), np.append(arm, mid))
+    states = [0, 1] + ([2, C - 1] if C >= 3 else [])
+    blocks = [(s, k) for s in states for k in range(4 * r + 1)]
+    nbj = math.ceil(math.sqrt(len(blocks)))
+    nbi = math.ceil(len(blocks) / nbj)
+    g = np.zeros((nbi * d, nbj * d), dtype=np.uint8)
+    rng = np.random.default_rng(seed)
+    for idx, (s, k) in enumerate(blocks):
+        cells = np.zeros(d * d, dtype=np.uint8)
+        cells[off] = rng.integers(0, 2 if C < 3 else C, size=len(off), dtype=np.uint8)
+        pos = rng.permutation(arm)
+        cells[pos[:k]] = 1
+        if C >= 3:
+            cells[pos[k:]] = np.where(rng.random(len(arm) - k) < 0.5, 0, rng.integers(2, C, size=len(arm) - k))
+        cells[mid] = s
+        bi, bj = divmod(idx, nbj)
+        g[bi * d:(bi + 1) * d, bj * d:(bj + 1) * d] = cells.reshape(d, d)
+    s_arr = np.array([b[0] for b in blocks], dtype=np.int64)
+    n_box = np.array([b[1] + (b[0] == 1) for b in blocks], dtype=np.int64)
+    return g, s_arr, n_box, nbj, d
+
+
+def cross_rules(r):
+    n = 4 * r + 1
+    return [inputs.Rule(r, 0, 1, n // 4, n // 2, n // 3, n // 2, "N"), inputs.Rule(r, 0, 0, 1, n - 2, n // 2, n, "N"),
+            inputs.Rule(r, 4, 0, n // 5, (3 * n) // 5, 0, n // 4, "N")]
+
+
+@pytest.mark.parametrize("r", [1, 2, 5, 9, 16])
+def test_every_cross_count(ltl, r):
+    for rule in cross_rules(r):
+        g, s_arr, n_box, nbj, d = cross_sweep(r, rule.C, 2000 + r)
+        want = transition(rule, s_arr, n_box)
+        for method in ("cat_i8", "direct"):
+            sim = ltl.Simulation(torch.from_numpy(g).cuda(), rule, method)
+            sim.step(1)
+            out = sim.read().cpu().numpy()
+            sim.close()
+            idx = np.arange(len(s_arr))
+            got = out[(idx // nbj) * d + r, (idx % nbj) * d + r]
+            bad = np.flatnonzero(got != want)
+            assert len(bad) == 0, (f"{method} {rule.text()}: {len(bad)} of {len(want)} blocks wrong, e.g. state "
+                                   f"{s_arr[bad[0]]} count {n_box[bad[0]]}: got {got[bad[0]]}, want {want[bad[0]]}")

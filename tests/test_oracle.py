@@ -576,3 +576,13 @@ def test_gpu_count_sweep_expectations_match_the_oracle(r):
         nxt = oracle.step(g, rule)
         idx = np.arange(len(s_arr))
         assert np.array_equal(nxt[(idx // nbj) * d + r, (idx % nbj) * d + r], transition(rule, s_arr, n_box)), rule.text()
+
+
+@pytest.mark.parametrize("r", [1, 2, 5])
+def test_gpu_cross_sweep_expectations_match_the_oracle(r):
+    from test_gpu_bruteforce import cross_rules, cross_sweep, transition
+    for rule in cross_rules(r):
+        g, s_arr, n_box, nbj, d = cross_sweep(r, rule.C, 2000 + r)
+        nxt = oracle.step(g, rule)
+        idx = np.arange(len(s_arr))
+        assert np.array_equal(nxt[(idx // nbj) * d + r, (idx % nbj) * d + r], transition(rule, s_arr, n_box)), rule.text()
