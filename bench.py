@@ -348,6 +348,7 @@ def main():
             "method": "cat_i8",
             "tuning": tuning,
             "direct_stencil_cell_updates_per_s": direct_value,
+            "direct_stencil_algorithmic_GBs": 2 * direct_value / 1e9,   # one byte read + one written per cell-update
             "cat_over_direct": value / direct_value,
             "wall_s": wall,
         },
