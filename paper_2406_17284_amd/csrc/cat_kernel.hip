@@ -26,7 +26,9 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) c
     const Codec cd = make_codec();
     cat_tile<ELEM, EPI>(p, tile, lds, tid, lane, wave, nwaves, cd);
 }
-// Streaming form, for grids larger than the caches: one persistent workgroup per CU slot walks
+
+// Persistent form (tuning.persistent = 1), for grids whose tiles stream from HBM: one
+// workgroup per CU slot walks
 // a static sequence of tiles with two LDS buffers, so the next tile's direct loads are in
 // flight while the current tile computes. Workgroup b runs on XCD b mod 8 and takes every gx-th
 // tile (gx = workgroups per XCD) of that XCD's contiguous block of tiles, so the tiles one XCD

@@ -286,14 +286,13 @@ KernelLaunch cat_launch_shape(const CatParams &p, int elem, int epi, int waves, 
 int cat_occupancy(const CatParams &p, int elem, int epi, int waves, int persistent);
 KernelLaunch direct_launch_shape(const DirectParams &p);
 size_t cat_lds_bytes(const CatParams &p, int elem, int epi, int persistent);
-// Batched launches. cat_batch_func: the persistent kernel of an element type (launched with
-// `grid` workgroups of 64 * waves threads and `lds` bytes of dynamic LDS).
+// Batched launches. cat_batch_func: the batch kernel of an element type, launched with one
+// workgroup of 64 * waves threads per work-list entry and the batch's largest dynamic LDS.
 const void *cat_batch_func(int elem);
 int cat_batch_occupancy(int elem, int waves, size_t lds);
 const void *direct_batch_func();
 int direct_tile_rows();
 int direct_tile_cols();
 int direct_threads();
-
 
 }  // namespace ltl
