@@ -293,10 +293,14 @@ class Simulation:
         self.handle = ltl_create(self.H, self.W, rule, method, self.bufs[0].data_ptr(), self.bufs[1].data_ptr(),
                                  nbytes, init.data_ptr(), init.stride(0), self.stream)
         self.device = init.device
-        if boundary != "dead":
-            ltl_set_boundary(self.handle, BOUNDARIES[boundary] if isinstance(boundary, str) else int(boundary))
-        if tuning:
-            ltl_set_tuning(self.handle, **tuning)
+        try:
+            if boundary != "dead":
+                ltl_set_boundary(self.handle, BOUNDARIES[boundary] if isinstance(boundary, str) else int(boundary))
+            if tuning:
+                ltl_set_tuning(self.handle, **tuning)
+        except Exception:
+            self.close()   # a refused boundary or tuning: release the handle before raising
+            raise
 
     def step(self, n: int = 1) -> "Simulation":
         ltl_step(self.handle, n)
@@ -368,7 +372,11 @@ class Batch:
                                        self.arenas[1].data_ptr(), self.nbytes, [g.data_ptr() for g in inits],
                                        [g.stride(0) for g in inits], self.stream)
         if tuning:
-            ltl_batch_set_tuning(self.handle, **tuning)
+            try:
+                ltl_batch_set_tuning(self.handle, **tuning)
+            except Exception:
+                self.close()   # a refused tuning: release the handle before raising
+                raise
 
     def __len__(self) -> int:
         return len(self.H)

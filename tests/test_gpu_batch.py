@@ -96,9 +96,10 @@ def test_batch_tunings(ltl, method, tuning):
     try:
         batch.set_tuning(**tuning)
     except ltl.LtlError as e:
-        # only a shape the kernel cannot run may be refused
-        assert e.code == ltl.LTL_ERR_ARG
-        pytest.skip(f"shape refused: {e}")
+        # only a shape the kernel cannot run may be refused, and only with LTL_ERR_ARG
+        assert e.code == ltl.LTL_ERR_ARG, e
+        batch.close()
+        return
     batch.step(7)
     check_batch(batch, [oracle.run(g, r, 7) for g, r in zip(grids, rules)], f"{method} {tuning}")
     batch.close()

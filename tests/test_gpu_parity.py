@@ -263,7 +263,11 @@ def test_periodic_temporal_blocking(ltl, method, T, r):
     maxc = 5 if method == "cat_f16" else 14
     cell = 2 if method == "cat_f16" else 1
     if not shape_feasible(r, T, 64, 64, maxc=maxc, cell=cell):
-        pytest.skip("launch shape not runnable")
+        # the library must refuse a launch shape it cannot run
+        with pytest.raises(ltl.LtlError) as e:
+            run_periodic(ltl, g0, rule, method, 9, tuning=tuning, every_step=False)
+        assert e.value.code == ltl.LTL_ERR_ARG
+        return
     run_periodic(ltl, g0, rule, method, 9, tuning=tuning, every_step=False)
     # a torus smaller than the loaded window (margins wrap several times)
     run_periodic(ltl, inputs.bernoulli_grid(24, 32, 0.5, seed=301 + r), rule, method, 7, tuning=tuning,
