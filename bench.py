@@ -29,7 +29,7 @@ HBM_PEAK_GBS = 8000.0
 OPS_PER_CELL = 256       # two 16x16x64 int8 MFMAs per 256 cells, 2 ops per multiply-add
 DEFAULT_TUNING = "4,160,224,8"   # steps per launch, tile rows, tile cols, waves
 KERNEL_SRC = [os.path.join(ROOT, "paper_2406_17284_amd", "csrc", f) for f in ("cat_device.h", "cat_kernel.hip")]
-BATCH_TUNING = "2,176,224,8"   # the autotuner's pick for the 512-instance batch on MI355X
+BATCH_TUNING = "3,160,160,8"   # the autotuner's pick for the 512-instance batch on MI355X
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "cat_step_i8_bosco4096_traffic.json")
 MFMA_RECORD = os.path.join(ROOT, "profiles", "cat_step_i8_bosco4096_sq.json")
 

@@ -456,7 +456,9 @@ int32_t batch_autotune(ltl_batch &b, int probe_steps, ltl_tuning_t *best) {
     ltl_tuning_t best_t = b.tuning;
     int32_t rc = LTL_OK;
     for (int T : Ts) {
-        if (T > probe_steps) continue;
+        // each candidate runs a whole number of its own launches (no shorter remainder launch
+        // to bias it) covering at least probe_steps steps; candidates compare per step
+        const int n = T * ((probe_steps + T - 1) / T);
         for (auto &tl : tiles) {
             for (int wv : wavess) {
                 ltl_tuning_t t;
@@ -469,13 +471,14 @@ int32_t batch_autotune(ltl_batch &b, int probe_steps, ltl_tuning_t *best) {
                 if ((rc = batch_prepare(probe)) != LTL_OK) goto done;
                 (void)hipMemcpyAsync(probe.arena[0], b.arena[b.cur], b.arena_bytes, hipMemcpyDeviceToDevice, b.stream);
                 probe.cur = 0;
-                if ((rc = batch_steps(probe, probe_steps)) != LTL_OK) goto done;   // warm-up + graph build
+                if ((rc = batch_steps(probe, n)) != LTL_OK) goto done;   // warm-up + graph build
                 (void)hipEventRecord(ev0, b.stream);
-                if ((rc = batch_steps(probe, probe_steps)) != LTL_OK) goto done;
+                if ((rc = batch_steps(probe, n)) != LTL_OK) goto done;
                 (void)hipEventRecord(ev1, b.stream);
                 if (hipEventSynchronize(ev1) != hipSuccess) { rc = fail(LTL_ERR_HIP, "autotune sync"); goto done; }
                 float ms = 0;
                 (void)hipEventElapsedTime(&ms, ev0, ev1);
+                ms /= (float)n;
                 if (ms < best_ms) { best_ms = ms; best_t = t; }
             }
         }

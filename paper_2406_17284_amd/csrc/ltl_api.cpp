@@ -564,7 +564,9 @@ int32_t ltl_autotune(ltl_sim_t *sim, int32_t probe_steps, ltl_tuning_t *best) {
     ltl_tuning_t best_t = s.tuning;
     int32_t rc = LTL_OK;
     for (int T : Ts) {
-        if (T > probe_steps) continue;
+        // each candidate runs a whole number of its own launches (no shorter remainder launch
+        // to bias it) covering at least probe_steps steps; candidates compare per step
+        const int n = T * ((probe_steps + T - 1) / T);
         for (auto &tl : tiles) {
             for (int wv : wavess) {
               for (int pers = 0; pers < (s.method == LTL_DIRECT ? 1 : 2); ++pers) {
@@ -581,13 +583,14 @@ int32_t ltl_autotune(ltl_sim_t *sim, int32_t probe_steps, ltl_tuning_t *best) {
                 probe.tuning = t;
                 (void)hipMemcpyAsync(scratch[0], s.buf[s.cur], bytes, hipMemcpyDeviceToDevice, s.stream);
                 probe.cur = 0;
-                if ((rc = do_steps(probe, probe_steps)) != LTL_OK) goto done;   // warm-up + graph build
+                if ((rc = do_steps(probe, n)) != LTL_OK) goto done;   // warm-up + graph build
                 (void)hipEventRecord(ev0, s.stream);
-                if ((rc = do_steps(probe, probe_steps)) != LTL_OK) goto done;
+                if ((rc = do_steps(probe, n)) != LTL_OK) goto done;
                 (void)hipEventRecord(ev1, s.stream);
                 if (hipEventSynchronize(ev1) != hipSuccess) { rc = fail(LTL_ERR_HIP, "autotune sync"); goto done; }
                 float ms = 0;
                 (void)hipEventElapsedTime(&ms, ev0, ev1);
+                ms /= (float)n;
                 if (ms < best_ms) { best_ms = ms; best_t = t; }
               }
             }
