@@ -37,6 +37,11 @@
  * Pins (tests): Life still lifes / oscillators / spaceships, brute force over every
  * 3x3 and 5x5 neighbourhood, closed forms of the count, SciPy convolution, the band
  * product of Eq. 2-3, D4 symmetry, M0/M1 equivalence, the decay countdown.
+ *
+ * Parity unpinned: the decay semantics themselves (C >= 3). The paper defines C but prints
+ * no multi-state example, so the reading above is the standard Larger-than-Life one; the
+ * countdown closed form and the decay brute force pin this code to that reading, not the
+ * reading to the paper.
  */
 #include <stdint.h>
 #include <stddef.h>
