@@ -552,3 +552,24 @@ def test_window_epilogue_matches_half_lanes(ltl):
                 ref = got
                 assert np.array_equal(ref, oracle.run(g0, rule, 9)), rule.text()
             assert np.array_equal(got, ref), f"{method} {rule.text()}"
+
+
+# ------------------------------------------------------------------ autotuner on small grids
+@pytest.mark.parametrize("shape,boundary,rule", [
+    ((1, 1), "dead", inputs.BOSCO_M1), ((37, 53), "dead", inputs.BOSCO_M1), ((64, 48), "periodic", inputs.LIFE),
+    ((200, 336), "periodic", inputs.Rule(9, 4, 0, 90, 160, 97, 122)), ((150, 170), "dead", inputs.Rule(20, 0, 1, 300, 700, 320, 500)),
+], ids=lambda x: str(x) if not hasattr(x, "text") else x.text())
+def test_autotune_small_grids(ltl, shape, boundary, rule):
+    """The autotuner (every steps-per-launch, tile, wave count and form it tries) runs on a
+    copy, leaves the state untouched, and its pick computes the oracle's grid."""
+    g0 = (inputs.state_grid(*shape, rule.C, seed=7) if rule.C >= 3 else inputs.bernoulli_grid(*shape, 0.5, seed=7))
+    sim = ltl.Simulation(gpu_grid(g0), rule, "cat_i8", boundary=boundary)
+    sim.step(2)
+    before = sim.read().cpu().numpy()
+    best = sim.autotune(probe_steps=3)
+    assert np.array_equal(sim.read().cpu().numpy(), before)      # the probes ran on a copy
+    assert sim.tuning() == best
+    sim.step(5)
+    got = sim.read().cpu().numpy()
+    sim.close()
+    assert np.array_equal(got, oracle.run(g0, rule, 7, periodic=(boundary == "periodic"))), best
