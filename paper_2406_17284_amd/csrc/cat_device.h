@@ -249,7 +249,9 @@ __device__ __forceinline__ uint32_t pack_f16(float a, float b) {
 // Phase A of one item: H (horizontal band sums) of blocks rb0 - 1 .. rb0 + count for both
 // 16-column halves of the strip, packed, in registers. Software-pipelined in pairs of blocks:
 // the A chunks of the next pair are read from LDS before the MFMAs of this pair run.
-template <int ELEM>
+// FROM_STATES: At holds states (int8 Moore with decay): each chunk's alive bits (state == 1)
+// are derived in registers as it is read.
+template <int ELEM, bool FROM_STATES = false>
 __device__ __forceinline__ void phase_a(const uint8_t *At, uint32_t a_off, uint32_t a_off2, uint32_t PA, int rb0,
                                         int count, const Bands &bd, v16i &Ha, v16i &Hb, v16i &La, v16i &Lb) {
     if constexpr (ELEM == ELEM_I8X) {
@@ -333,7 +335,17 @@ __device__ __forceinline__ void phase_a(const uint8_t *At, uint32_t a_off, uint3
     if constexpr (ELEM == ELEM_I8) {
         const v4i zero = {0, 0, 0, 0};
         v4i a[4];
-#define CAT_LDA(K) a[(K) & 3] = *reinterpret_cast<const v4i *>(At + (a_off + (uint32_t)(16 * (rb0 - 1 + (K))) * PA));
+#define CAT_LDA(K)                                                                                 \
+        {                                                                                          \
+            v4i q = *reinterpret_cast<const v4i *>(At + (a_off + (uint32_t)(16 * (rb0 - 1 + (K))) * PA)); \
+            if constexpr (FROM_STATES) {                                                           \
+                q[0] = (int32_t)alive_of((uint32_t)q[0]);                                          \
+                q[1] = (int32_t)alive_of((uint32_t)q[1]);                                          \
+                q[2] = (int32_t)alive_of((uint32_t)q[2]);                                          \
+                q[3] = (int32_t)alive_of((uint32_t)q[3]);                                          \
+            }                                                                                      \
+            a[(K) & 3] = q;                                                                        \
+        }
 #define CAT_HB(K)                                                                                  \
         {                                                                                          \
             v4i da = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[(K) & 3], bd.op[0], zero, 0, 0, 0);   \
@@ -485,7 +497,8 @@ __device__ __forceinline__ void phase_b(const CatParams &p, uint8_t *Qt, uint8_t
                                         const Codec &cd, const v16i &Ha, const v16i &Hb, const v16i &La,
                                         const v16i &Lb) {
     constexpr int CELL = ElemT<ELEM>::CELL;
-    constexpr bool SEPARATE = (EPI == EPI_DECAY) || (ELEM == ELEM_F16);   // Q and A are distinct tiles
+    // Q and A are distinct tiles (int8 Moore decay reads its alive bits from Q)
+    constexpr bool SEPARATE = (ELEM == ELEM_F16) || (EPI == EPI_DECAY && ELEM != ELEM_I8);
     const uint32_t PS = (uint32_t)p.PS, PA = (uint32_t)p.PA;
     v4i ca[4], cb[4];
     uint32_t sa[4], sb[4];
@@ -535,7 +548,10 @@ __device__ __forceinline__ void phase_b(const CatParams &p, uint8_t *Qt, uint8_t
                 *reinterpret_cast<uint32_t *>(Qt + qo) = na;                                       \
                 *reinterpret_cast<uint32_t *>(Qt + qo + 16) = nb;                                  \
             }                                                                                      \
-            if constexpr (kIsI8<ELEM>) {                                                           \
+            if constexpr (ELEM == ELEM_I8 && EPI == EPI_DECAY) {                                   \
+                (void)ala;   /* int8 Moore decay: the alive bits are derived from Q when read */    \
+                (void)alb;                                                                         \
+            } else if constexpr (kIsI8<ELEM>) {   /* (two-state rules: the state itself) */        \
                 *reinterpret_cast<uint32_t *>(At + ao) = ala;                                      \
                 *reinterpret_cast<uint32_t *>(At + ao + 16) = alb;                                 \
             } else if constexpr (ELEM == ELEM_F8) {                                                \
@@ -619,7 +635,8 @@ __device__ __forceinline__ void cat_steps(const CatParams &p, uint8_t *Qt, uint8
         LaneOff lo;
         lo.q = (uint32_t)((L + li) * (int)PS + (L + j0 + 4 * lg));
         lo.a = (uint32_t)((L + li) * (int)PA + (L + j0 + 4 * lg) * CELL);
-        if (count > 0) phase_a<ELEM>(At, a_off, a_off2, PA, rb0, count, bd, Ha, Hb, La, Lb);
+        if (count > 0)
+            phase_a<ELEM, ELEM == ELEM_I8 && EPI == EPI_DECAY>(At, a_off, a_off2, PA, rb0, count, bd, Ha, Hb, La, Lb);
         if (!last) __syncthreads();   // every read of the old states precedes any in-place write
         if (count > 0) {
             const int gca = gj0 + j0 + 4 * lg;
@@ -713,7 +730,7 @@ template <int ELEM, int EPI>
 __device__ __forceinline__ void tile_steps(const CatParams &p, int gi0, int gj0, uint8_t *Qt, uint8_t *At, int tid,
                                            int lane, int wave, int nwaves, const Bands &bd, const Codec &cd) {
     // alive map from the loaded states (int8 without decay reads the states directly)
-    if constexpr (!(kIsI8<ELEM> && EPI != EPI_DECAY)) {
+    if constexpr (!(kIsI8<ELEM> && (EPI != EPI_DECAY || ELEM == ELEM_I8))) {
         const int W2 = p.TW + 2 * p.L;          // window columns (the PS - W2 pad is never read)
         const int vpr = W2 >> 4;
         const int nvec = (p.TH + 2 * p.L) * vpr;

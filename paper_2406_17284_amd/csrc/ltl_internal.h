@@ -229,7 +229,8 @@ inline void cat_lds_layout(int elem, int epi, int TH, int TW, int L, int *PS, in
     const int rows = TH + 2 * L;
     *PS = TW + 2 * L + 16;
     *lds_tile = roundup(rows * *PS, 1024);
-    const bool separate = (epi == EPI_DECAY) || (elem == ELEM_F16);
+    // int8 Moore decay derives the alive bits from the states as it reads them (no second tile)
+    const bool separate = (elem == ELEM_F16) || (epi == EPI_DECAY && elem != ELEM_I8);
     *PA = cat_cell_bytes(elem) * (TW + 2 * L) + 16;
     *a_tile = separate ? *lds_tile : 0;
     *lds_total = *lds_tile + (separate ? roundup(rows * *PA, 1024) : 0);
