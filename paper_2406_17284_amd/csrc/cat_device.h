@@ -164,7 +164,7 @@ template <> struct ElemT<ELEM_I8X> { static constexpr int CELL = 1, MAXC = CAT_M
 // int8 element types (0/1 bytes, the state tile is the alive map for two-state rules)
 template <int ELEM> constexpr bool kIsI8 = (ELEM == ELEM_I8 || ELEM == ELEM_I8W || ELEM == ELEM_I8X);
 template <> struct ElemT<ELEM_F8> { static constexpr int CELL = 1, MAXC = CAT_MAXC_F8, NOPS = 8; };
-template <> struct ElemT<ELEM_F16> { static constexpr int CELL = 2, MAXC = CAT_MAXC_F16, NOPS = 6; };
+template <> struct ElemT<ELEM_F16> { static constexpr int CELL = 1, MAXC = CAT_MAXC_F16, NOPS = 6; };
 
 struct Codec {
     uint32_t one8;   // fp8 encoding of 1.0 (byte), as the hardware converts it
@@ -188,10 +188,6 @@ __device__ __forceinline__ uint2 enc16(uint32_t alive) {
     uint32_t lo = __builtin_amdgcn_perm(0u, alive, 0x0c010c00u);   // bytes 0, 1 -> 16-bit lanes
     uint32_t hi = __builtin_amdgcn_perm(0u, alive, 0x0c030c02u);
     return make_uint2(__umul24(lo, 0x3C00u), __umul24(hi, 0x3C00u));
-}
-// four fp16 (0 / 1.0) -> alive bytes: the high byte of 1.0 is 0x3C, whose bit 2 is set
-__device__ __forceinline__ uint32_t dec16(uint32_t lo, uint32_t hi) {
-    return (__builtin_amdgcn_perm(hi, lo, 0x07050301u) >> 2) & 0x01010101u;
 }
 
 // Geometry of one step: strips of 32 columns, each cut into `nseg` row segments of at most
@@ -401,14 +397,22 @@ __device__ __forceinline__ void phase_a(const uint8_t *At, uint32_t a_off, uint3
 #undef CAT_HB
 #undef CAT_LDA
     } else {
-        // fp16: two K = 32 chunks (8 halves = 16 bytes per lane each, 64 bytes apart)
+        // fp16: two K = 32 chunks of 8 cells (32 columns apart), read as state bytes from the
+        // one tile and expanded in registers to fp16 0 / 1.0 (alive: state == 1)
         const v4f zf = {0.f, 0.f, 0.f, 0.f};
         v4i a0[4], a1[4];
 #define CAT_LDA(K)                                                                                 \
         {                                                                                          \
             const uint8_t *q = At + (a_off + (uint32_t)(16 * (rb0 - 1 + (K))) * PA);               \
-            a0[(K) & 3] = *reinterpret_cast<const v4i *>(q);                                       \
-            a1[(K) & 3] = *reinterpret_cast<const v4i *>(q + 64);                                  \
+            uint2 s0 = *reinterpret_cast<const uint2 *>(q);                                        \
+            uint2 s1 = *reinterpret_cast<const uint2 *>(q + 32);                                   \
+            if constexpr (FROM_STATES) {                                                           \
+                s0 = make_uint2(alive_of(s0.x), alive_of(s0.y));                                   \
+                s1 = make_uint2(alive_of(s1.x), alive_of(s1.y));                                   \
+            }                                                                                      \
+            const uint2 e00 = enc16(s0.x), e01 = enc16(s0.y), e10 = enc16(s1.x), e11 = enc16(s1.y); \
+            a0[(K) & 3] = v4i{(int32_t)e00.x, (int32_t)e00.y, (int32_t)e01.x, (int32_t)e01.y};     \
+            a1[(K) & 3] = v4i{(int32_t)e10.x, (int32_t)e10.y, (int32_t)e11.x, (int32_t)e11.y};     \
         }
 #define CAT_HB(K)                                                                                  \
         {                                                                                          \
@@ -498,7 +502,7 @@ __device__ __forceinline__ void phase_b(const CatParams &p, uint8_t *Qt, uint8_t
                                         const v16i &Lb) {
     constexpr int CELL = ElemT<ELEM>::CELL;
     // Q and A are distinct tiles (int8 Moore decay reads its alive bits from Q)
-    constexpr bool SEPARATE = (ELEM == ELEM_F16) || (EPI == EPI_DECAY && ELEM != ELEM_I8);
+    constexpr bool SEPARATE = EPI == EPI_DECAY && ELEM != ELEM_I8 && ELEM != ELEM_F16;
     const uint32_t PS = (uint32_t)p.PS, PA = (uint32_t)p.PA;
     v4i ca[4], cb[4];
     uint32_t sa[4], sb[4];
@@ -509,20 +513,14 @@ __device__ __forceinline__ void phase_b(const CatParams &p, uint8_t *Qt, uint8_t
     {                                                                                              \
         ca[(M) & 3] = vproduct<ELEM, (M)>(Ha, La, bd, acc0);                                       \
         cb[(M) & 3] = vproduct<ELEM, (M)>(Hb, Lb, bd, acc0);                                       \
-        if constexpr (EPI == EPI_DECAY || kIsI8<ELEM>) {                                           \
+        if constexpr (EPI == EPI_DECAY || kIsI8<ELEM> || ELEM == ELEM_F16) {                       \
             const uint32_t qo = lo.q + (uint32_t)(16 * (rb0 + (M))) * PS;                          \
             sa[(M) & 3] = *reinterpret_cast<const uint32_t *>(Qt + qo);                            \
             sb[(M) & 3] = *reinterpret_cast<const uint32_t *>(Qt + qo + 16);                       \
-        } else if constexpr (ELEM == ELEM_F8) {                                                    \
+        } else {   /* fp8 without decay: states decoded from its encoding */                      \
             const uint32_t ao = lo.a + (uint32_t)(16 * (rb0 + (M))) * PA;                          \
             sa[(M) & 3] = dec8(*reinterpret_cast<const uint32_t *>(At + ao), cd);                  \
             sb[(M) & 3] = dec8(*reinterpret_cast<const uint32_t *>(At + ao + 16), cd);             \
-        } else {                                                                                   \
-            const uint32_t ao = lo.a + (uint32_t)(16 * (rb0 + (M))) * PA;                          \
-            const uint2 xa = *reinterpret_cast<const uint2 *>(At + ao);                            \
-            const uint2 xb = *reinterpret_cast<const uint2 *>(At + ao + 32);                       \
-            sa[(M) & 3] = dec16(xa.x, xa.y);                                                       \
-            sb[(M) & 3] = dec16(xb.x, xb.y);                                                       \
         }                                                                                          \
     }
     // transition and store of block M
@@ -548,18 +546,15 @@ __device__ __forceinline__ void phase_b(const CatParams &p, uint8_t *Qt, uint8_t
                 *reinterpret_cast<uint32_t *>(Qt + qo) = na;                                       \
                 *reinterpret_cast<uint32_t *>(Qt + qo + 16) = nb;                                  \
             }                                                                                      \
-            if constexpr (ELEM == ELEM_I8 && EPI == EPI_DECAY) {                                   \
-                (void)ala;   /* int8 Moore decay: the alive bits are derived from Q when read */    \
+            if constexpr ((ELEM == ELEM_I8 || ELEM == ELEM_F16) && EPI == EPI_DECAY) {             \
+                (void)ala;   /* int8 Moore and fp16 decay derive the alive bits from Q when read */ \
                 (void)alb;                                                                         \
-            } else if constexpr (kIsI8<ELEM>) {   /* (two-state rules: the state itself) */        \
+            } else if constexpr (kIsI8<ELEM> || ELEM == ELEM_F16) {   /* two-state: the state */   \
                 *reinterpret_cast<uint32_t *>(At + ao) = ala;                                      \
                 *reinterpret_cast<uint32_t *>(At + ao + 16) = alb;                                 \
-            } else if constexpr (ELEM == ELEM_F8) {                                                \
+            } else {   /* fp8: its encoding of 1.0 */                                              \
                 *reinterpret_cast<uint32_t *>(At + ao) = enc8(ala, cd);                            \
                 *reinterpret_cast<uint32_t *>(At + ao + 16) = enc8(alb, cd);                       \
-            } else {                                                                               \
-                *reinterpret_cast<uint2 *>(At + ao) = enc16(ala);                                  \
-                *reinterpret_cast<uint2 *>(At + ao + 32) = enc16(alb);                             \
             }                                                                                      \
         }                                                                                          \
     }
@@ -636,7 +631,8 @@ __device__ __forceinline__ void cat_steps(const CatParams &p, uint8_t *Qt, uint8
         lo.q = (uint32_t)((L + li) * (int)PS + (L + j0 + 4 * lg));
         lo.a = (uint32_t)((L + li) * (int)PA + (L + j0 + 4 * lg) * CELL);
         if (count > 0)
-            phase_a<ELEM, ELEM == ELEM_I8 && EPI == EPI_DECAY>(At, a_off, a_off2, PA, rb0, count, bd, Ha, Hb, La, Lb);
+            phase_a<ELEM, (ELEM == ELEM_I8 || ELEM == ELEM_F16) && EPI == EPI_DECAY>(At, a_off, a_off2, PA, rb0, count,
+                                                                                   bd, Ha, Hb, La, Lb);
         if (!last) __syncthreads();   // every read of the old states precedes any in-place write
         if (count > 0) {
             const int gca = gj0 + j0 + 4 * lg;
@@ -729,8 +725,10 @@ __device__ __forceinline__ Bands load_bands(const CatParams &p, int lane, const 
 template <int ELEM, int EPI>
 __device__ __forceinline__ void tile_steps(const CatParams &p, int gi0, int gj0, uint8_t *Qt, uint8_t *At, int tid,
                                            int lane, int wave, int nwaves, const Bands &bd, const Codec &cd) {
-    // alive map from the loaded states (int8 without decay reads the states directly)
-    if constexpr (!(kIsI8<ELEM> && (EPI != EPI_DECAY || ELEM == ELEM_I8))) {
+    // alive map from the loaded states, where a kernel keeps one: fp8 (its encoding of 1.0, in
+    // place) and the int8 wide and cross elements with decay (a second tile). int8 Moore and
+    // fp16 read the states and derive the alive bits in registers.
+    if constexpr (ELEM == ELEM_F8 || ((ELEM == ELEM_I8W || ELEM == ELEM_I8X) && EPI == EPI_DECAY)) {
         const int W2 = p.TW + 2 * p.L;          // window columns (the PS - W2 pad is never read)
         const int vpr = W2 >> 4;
         const int nvec = (p.TH + 2 * p.L) * vpr;
@@ -743,14 +741,9 @@ __device__ __forceinline__ void tile_steps(const CatParams &p, int gi0, int gj0,
                 al = make_uint4(alive_of(q.x), alive_of(q.y), alive_of(q.z), alive_of(q.w));
             if constexpr (kIsI8<ELEM>) {
                 *reinterpret_cast<uint4 *>(At + row * p.PA + col) = al;
-            } else if constexpr (ELEM == ELEM_F8) {
+            } else {
                 *reinterpret_cast<uint4 *>(At + row * p.PA + col) =
                     make_uint4(enc8(al.x, cd), enc8(al.y, cd), enc8(al.z, cd), enc8(al.w, cd));
-            } else {
-                uint2 e0 = enc16(al.x), e1 = enc16(al.y), e2 = enc16(al.z), e3 = enc16(al.w);
-                uint8_t *d = At + row * p.PA + 2 * col;
-                *reinterpret_cast<uint4 *>(d) = make_uint4(e0.x, e0.y, e1.x, e1.y);
-                *reinterpret_cast<uint4 *>(d + 16) = make_uint4(e2.x, e2.y, e3.x, e3.y);
             }
         }
         __syncthreads();

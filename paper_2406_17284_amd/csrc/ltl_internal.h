@@ -201,7 +201,7 @@ inline int cat_maxc(int elem) {
     return elem == ELEM_F16 ? CAT_MAXC_F16 : elem == ELEM_F8 ? CAT_MAXC_F8 : elem == ELEM_I8W ? CAT_MAXC_I8W
          : elem == ELEM_I8X ? CAT_MAXC_I8X : CAT_MAXC_I8;
 }
-inline int cat_cell_bytes(int elem) { return elem == ELEM_F16 ? 2 : 1; }
+inline int cat_cell_bytes(int elem) { (void)elem; return 1; }   // every element reads state bytes
 
 // Whether a launch shape can run: in every step of a T-step launch the strips x segments
 // must not outnumber the waves (each wave keeps one item's H blocks in registers across the
@@ -229,8 +229,8 @@ inline void cat_lds_layout(int elem, int epi, int TH, int TW, int L, int *PS, in
     const int rows = TH + 2 * L;
     *PS = TW + 2 * L + 16;
     *lds_tile = roundup(rows * *PS, 1024);
-    // int8 Moore decay derives the alive bits from the states as it reads them (no second tile)
-    const bool separate = (elem == ELEM_F16) || (epi == EPI_DECAY && elem != ELEM_I8);
+    // int8 Moore and fp16 derive the alive bits from the states as they read them (no second tile)
+    const bool separate = epi == EPI_DECAY && elem != ELEM_I8 && elem != ELEM_F16;
     *PA = cat_cell_bytes(elem) * (TW + 2 * L) + 16;
     *a_tile = separate ? *lds_tile : 0;
     *lds_total = *lds_tile + (separate ? roundup(rows * *PA, 1024) : 0);

@@ -108,17 +108,16 @@ def test_shapes(ltl, shape, method):
 
 
 def shape_feasible(r, T, TH, TW, waves=8, maxc=14, cell=1, lds_max=160 * 1024):
-    """Whether the CAT kernel can run this launch shape: the LDS tiles fit and in every step the
-    32-column strips times the row segments (at most `maxc` 16-row blocks) fit the waves.
-    int8 above r = 16 reads two more H blocks per segment (11 output blocks, margin + 32)."""
+    """Whether the CAT kernel can run this launch shape: the LDS state tile fits and in every
+    step the 32-column strips times the row segments (at most `maxc` 16-row blocks) fit the
+    waves. int8 above r = 16 reads two more H blocks per segment (11 output blocks, margin
+    + 32); cell = 2 marks fp16, which has no wide variant."""
     wide = r > 16 and cell == 1 and maxc == 14
     if wide:
         maxc = 9
     margin = -(-r * (T - 1) // 16) * 16 + (48 if wide else 16)
     rows, cols = TH + 2 * margin, TW + 2 * margin
     lds = -(-rows * (cols + 16) // 1024) * 1024
-    if cell == 2:   # fp16: a second tile holds the alive map, two bytes per cell
-        lds += -(-rows * (2 * cols + 16) // 1024) * 1024
     if lds > lds_max:
         return False
     for t in range(1, T + 1):
