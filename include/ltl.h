@@ -72,7 +72,7 @@ typedef struct {
     int32_t steps_per_launch; /* T >= 1 time steps fused in one kernel launch (temporal blocking) */
     int32_t tile_rows;        /* output rows per workgroup: multiple of 16, 16..512 */
     int32_t tile_cols;        /* output columns per workgroup: multiple of 32, 32..512 */
-    int32_t waves;            /* 64-lane waves per workgroup: 1..16 */
+    int32_t waves;            /* 64-lane waves per workgroup: 1..8 (CAT), 1..16 (direct) */
     int32_t use_graph;        /* 1: replay multi-launch loops from a cached hipGraph */
     int32_t persistent;       /* CAT methods, single grid: 1 = persistent workgroups (about one per
                                  CU slot) that each walk a contiguous run of tiles, loading tile
@@ -111,7 +111,8 @@ int32_t ltl_create(ltl_sim_t **out, int32_t H, int32_t W, const ltl_rule_t *rule
                    hipStream_t stream);
 
 /* Enqueue n_steps >= 0 synchronous steps. ltl_step(a); ltl_step(b) equals ltl_step(a + b)
- * cell for cell. */
+ * cell for cell. With use_graph, the steps run as replays of cached hipGraphs of at most 64
+ * launches each (steps_per_launch x 64 steps); the first call with a new length builds them. */
 int32_t ltl_step(ltl_sim_t *sim, int32_t n_steps);
 
 /* Enqueue a copy of the current H x W states into device memory dst (row pitch dst_pitch >= W). */

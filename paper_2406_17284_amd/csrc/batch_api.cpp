@@ -395,8 +395,7 @@ int32_t batch_build_graph(ltl_batch &b, int n, hipGraphExec_t *out) {
     return LTL_OK;
 }
 
-int32_t batch_steps(ltl_batch &b, int32_t n) {
-    if (n == 0) return LTL_OK;
+int32_t batch_chunk(ltl_batch &b, int32_t n) {
     std::vector<int> sizes = batch_sizes(b, n);
     if (b.tuning.use_graph && sizes.size() > 1) {
         auto key = std::make_pair(n, b.cur);
@@ -423,6 +422,18 @@ int32_t batch_steps(ltl_batch &b, int32_t n) {
         }
     }
     b.steps_done += n;
+    return LTL_OK;
+}
+
+int32_t batch_steps(ltl_batch &b, int32_t n) {
+    const int T = (b.method == LTL_DIRECT) ? 1 : b.tuning.steps_per_launch;
+    const int32_t chunk = T * kMaxChunkLaunches;
+    while (n > 0) {
+        const int32_t m = std::min(n, chunk);
+        int32_t rc = batch_chunk(b, m);
+        if (rc != LTL_OK) return rc;
+        n -= m;
+    }
     return LTL_OK;
 }
 

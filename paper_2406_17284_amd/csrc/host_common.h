@@ -40,6 +40,11 @@ size_t max_lds_bytes();
 // Element type of the band products for a method, radius and neighbourhood code.
 int elem_of(int method, int R, int N);
 
+// Launches per step chunk: a call of n steps runs as chunks of at most this many launches,
+// each one cached hipGraph (or that many plain launches), so the graph size and the host
+// vectors stay bounded whatever n is.
+constexpr int kMaxChunkLaunches = 64;
+
 // Bytes of one band table (LTL_BAND_OPS operands x 64 lanes x 16 bytes).
 constexpr size_t kBandBytes = LTL_BAND_TABLE_INTS * sizeof(int32_t);
 

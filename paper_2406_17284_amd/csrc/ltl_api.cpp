@@ -268,7 +268,7 @@ int32_t check_tuning(const ltl_sim &s, const ltl_tuning_t &t) {
     if (t.steps_per_launch < 1 || t.steps_per_launch > 64) return fail(LTL_ERR_ARG, "steps_per_launch must be in 1..64");
     if (t.tile_rows < 16 || t.tile_rows > 512 || t.tile_rows % 16) return fail(LTL_ERR_ARG, "tile_rows must be a multiple of 16 in 16..512");
     if (t.tile_cols < 32 || t.tile_cols > 512 || t.tile_cols % 32) return fail(LTL_ERR_ARG, "tile_cols must be a multiple of 32 in 32..512");
-    if (t.waves < 1 || t.waves > (s.method == LTL_DIRECT ? 16 : 8)) return fail(LTL_ERR_ARG, "waves must be in 1..8");
+    if (t.waves < 1 || t.waves > (s.method == LTL_DIRECT ? 16 : 8)) return fail(LTL_ERR_ARG, "waves must be in 1..8 (1..16 for the direct method)");
     if (s.method != LTL_DIRECT) {
         CatParams p = cat_params(s, t, t.steps_per_launch, nullptr, nullptr);
         size_t lds = cat_lds_bytes(p, elem_of(s.method, s.rule.R, s.rule.N), s.epi, t.persistent);
@@ -371,8 +371,7 @@ int32_t build_graph(ltl_sim &s, int n, int from, hipGraphExec_t *out) {
     return LTL_OK;
 }
 
-int32_t do_steps(ltl_sim &s, int32_t n) {
-    if (n == 0) return LTL_OK;
+int32_t do_chunk(ltl_sim &s, int32_t n) {
     std::vector<int> sizes = launch_sizes(s, n);
     if (s.tuning.use_graph && sizes.size() > 1) {
         auto key = std::make_pair(n, s.cur);
@@ -396,6 +395,18 @@ int32_t do_steps(ltl_sim &s, int32_t n) {
         }
     }
     s.steps_done += n;
+    return LTL_OK;
+}
+
+int32_t do_steps(ltl_sim &s, int32_t n) {
+    const int T = (s.method == LTL_DIRECT) ? 1 : s.tuning.steps_per_launch;
+    const int32_t chunk = T * kMaxChunkLaunches;
+    while (n > 0) {
+        const int32_t m = std::min(n, chunk);
+        int32_t rc = do_chunk(s, m);
+        if (rc != LTL_OK) return rc;
+        n -= m;
+    }
     return LTL_OK;
 }
 
@@ -559,7 +570,7 @@ int32_t ltl_autotune(ltl_sim_t *sim, int32_t probe_steps, ltl_tuning_t *best) {
     const int Ts[] = {1, 2, 3, 4, 5, 6, 8};
     const int tiles[][2] = {{64, 64}, {96, 96}, {128, 128}, {128, 192}, {160, 160}, {192, 128}, {192, 192},
                             {192, 224}, {128, 224}, {160, 224}, {176, 224}, {224, 224}, {64, 128}, {128, 96}};
-    const int wavess[] = {0, 8, 16};  // 0: fewest waves that fit every step
+    const int wavess[] = {0, 8};  // 0: fewest waves that fit every step
     float best_ms = 1e30f;
     ltl_tuning_t best_t = s.tuning;
     int32_t rc = LTL_OK;
@@ -569,7 +580,7 @@ int32_t ltl_autotune(ltl_sim_t *sim, int32_t probe_steps, ltl_tuning_t *best) {
         const int n = T * ((probe_steps + T - 1) / T);
         for (auto &tl : tiles) {
             for (int wv : wavess) {
-              for (int pers = 0; pers < (s.method == LTL_DIRECT ? 1 : 2); ++pers) {
+              for (int pers = 0; pers < 2; ++pers) {
                 ltl_tuning_t t;
                 t.steps_per_launch = T; t.tile_rows = tl[0]; t.tile_cols = tl[1]; t.waves = wv; t.use_graph = 1;
                 t.persistent = pers;

@@ -263,13 +263,47 @@ def ltl_batch_destroy(batch: int) -> None:
 
 
 # ------------------------------------------------------------ torch-owned memory
+def _torch_stream(stream, device):
+    """The stream the library enqueues on, as a torch stream (default: the current one)."""
+    import torch
+
+    if stream is None:
+        return torch.cuda.current_stream(device)
+    if isinstance(stream, int):
+        return torch.cuda.ExternalStream(stream, device=device)
+    return stream
+
+
+def _join_current(stream, device, tensors) -> None:
+    """Order `stream` after torch's current stream (where `tensors` were made or written) and
+    keep their memory alive until the work `stream` has queued on them is done."""
+    import torch
+
+    cur = torch.cuda.current_stream(device)
+    if stream.cuda_stream != cur.cuda_stream:
+        stream.wait_stream(cur)
+        for t in tensors:
+            t.record_stream(stream)
+
+
+def _check_out(out, H: int, W: int, device) -> None:
+    import torch
+
+    if (out.device != device or out.dtype != torch.uint8 or tuple(out.shape) != (H, W) or out.stride(1) != 1
+            or (H > 1 and out.stride(0) < W)):
+        raise ValueError(f"out must be a uint8 tensor of shape ({H}, {W}) on {device} with rows of unit "
+                         "column stride that do not overlap")
+
+
 class Simulation:
     """One automaton whose two ping-pong buffers are torch uint8 tensors on the GPU.
 
     init      2-D uint8 CUDA tensor of states (each < max(C, 2)); copied at creation.
     rule      an ``inputs.Rule`` or anything with R, C, M, S1, S2, B1, B2 (and N) attributes.
     method    "cat_i8" | "cat_f16" | "cat_f8" | "direct" (or the ltl_method_t value).
-    stream    torch stream the library enqueues on (default: the current stream).
+    stream    torch stream (or raw HIP stream handle) the library enqueues on (default: the
+              current stream); it is ordered after the current stream where it reads tensors
+              made there (``init``, a default ``out``).
     tuning    launch shape, the ltl_tuning_t fields as keywords: steps_per_launch, tile_rows,
               tile_cols, waves, use_graph, persistent (0 = library default for the first four).
     boundary  "dead" (ghost halo of dead cells) or "periodic" (torus; W must be a multiple of 16).
@@ -286,10 +320,11 @@ class Simulation:
             raise ValueError("init must be a 2-D uint8 CUDA tensor")
         init = init.contiguous()
         self.H, self.W = int(init.shape[0]), int(init.shape[1])
-        self.stream = stream if stream is not None else torch.cuda.current_stream(init.device)
+        self.stream = _torch_stream(stream, init.device)
         nbytes = ltl_buffer_bytes(self.H, self.W)
         # 256-byte aligned: torch's caching allocator hands out 512-byte aligned blocks
         self.bufs = [torch.empty(nbytes, dtype=torch.uint8, device=init.device) for _ in range(2)]
+        _join_current(self.stream, init.device, [init] + self.bufs)
         self.handle = ltl_create(self.H, self.W, rule, method, self.bufs[0].data_ptr(), self.bufs[1].data_ptr(),
                                  nbytes, init.data_ptr(), init.stride(0), self.stream)
         self.device = init.device
@@ -311,6 +346,8 @@ class Simulation:
 
         if out is None:
             out = torch.empty((self.H, self.W), dtype=torch.uint8, device=self.device)
+        _check_out(out, self.H, self.W, self.device)
+        _join_current(self.stream, self.device, [out])
         ltl_read(self.handle, out.data_ptr(), out.stride(0))
         return out
 
@@ -365,9 +402,10 @@ class Batch:
         self.device = inits[0].device
         self.H = [int(g.shape[0]) for g in inits]
         self.W = [int(g.shape[1]) for g in inits]
-        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.stream = _torch_stream(stream, self.device)
         self.nbytes = ltl_batch_buffer_bytes(self.H, self.W)
         self.arenas = [torch.empty(self.nbytes, dtype=torch.uint8, device=self.device) for _ in range(2)]
+        _join_current(self.stream, self.device, list(inits) + self.arenas)
         self.handle = ltl_batch_create(self.H, self.W, rules, method, self.arenas[0].data_ptr(),
                                        self.arenas[1].data_ptr(), self.nbytes, [g.data_ptr() for g in inits],
                                        [g.stride(0) for g in inits], self.stream)
@@ -390,6 +428,8 @@ class Batch:
 
         if out is None:
             out = torch.empty((self.H[index], self.W[index]), dtype=torch.uint8, device=self.device)
+        _check_out(out, self.H[index], self.W[index], self.device)
+        _join_current(self.stream, self.device, [out])
         ltl_batch_read(self.handle, index, out.data_ptr(), out.stride(0))
         return out
 

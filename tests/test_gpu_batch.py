@@ -119,6 +119,21 @@ def test_batch_resume_and_graph(ltl):
             batch.close()
 
 
+def test_batch_long_run_spans_several_step_chunks(ltl):
+    """140 one-step launches run as chunks of at most 64 launches (64 + 64 + 12), each a cached
+    graph; with and without graphs, and split across calls, every instance equals the oracle."""
+    grids, rules = small_batch(6, max_r=4)
+    refs = [oracle.run(g, r, 140) for g, r in zip(grids, rules)]
+    for use_graph, chunks in ((1, [140]), (0, [140]), (1, [70, 70])):
+        batch = ltl.Batch([gpu_grid(g) for g in grids], rules, "cat_i8",
+                          tuning=dict(steps_per_launch=1, use_graph=use_graph))
+        for n in chunks:
+            batch.step(n)
+        assert batch.steps_done == 140
+        check_batch(batch, refs, f"graph={use_graph} chunks={chunks}")
+        batch.close()
+
+
 def test_batch_single_instance_equals_simulation(ltl):
     g = inputs.bernoulli_grid(300, 500, 0.5, seed=77)
     rule = inputs.BOSCO_M1

@@ -186,6 +186,55 @@ def test_resume_and_graph_chunks(ltl):
     run_and_compare(ltl, g0, rule, "cat_i8", 17, tuning=dict(tuning, use_graph=0), chunks=[5, 12])
 
 
+@pytest.mark.parametrize("method", ["cat_i8", "direct"])
+def test_long_runs_span_several_step_chunks(ltl, method):
+    """A call runs as chunks of at most 64 launches (one cached graph each): 150 one-step launches
+    (64 + 64 + 22) and 197 steps at three per launch (192 + 5), with and without graphs and split
+    across calls, equal the oracle."""
+    rule = inputs.BOSCO_M1
+    g0 = inputs.bernoulli_grid(128, 150, 0.5, seed=83)
+    T = 1 if method == "direct" else 3
+    n = 150 if T == 1 else 197
+    base = dict(steps_per_launch=T) if method == "direct" else dict(steps_per_launch=T, tile_rows=64, tile_cols=64)
+    for use_graph in (1, 0):
+        run_and_compare(ltl, g0, rule, method, n, tuning=dict(base, use_graph=use_graph))
+    run_and_compare(ltl, g0, rule, method, n, tuning=dict(base, use_graph=1), chunks=[130, n - 130])
+    if method == "cat_i8":
+        run_and_compare(ltl, g0, rule, method, 150, tuning=dict(base, steps_per_launch=1, use_graph=1))
+
+
+def test_side_stream_and_read_into(ltl):
+    """A handle on its own stream, created from a non-contiguous tensor (the binding's contiguous
+    copy is made on the current stream), reads into a caller's tensor; a tensor of the wrong
+    shape, type or layout is refused before any copy."""
+    rule = inputs.BOSCO_M1
+    g0 = inputs.bernoulli_grid(150, 130, 0.5, seed=91)
+    src = gpu_grid(np.ascontiguousarray(g0.T)).t()          # g0 as a transposed view
+    assert not src.is_contiguous()
+    side = torch.cuda.Stream()
+    sim = ltl.Simulation(src, rule, "cat_i8", stream=side)
+    sim.step(7)
+    out = torch.full((150, 130), 255, dtype=torch.uint8, device="cuda")
+    assert sim.read(out) is out
+    side.synchronize()
+    assert np.array_equal(out.cpu().numpy(), oracle.run(g0, rule, 7))
+    for bad in (torch.empty((150, 129), dtype=torch.uint8, device="cuda"),
+                torch.empty((150, 130), dtype=torch.int32, device="cuda"),
+                torch.empty((130, 150), dtype=torch.uint8, device="cuda").t(),
+                torch.empty((150, 130), dtype=torch.uint8)):
+        with pytest.raises(ValueError):
+            sim.read(bad)
+    sim.close()
+    batch = ltl.Batch([gpu_grid(g0)], [rule], "cat_i8", stream=side)
+    batch.step(7)
+    with pytest.raises(ValueError):
+        batch.read(0, torch.empty((150, 131), dtype=torch.uint8, device="cuda"))
+    out2 = batch.read(0)
+    side.synchronize()
+    assert torch.equal(out2, out)
+    batch.close()
+
+
 def test_life_256_every_step(ltl):
     w = inputs.WORKLOADS["life256"]
     g0 = inputs.bernoulli_grid(w.H, w.W, w.p, w.seed)
