@@ -199,6 +199,24 @@ def test_count_matches_scipy_convolution(r):
     assert np.array_equal(oracle.count(g, r), ref)
 
 
+@pytest.mark.parametrize("r", [1, 6, 16, 32])
+@pytest.mark.parametrize("periodic", [False, True])
+def test_count_is_additive_over_disjoint_alive_sets(r, periodic):
+    """The count is linear in the alive map (Eq. 2-3 are matrix products): split the cells of a
+    grid into two disjoint grids and the counts add. A clamp, a saturating or too narrow
+    accumulator, or any term that depends on two cells at once breaks it."""
+    rng = np.random.default_rng(100 + r)
+    g = rng.integers(0, 4, size=(57, 96)).astype(np.uint8)   # states 0..3: only 1 is alive
+    part = rng.random(g.shape) < 0.5
+    a = np.where(part, g, 0).astype(np.uint8)
+    b = np.where(part, 0, g).astype(np.uint8)
+    for count in (oracle.count, oracle.np_count):
+        for cross in (False, True):
+            whole, pa, pb = (count(x, r, periodic=periodic, cross=cross) for x in (g, a, b))
+            assert pa.any() and pb.any()
+            assert np.array_equal(whole, pa + pb), (count.__name__, cross)
+
+
 @pytest.mark.parametrize("r", [1, 2, 5, 16])
 def test_count_is_the_band_product_of_eq2_eq3(r):
     """Eq. 2-3: H = Lambda Pi, R = Pi H with Pi[a][b] = 1 iff |a - b| <= r (band truncated
