@@ -169,6 +169,42 @@ def bench_decay(args, ltl, inputs, torch):
     return res
 
 
+XGMI_LINK_GBS = 153.0   # one xGMI link of an MI355X, one direction (published figure)
+
+
+def bench_shard(args, ltl, inputs, torch):
+    """One GPU's share of the radius-sweep grid split into `args.shard` row strips: the CAT int8
+    rate on a (side/N) x side strip next to the whole grid's, and the halo a strip would trade
+    with each neighbour per launch (r * T rows of `side` bytes, one xGMI link per neighbour).
+    The exchange time is the link model, not a measurement: this library runs on one GPU."""
+    side, n = args.sweep_side, args.shard
+    rows = side // n
+    full = inputs.bernoulli_grid_torch(side, side, 0.5, 3, device="cuda")
+    strip = full[:rows].contiguous()
+    res = {"workload": f"{rows}x{side} row strip (1/{n}) of the {side}x{side} sweep grid, sweep rules, 50 steps",
+           "xgmi_link_GBs_model": XGMI_LINK_GBS, "per_r": {}}
+    for r in (1, 5, 16):
+        rule = inputs.sweep_rule(r)
+        row = {}
+        for name, g in (("strip", strip), ("whole", full)):
+            s = ltl.Simulation(g, rule, "cat_i8")
+            s.autotune(probe_steps=10)
+            s.step(50)
+            secs, _ = timed_runs(s, 50, 1, torch)
+            row[name + "_cell_updates_per_s"] = g.shape[0] * side * 50 / secs
+            if name == "strip":
+                T = s.tuning()["steps_per_launch"]
+                row["strip_tuning"] = s.tuning()
+                launch_s = secs / (50 / T)
+            s.close()
+        halo = r * T * side
+        row["halo_bytes_per_edge_per_launch"] = halo
+        row["launch_us"] = launch_s * 1e6
+        row["exchange_us_model"] = halo / (XGMI_LINK_GBS * 1e9) * 1e6
+        res["per_r"][str(r)] = row
+    return res
+
+
 def mfma_issued(tuning, avg_launch_s, cells, r):
     """Counter-measured MFMA utilisation of the timed kernel: int8 ops the MFMAs issue per
     launch (committed SQ counter record) over launch time x peak, and the useful fraction:
@@ -254,6 +290,8 @@ def main():
     ap.add_argument("--sweep", action="store_true", help="also time the radius sweep r=1..16 on 16384^2")
     ap.add_argument("--sweep-side", type=int, default=16384)
     ap.add_argument("--sweep-rmax", type=int, default=16, help="largest radius of the sweep (int8 and direct reach 32)")
+    ap.add_argument("--shard", type=int, default=0, metavar="N",
+                    help="also time one GPU's row strip (1/N) of the sweep grid and the halo it would exchange")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the 512-instance batched workload")
     ap.add_argument("--decay", action="store_true", help="also time the C=8 R16 decay workload on 32768^2")
@@ -397,6 +435,9 @@ def main():
             sweep[str(r)] = row
         out["sweep"] = {"workload": f"{side}x{side}, r=1..{args.sweep_rmax} sweep rules, Bernoulli(0.5) seed 3, 50 steps",
                         "cell_updates_per_s": sweep}
+
+    if args.shard > 1:
+        out["shard"] = bench_shard(args, ltl, inputs, torch)
 
     # ---- the same workload on a torus (the paper's experimental boundary condition)
     sp = ltl.Simulation(g0, w.rule, "cat_i8", boundary="periodic")
