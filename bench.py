@@ -173,25 +173,30 @@ XGMI_LINK_GBS = 153.0   # one xGMI link of an MI355X, one direction (published f
 
 
 def bench_shard(args, ltl, inputs, torch):
-    """One GPU's share of the radius-sweep grid split into `args.shard` row strips: the CAT int8
-    rate on a (side/N) x side strip next to the whole grid's, and the halo a strip would trade
-    with each neighbour per launch (r * T rows of `side` bytes, one xGMI link per neighbour).
-    The exchange time is the link model, not a measurement: this library runs on one GPU."""
+    """One GPU's share of the radius-sweep grid split N = `args.shard` ways: the CAT int8 rate on
+    a (side/N) x side row strip and on a 2-D block of the same size (side/a x side/b, a * b = N,
+    a >= b closest) next to the whole grid's, and the halo a strip would trade with each
+    neighbour per launch (r * T rows of `side` bytes, one xGMI link per neighbour). The exchange
+    time is the link model, not a measurement: this library runs on one GPU."""
     side, n = args.sweep_side, args.shard
     rows = side // n
+    b = max(d for d in range(1, n + 1) if n % d == 0 and d * d <= n)
+    a = n // b
     full = inputs.bernoulli_grid_torch(side, side, 0.5, 3, device="cuda")
     strip = full[:rows].contiguous()
-    res = {"workload": f"{rows}x{side} row strip (1/{n}) of the {side}x{side} sweep grid, sweep rules, 50 steps",
+    block = full[:side // a, :side // b].contiguous()
+    res = {"workload": f"{rows}x{side} row strip and {side // a}x{side // b} block (1/{n}) of the {side}x{side} "
+                       "sweep grid, sweep rules, 50 steps",
            "xgmi_link_GBs_model": XGMI_LINK_GBS, "per_r": {}}
     for r in (1, 5, 16):
         rule = inputs.sweep_rule(r)
         row = {}
-        for name, g in (("strip", strip), ("whole", full)):
+        for name, g in (("strip", strip), ("block", block), ("whole", full)):
             s = ltl.Simulation(g, rule, "cat_i8")
             s.autotune(probe_steps=10)
             s.step(50)
             secs, _ = timed_runs(s, 50, 1, torch)
-            row[name + "_cell_updates_per_s"] = g.shape[0] * side * 50 / secs
+            row[name + "_cell_updates_per_s"] = g.shape[0] * g.shape[1] * 50 / secs
             if name == "strip":
                 T = s.tuning()["steps_per_launch"]
                 row["strip_tuning"] = s.tuning()
