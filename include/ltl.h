@@ -128,8 +128,8 @@ int32_t ltl_set_tuning(ltl_sim_t *sim, const ltl_tuning_t *tuning);
 
 /* Time candidate launch shapes on this simulation (each on a device copy of the current
  * state, so the simulation itself does not advance, for the whole number of its launches
- * that covers at least probe_steps steps), keep the fastest per step and return it in *best
- * (may be NULL). Synchronizes the stream. */
+ * that covers at least probe_steps steps, 1..4096), keep the fastest per step and return it
+ * in *best (may be NULL). Synchronizes the stream. */
 int32_t ltl_autotune(ltl_sim_t *sim, int32_t probe_steps, ltl_tuning_t *best);
 
 /* Boundary condition of the grid (default LTL_BOUNDARY_DEAD).
@@ -190,8 +190,8 @@ int32_t ltl_batch_current(ltl_batch_t *batch, int32_t index, void **buf, size_t 
 int32_t ltl_batch_get_tuning(ltl_batch_t *batch, ltl_tuning_t *tuning);
 int32_t ltl_batch_set_tuning(ltl_batch_t *batch, const ltl_tuning_t *tuning);
 /* Time candidate shapes (on a device copy of the arenas, the batch itself does not advance;
- * each for the whole number of its launches that covers at least probe_steps steps), keep
- * the fastest per step, return it in *best (may be NULL). Synchronizes. */
+ * each for the whole number of its launches that covers at least probe_steps steps,
+ * 1..4096), keep the fastest per step, return it in *best (may be NULL). Synchronizes. */
 int32_t ltl_batch_autotune(ltl_batch_t *batch, int32_t probe_steps, ltl_tuning_t *best);
 /* Release the handle; does not free the arenas or synchronize. NULL is accepted. */
 int32_t ltl_batch_destroy(ltl_batch_t *batch);

@@ -653,7 +653,7 @@ int32_t ltl_batch_set_tuning(ltl_batch_t *batch, const ltl_tuning_t *tuning) {
 
 int32_t ltl_batch_autotune(ltl_batch_t *batch, int32_t probe_steps, ltl_tuning_t *best) {
     if (!batch) return fail(LTL_ERR_ARG, "batch is NULL");
-    if (probe_steps < 1) return fail(LTL_ERR_ARG, "probe_steps must be >= 1");
+    if (probe_steps < 1 || probe_steps > 4096) return fail(LTL_ERR_ARG, "probe_steps must be in 1..4096");
     return batch_autotune(*batch, probe_steps, best);
 }
 

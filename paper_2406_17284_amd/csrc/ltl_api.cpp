@@ -543,7 +543,7 @@ int32_t ltl_set_tuning(ltl_sim_t *sim, const ltl_tuning_t *tuning) {
 
 int32_t ltl_autotune(ltl_sim_t *sim, int32_t probe_steps, ltl_tuning_t *best) {
     if (!sim) return fail(LTL_ERR_ARG, "sim is NULL");
-    if (probe_steps < 1) return fail(LTL_ERR_ARG, "probe_steps must be >= 1");
+    if (probe_steps < 1 || probe_steps > 4096) return fail(LTL_ERR_ARG, "probe_steps must be in 1..4096");
     ltl_sim &s = *sim;
     if (s.method == LTL_DIRECT) {
         if (best) *best = s.tuning;

@@ -172,6 +172,10 @@ def test_batch_autotune_keeps_results(ltl):
     grids, rules = small_batch(5, max_r=16, decay=False)
     batch = ltl.Batch([gpu_grid(g) for g in grids], rules, "cat_i8")
     batch.step(2)
+    for bad in (0, 4097):                                         # probe length out of range
+        with pytest.raises(ltl.LtlError) as e:
+            batch.autotune(probe_steps=bad)
+        assert e.value.code == ltl.LTL_ERR_ARG
     best = batch.autotune(probe_steps=3)
     assert best == batch.tuning()
     assert batch.steps_done == 2

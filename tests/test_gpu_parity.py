@@ -623,6 +623,10 @@ def test_autotune_small_grids(ltl, shape, boundary, rule):
     sim = ltl.Simulation(gpu_grid(g0), rule, "cat_i8", boundary=boundary)
     sim.step(2)
     before = sim.read().cpu().numpy()
+    for bad in (0, 4097):                                         # probe length out of range
+        with pytest.raises(ltl.LtlError) as e:
+            sim.autotune(probe_steps=bad)
+        assert e.value.code == ltl.LTL_ERR_ARG
     best = sim.autotune(probe_steps=3)
     assert np.array_equal(sim.read().cpu().numpy(), before)      # the probes ran on a copy
     assert sim.tuning() == best
