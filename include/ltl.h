@@ -177,7 +177,8 @@ int32_t ltl_batch_create(ltl_batch_t **out, int32_t count, const int32_t *H, con
                          size_t bytes, const void *const *init, const size_t *init_pitch,
                          hipStream_t stream);
 /* Enqueue n_steps >= 0 steps of every instance (batch_step(a); batch_step(b) equals
- * batch_step(a + b) cell for cell). */
+ * batch_step(a + b) cell for cell). With use_graph, the steps run as replays of cached
+ * hipGraphs of at most 64 launches each, as for ltl_step. */
 int32_t ltl_batch_step(ltl_batch_t *batch, int32_t n_steps);
 /* Enqueue a copy of instance `index` (H x W states) into device memory dst, row pitch dst_pitch >= W. */
 int32_t ltl_batch_read(ltl_batch_t *batch, int32_t index, void *dst, size_t dst_pitch);
