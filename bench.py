@@ -149,6 +149,29 @@ def bench_batch(args, ltl, inputs, torch):
     return res
 
 
+def bench_life(ltl, inputs, torch):
+    """The small workload: Life (R1 C0 M1 S3..4 B3..3) on 256^2, 64 steps per run, autotuned;
+    launch-latency bound (one 256^2 grid is a few tiles). Returns the result object, the
+    initial grid and the GPU grid after one run (for the oracle check)."""
+    w = inputs.WORKLOADS["life256"]
+    g_np = inputs.bernoulli_grid(w.H, w.W, w.p, w.seed)
+    g = torch.from_numpy(g_np).cuda()
+    s = ltl.Simulation(g, w.rule, "cat_i8")
+    tuning = s.autotune(probe_steps=w.steps)
+    s.step(w.steps)
+    runs = 20
+    secs, _ = timed_runs(s, w.steps, runs, torch)
+    s.close()
+    s = ltl.Simulation(g, w.rule, "cat_i8", tuning={k: tuning[k] for k in SHAPE_KEYS})
+    s.step(w.steps)
+    final = s.read().cpu().numpy()
+    s.close()
+    res = {"workload": f"life256: R1 C0 M1 S3..4 B3..3 N_M, 256x256, Bernoulli(0.5) seed {w.seed}, "
+                       f"{w.steps} steps per run", "tuning": tuning, "us_per_run": secs / runs * 1e6,
+           "value": w.H * w.W * w.steps * runs / secs, "unit": "cell-updates/s"}
+    return res, g_np, final
+
+
 def bench_decay(args, ltl, inputs, torch):
     """The multi-state workload: R16 C8 M0 S300..500 B330..420, 32768^2, 20 steps per bench step
     (the CAT step time does not depend on the grid's contents)."""
@@ -463,6 +486,7 @@ def main():
     if not args.no_batch:
         out["batched"] = bench_batch(args, ltl, inputs, torch)
 
+    out["life256"], life_init, life_final = bench_life(ltl, inputs, torch)
     if args.decay:
         out["decay"] = bench_decay(args, ltl, inputs, torch)
     if args.energy:
@@ -488,6 +512,9 @@ def main():
         oracle.run(one, w.rule, 1)
         t_single = time.perf_counter() - t0
         oracle.set_threads(threads)
+        lw = inputs.WORKLOADS["life256"]
+        out["life256"]["cat_vs_oracle_equal"] = bool(np.array_equal(oracle.run(life_init, lw.rule, lw.steps),
+                                                                     life_final))
         out["cpu_baseline"] = {"value": cells * n_cpu / tc, "unit": "cell-updates/s", "cores": threads,
                                "kind": "oracle", "sample": sample,
                                "single_thread_value": cells / t_single,
