@@ -149,6 +149,29 @@ def test_temporal_blocking(ltl, T, r, method):
     run_and_compare(ltl, g0, rule, method, 9, tuning=tuning)
 
 
+@pytest.mark.parametrize("method", ["cat_i8", "cat_f16", "cat_f8"])
+@pytest.mark.parametrize("T", [8, 12, 16, 33, 64])
+@pytest.mark.parametrize("r", [1, 2])
+def test_long_temporal_blocking(ltl, T, r, method):
+    """Steps per launch above 7 (the autotuner takes T = 8 at r = 1) up to the 64 the tuning
+    accepts: 2T + 3 steps (two whole launches and a shorter one) equal the oracle, on a dead halo
+    and (int8) on a torus; launch shapes the kernel cannot hold are refused."""
+    rule = inputs.sweep_rule(r)
+    g0 = inputs.bernoulli_grid(200, 333, 0.5, seed=200 + r)
+    n = 2 * T + 3
+    tuning = dict(steps_per_launch=T, tile_rows=64, tile_cols=64, waves=0)
+    maxc = 5 if method == "cat_f16" else 14
+    if not shape_feasible(r, T, 64, 64, maxc=maxc):
+        with pytest.raises(ltl.LtlError) as e:
+            run_and_compare(ltl, g0, rule, method, n, tuning=tuning)
+        assert e.value.code == ltl.LTL_ERR_ARG
+        return
+    run_and_compare(ltl, g0, rule, method, n, tuning=tuning)
+    if method == "cat_i8":
+        run_periodic(ltl, inputs.bernoulli_grid(208, 336, 0.5, seed=300 + r), rule, method, n, tuning=tuning,
+                     every_step=False)
+
+
 @pytest.mark.parametrize("tile", [(16, 32), (32, 64), (64, 64), (128, 128), (48, 96), (192, 128), (128, 224), (80, 224)])
 def test_tile_shapes(ltl, tile):
     rule = inputs.Rule(7, 0, 1, 56, 101, 60, 76)
