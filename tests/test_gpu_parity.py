@@ -172,6 +172,31 @@ def test_long_temporal_blocking(ltl, T, r, method):
                      every_step=False)
 
 
+TALL_RULES = [inputs.sweep_rule(3), inputs.sweep_rule(12), inputs.Rule(6, 5, 0, 30, 70, 35, 50)]
+
+
+@pytest.mark.parametrize("method", ["cat_i8", "cat_f16", "cat_f8"])
+@pytest.mark.parametrize("tile", [(512, 32), (448, 96), (320, 64), (272, 128)], ids=lambda t: f"{t[0]}x{t[1]}")
+@pytest.mark.parametrize("rule", TALL_RULES, ids=lambda r: r.text())
+def test_tall_tiles(ltl, rule, tile, method):
+    """Tiles taller than one row segment (a 32-column strip split over several waves), up to the
+    512 rows the tuning accepts, over byte, windowed and decay epilogues; a ragged last tile row
+    (1100 = 2 x 512 + 76). Shapes the kernel cannot hold are refused."""
+    if method == "cat_f8" and f8_refuses(ltl, rule):
+        return
+    g0 = (inputs.state_grid(1100, 150, rule.C, seed=31) if rule.C >= 3
+          else inputs.bernoulli_grid(1100, 150, 0.5, seed=31))
+    maxc = 5 if method == "cat_f16" else 14
+    for T in (1, 3):
+        tuning = dict(steps_per_launch=T, tile_rows=tile[0], tile_cols=tile[1], waves=0)
+        if not shape_feasible(rule.R, T, *tile, maxc=maxc):
+            with pytest.raises(ltl.LtlError) as e:
+                run_and_compare(ltl, g0, rule, method, 7, tuning=tuning)
+            assert e.value.code == ltl.LTL_ERR_ARG
+            continue
+        run_and_compare(ltl, g0, rule, method, 7, tuning=tuning)
+
+
 @pytest.mark.parametrize("tile", [(16, 32), (32, 64), (64, 64), (128, 128), (48, 96), (192, 128), (128, 224), (80, 224)])
 def test_tile_shapes(ltl, tile):
     rule = inputs.Rule(7, 0, 1, 56, 101, 60, 76)
