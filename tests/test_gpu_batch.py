@@ -89,6 +89,8 @@ def test_batch_every_step(ltl, method, seed):
     dict(steps_per_launch=3, tile_rows=64, tile_cols=128),
     dict(steps_per_launch=1, tile_rows=16, tile_cols=32),
     dict(steps_per_launch=4, tile_rows=32, tile_cols=64, use_graph=0),
+    dict(steps_per_launch=1, tile_rows=512, tile_cols=32),
+    dict(steps_per_launch=2, tile_rows=320, tile_cols=64),
 ], ids=lambda t: "T{steps_per_launch}_{tile_rows}x{tile_cols}".format(**t))
 def test_batch_tunings(ltl, method, tuning):
     grids, rules = small_batch(3, max_r=7 if method == "cat_f8" else 9)
@@ -102,6 +104,25 @@ def test_batch_tunings(ltl, method, tuning):
         return
     batch.step(7)
     check_batch(batch, [oracle.run(g, r, 7) for g, r in zip(grids, rules)], f"{method} {tuning}")
+    batch.close()
+
+
+@pytest.mark.parametrize("method", CAT_METHODS)
+@pytest.mark.parametrize("T", [8, 16])
+def test_batch_long_temporal_blocking(ltl, method, T):
+    """8 and 16 steps per launch on a batch of radius-1..2 instances (decay included): 2T + 3
+    steps equal the oracle; int8 must accept the shape (its margins fit a 64 x 64 tile)."""
+    grids, rules = small_batch(9, max_r=2)
+    refs = [oracle.run(g, r, 2 * T + 3) for g, r in zip(grids, rules)]
+    batch = ltl.Batch([gpu_grid(g) for g in grids], rules, method)
+    try:
+        batch.set_tuning(steps_per_launch=T, tile_rows=64, tile_cols=64)
+    except ltl.LtlError as e:
+        assert method != "cat_i8" and e.code == ltl.LTL_ERR_ARG, e
+        batch.close()
+        return
+    batch.step(2 * T + 3)
+    check_batch(batch, refs, f"{method} T={T}")
     batch.close()
 
 
