@@ -67,12 +67,14 @@ typedef enum {
     LTL_DIRECT = 3   /* comparison method: LDS tile + direct sum over the neighbourhood per cell */
 } ltl_method_t;
 
-/* Launch shape. Zero fields mean "library default". The result never depends on it. */
+/* Launch shape. Zero fields mean "library default". The result never depends on it. The
+ * direct method runs fixed 32 x 64 tiles, one step per launch: it checks tile_rows, tile_cols
+ * and waves against the ranges below but does not use them; only use_graph applies to it. */
 typedef struct {
     int32_t steps_per_launch; /* T >= 1 time steps fused in one kernel launch (temporal blocking) */
     int32_t tile_rows;        /* output rows per workgroup: multiple of 16, 16..512 */
     int32_t tile_cols;        /* output columns per workgroup: multiple of 32, 32..512 */
-    int32_t waves;            /* 64-lane waves per workgroup: 1..8 (CAT), 1..16 (direct) */
+    int32_t waves;            /* 64-lane waves per workgroup: 1..8 (CAT; the direct method accepts 1..16) */
     int32_t use_graph;        /* 1: replay multi-launch loops from a cached hipGraph */
     int32_t persistent;       /* CAT methods, single grid: 1 = persistent workgroups (about one per
                                  CU slot) that each walk a contiguous run of tiles, loading tile
