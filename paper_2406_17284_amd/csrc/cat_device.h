@@ -485,8 +485,9 @@ __device__ __forceinline__ v4i vproduct(const v16i &H, const v16i &L, const Band
 }
 
 // Offsets of this lane's cells in the LDS tiles: Q holds states (pitch PS, one byte per cell),
-// A the alive map in the element encoding (pitch PA). For int8 and fp8 without decay the two
-// tiles are the same bytes.
+// A the alive map in the element encoding (pitch PA). The two are the same bytes except for
+// decay rules on fp8 and on the wide and cross int8 elements, which keep a second tile; fp16
+// and int8 Moore build their operands (alive bits for decay) in registers from Q.
 struct LaneOff {
     uint32_t q, a;   // block-row-0 offset of the lane's first cell of half a (half b: +16 cells)
 };

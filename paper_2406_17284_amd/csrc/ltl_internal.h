@@ -222,8 +222,8 @@ inline bool cat_shape_fits(int elem, int r, int T, int TH, int TW, int waves) {
 // multiple of 32) plus 16 more bytes per row, so its pitch is = 16 (mod 32) and the 16 rows of
 // a 16-byte-per-lane operand read fall into distinct bank groups; rows are dense so 1 KiB of
 // consecutive LDS maps to consecutive window bytes (one direct global->LDS load per wave).
-// The alive tile is the state tile itself for int8 / fp8 two-state rules, else a second tile
-// in the element encoding.
+// The alive tile is the state tile itself, except for decay rules on fp8 and on the wide and
+// cross int8 elements, which keep a second tile in the element encoding.
 inline void cat_lds_layout(int elem, int epi, int TH, int TW, int L, int *PS, int *PA, int *lds_tile, int *a_tile,
                            int *lds_total) {
     const int rows = TH + 2 * L;
