@@ -126,6 +126,48 @@ def test_batch_long_temporal_blocking(ltl, method, T):
     batch.close()
 
 
+def draw_batch_case(k):
+    """Seeded batch case: 1..10 instances of random size, radius, rule (decay states, M0/M1,
+    empty ranges), one method, a random launch shape and a random split of the steps."""
+    rng = np.random.default_rng(20_000 + k)
+    method = str(rng.choice(["cat_i8", "cat_i8", "cat_f16", "cat_f8", "direct"]))
+    max_r = 7 if method == "cat_f8" else 16
+    count = int(rng.integers(1, 11))
+    shapes = [(int(rng.integers(1, 300)), int(rng.integers(1, 300))) for _ in range(count)]
+    grids, rules = [], []
+    for i, (H, W) in enumerate(shapes):
+        rule = random_rule(rng, max_r)
+        grids.append(inputs.state_grid(H, W, rule.C, seed=50 * k + i) if rule.C >= 3
+                     else inputs.bernoulli_grid(H, W, 0.5, seed=50 * k + i))
+        rules.append(rule)
+    tuning = None
+    if method != "direct" and rng.random() < 0.8:
+        tuning = dict(steps_per_launch=int(rng.integers(1, 9)), tile_rows=16 * int(rng.integers(1, 15)),
+                      tile_cols=32 * int(rng.integers(1, 8)), waves=int(rng.choice([0, 0, 8])),
+                      use_graph=int(rng.integers(0, 2)))
+    steps = int(rng.integers(1, 12))
+    cut = int(rng.integers(0, steps + 1))
+    return method, grids, rules, tuning, [cut, steps - cut]
+
+
+@pytest.mark.parametrize("k", range(40))
+def test_batch_random_case(ltl, k):
+    method, grids, rules, tuning, chunks = draw_batch_case(k)
+    what = f"case {k}: {method} {len(grids)} instances tuning={tuning} chunks={chunks}"
+    refs = [oracle.run(g, r, sum(chunks)) for g, r in zip(grids, rules)]
+    batch = ltl.Batch([gpu_grid(g) for g in grids], rules, method)
+    if tuning is not None:
+        try:
+            batch.set_tuning(**tuning)
+        except ltl.LtlError as e:
+            assert e.code == ltl.LTL_ERR_ARG, what   # a shape some instance cannot run
+    for n in chunks:
+        batch.step(n)
+    assert batch.steps_done == sum(chunks), what
+    check_batch(batch, refs, what)
+    batch.close()
+
+
 def test_batch_resume_and_graph(ltl):
     grids, rules = small_batch(4, max_r=6)
     refs = [oracle.run(g, r, 9) for g, r in zip(grids, rules)]
