@@ -1,15 +1,23 @@
 """Benchmark: Larger-than-Life cell-updates/s on one MI355X, CAT int8-MFMA vs the LDS direct stencil.
 
-A bench step is one full run of the workload: ``ltl_step(100)`` on the Bosco-type rule
-R5 C0 M1 S34..58 B34..45 N_M over a 4096 x 4096 uint8 grid (Bernoulli(0.5), seed 2, dead
-ghost halo), inputs resident in HBM. Prints one JSON line.
+Headline (``value``): the Bosco-type rule R5 C0 M1 S34..58 B34..45 N_M on a 4096 x 4096 uint8
+grid (Bernoulli(0.5), seed 2, dead ghost halo), one bench step = ``ltl_step(100)`` with the
+grid resident in HBM, the launch shape the library picks by itself (tuning table). Timing:
+``--warmup`` untimed bench steps, then ``--steps`` repetitions, each restarting from the same
+initial grid and timed with HIP events on the simulation's stream; the median is reported.
 
-Also reported (not the headline value): the batched workload (512 instances of log-uniform
-sides in [128, 2048], r uniform in 1..16, per-instance rules; one ``ltl_batch_step(32)``
-hipGraph per bench step), and with --sweep the radius sweep r = 1..16 on 16384^2 for the
-int8, fp16 and fp8 (r <= 7) CAT variants and the direct stencil.
+Also measured by default (each with its own median over repetitions restarting from its
+initial grid, bit-exactness against the oracle's digests, and a CPU-oracle baseline):
+  * sweep: the radius sweep r = 1..16 on 16384^2 (50 steps, sweep rules), CAT int8, int8 at
+    one step per launch, fp16, fp8 (r <= 7) and the direct stencil;
+  * life256: Life on 256^2, 64 steps;
+  * batched: the 512-instance batch, 32 steps (one hipGraph);
+  * decay: the C = 8 R16 rule on 32768^2, 20 steps;
+  * periodic: the headline workload on a torus.
+Prints one JSON line on stdout (progress goes to stderr).
 
-  python bench.py [--gpus 1] [--steps K] [--warmup W] [--sweep] [--no-cpu] [--no-batch] [--autotune]
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-sweep] [--no-life] [--no-batch] [--no-decay]
+                  [--no-cpu] [--tuning T,rows,cols,waves[,persistent[,lds_pad]]] [--energy] [--shard N]
 """
 from __future__ import annotations
 
@@ -17,6 +25,7 @@ import argparse
 import json
 import math
 import os
+import statistics
 import sys
 import time
 
@@ -24,14 +33,19 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "cell-updates/s vs radius r=1..16, CAT int8-MFMA vs direct stencil, bit-exact"
-INT8_PEAK_TOPS = 5000.0  # MI355X dense int8 MFMA
+PEAK_TOPS = {"cat_i8": 5000.0, "cat_f8": 5000.0, "cat_f16": 2500.0}   # MI355X dense MFMA, per element type
 HBM_PEAK_GBS = 8000.0
+VALU_PEAK_OPS = 256 * 4 * 16 * 2.4e9   # int32 lane-ops/s: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
 OPS_PER_CELL = 256       # two 16x16x64 int8 MFMAs per 256 cells, 2 ops per multiply-add
-DEFAULT_TUNING = "4,160,224,8"   # steps per launch, tile rows, tile cols, waves
 KERNEL_SRC = [os.path.join(ROOT, "paper_2406_17284_amd", "csrc", f) for f in ("cat_device.h", "cat_kernel.hip")]
-BATCH_TUNING = "3,160,160,8"   # the autotuner's pick for the 512-instance batch on MI355X
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "cat_step_i8_bosco4096_traffic.json")
 MFMA_RECORD = os.path.join(ROOT, "profiles", "cat_step_i8_bosco4096_sq.json")
+DIGESTS = os.path.join(ROOT, "tests", "golden", "oracle_digests.json")
+SHAPE_KEYS = ("steps_per_launch", "tile_rows", "tile_cols", "waves", "persistent", "lds_pad")
+
+
+def log(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def kernel_hash() -> str:
@@ -44,56 +58,53 @@ def kernel_hash() -> str:
     return h.hexdigest()
 
 
-SHAPE_KEYS = ("steps_per_launch", "tile_rows", "tile_cols", "waves", "persistent")
-
-
 def parse_tuning(text):
-    """'T,tile_rows,tile_cols,waves[,persistent]' -> keyword arguments of set_tuning."""
+    """'T,tile_rows,tile_cols,waves[,persistent[,lds_pad]]' -> keyword arguments of set_tuning."""
     vals = [int(x) for x in text.split(",")]
     return dict(zip(SHAPE_KEYS, vals))
+
+
+def _shape(tuning):
+    return [int(tuning.get(k, 0)) for k in SHAPE_KEYS]
+
+
+def _record(path, tuning, field):
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_sha256") != kernel_hash() or list(rec.get("tuning", []))[:len(SHAPE_KEYS)] + \
+            [0] * (len(SHAPE_KEYS) - len(rec.get("tuning", []))) != _shape(tuning):
+        return None
+    return rec[field]
 
 
 def recorded_traffic(tuning):
     """HBM bytes per launch from the committed FETCH_SIZE / WRITE_SIZE counter record, if it was
     taken on this kernel source and launch shape; else None."""
-    try:
-        with open(TRAFFIC_RECORD) as f:
-            rec = json.load(f)
-    except (OSError, ValueError):
-        return None
-    shape = [tuning[k] for k in SHAPE_KEYS]
-    if rec.get("kernel_sha256") != kernel_hash() or rec.get("tuning") != shape:
-        return None
-    return rec["hbm_bytes_per_launch"]
+    return _record(TRAFFIC_RECORD, tuning, "hbm_bytes_per_launch")
 
 
 def recorded_mfma_ops(tuning):
     """int8 MFMA ops issued per launch (SQ_INSTS_VALU_MFMA_MOPS_I8 x 512) from the committed
     counter record, if it was taken on this kernel source and launch shape; else None."""
-    try:
-        with open(MFMA_RECORD) as f:
-            rec = json.load(f)
-    except (OSError, ValueError):
-        return None
-    shape = [tuning[k] for k in SHAPE_KEYS]
-    if rec.get("kernel_sha256") != kernel_hash() or rec.get("tuning") != shape:
-        return None
-    return rec["mfma_ops_per_launch"]
+    return _record(MFMA_RECORD, tuning, "mfma_ops_per_launch")
 
 
-def timed_runs(sim, n_per_run, runs, torch):
-    stream = sim.stream
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ev0.record(stream)
-    for _ in range(runs):
-        sim.step(n_per_run)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    return ev0.elapsed_time(ev1) / 1e3, wall
+def mfma_issued(tuning, avg_launch_s, cells, r):
+    """Counter-measured MFMA utilisation of the timed kernel: int8 ops the MFMAs issue per
+    launch (committed SQ counter record) over launch time x peak, and the useful fraction:
+    the band non-zeros, 4(2r+1) ops per cell-update, over the ops issued per cell-update."""
+    ops = recorded_mfma_ops(tuning)
+    if ops is None:
+        return None
+    steps = tuning["steps_per_launch"]
+    issued_per_cell = ops / (cells * steps)
+    return {"ops_per_launch": ops, "frac_of_peak": ops / avg_launch_s / (PEAK_TOPS["cat_i8"] * 1e12),
+            "issued_ops_per_cell_update": issued_per_cell,
+            "useful_ops_per_cell_update": 4 * (2 * r + 1),
+            "useful_frac": 4 * (2 * r + 1) / issued_per_cell}
 
 
 def cpu_model() -> str:
@@ -107,88 +118,255 @@ def cpu_model() -> str:
     return "unknown"
 
 
-def bench_batch(args, ltl, inputs, torch):
-    """The batched workload: 512 automata advanced together, 32 steps per bench step."""
-    insts = inputs.batch_instances()
-    steps = 32
-    dev = [inputs.bernoulli_grid_torch(x.H, x.W, 0.5, x.seed, device="cuda") for x in insts]
-    rules = [x.rule for x in insts]
-    cells = sum(x.H * x.W for x in insts)
-    res = {"workload": "512 instances, sides log-uniform in [128, 2048], r uniform in 1..16, S/B uniform in "
-                       "[0.2, 0.5] x (2r+1)^2, M1, Bernoulli(0.5), 32 steps per bench step (one hipGraph)",
-           "cells": cells}
-    bt = ltl.Batch(dev, rules, "cat_i8")
-    if args.autotune:
-        bt.autotune(probe_steps=4)
-    else:
-        T, th, tw, wv = (int(x) for x in args.batch_tuning.split(","))
-        bt.set_tuning(steps_per_launch=T, tile_rows=th, tile_cols=tw, waves=wv)
-    for _ in range(max(1, args.warmup)):
-        bt.step(steps)
-    secs, _ = timed_runs(bt, steps, args.steps, torch)
-    res["value"] = cells * steps * args.steps / secs
-    res["unit"] = "cell-updates/s"
-    res["ms_per_bench_step"] = secs / args.steps * 1e3
-    res["tuning"] = bt.tuning()
-    bt.close()
+def load_digests():
+    try:
+        with open(DIGESTS) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
 
-    db = ltl.Batch(dev, rules, "direct")
-    db.step(steps)
-    dsecs, _ = timed_runs(db, steps, 1, torch)
-    res["direct_stencil_cell_updates_per_s"] = cells * steps / dsecs
-    db.close()
 
-    # cross-check: a fresh CAT batch and the direct batch after the same 32 steps, all instances
-    a = ltl.Batch(dev, rules, "cat_i8")
-    b = ltl.Batch(dev, rules, "direct")
-    a.step(steps)
-    b.step(steps)
-    res["cat_vs_direct_equal"] = all(torch.equal(a.read(i), b.read(i)) for i in range(len(insts)))
-    a.close()
-    b.close()
+def digest_of(t) -> str:
+    import numpy as np
+    import xxhash
+
+    a = np.ascontiguousarray(t.cpu().numpy())
+    return xxhash.xxh3_128_hexdigest(memoryview(a).cast("B"))
+
+
+def golden(digests, name, step):
+    """The oracle's digest of workload `name` after `step` steps, or None if not recorded."""
+    w = digests.get(name)
+    if not w:
+        return None
+    for e in w.get("steps", []):
+        if e["step"] == step:
+            return e["digest"]
+    return None
+
+
+# ------------------------------------------------------------------------------ timing
+def time_reps(stream, run, reset, reps, torch):
+    """Seconds of `reps` runs of `run()` (HIP events on `stream`), each after `reset()` restored
+    the initial state outside the timed region."""
+    out = []
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    for _ in range(reps):
+        reset()
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        run()
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        out.append(ev0.elapsed_time(ev1) / 1e3)
+    return out
+
+
+def sim_reset(sim, g0):
+    def reset():
+        sim.current_padded()[:, :sim.W].copy_(g0)
+    return reset
+
+
+def batch_reset(b, g0s):
+    def reset():
+        for i, g in enumerate(g0s):
+            b.current_padded(i)[:, :b.W[i]].copy_(g)
+    return reset
+
+
+def sim_rate(ltl, torch, g0, rule, method, steps, reps, tuning=None, boundary="dead", warmup=1):
+    """Median seconds per `steps`-step run (restarting from g0 each time), the final grid after
+    `steps` steps, the launch shape and the per-run times."""
+    sim = ltl.Simulation(g0, rule, method, tuning=tuning, boundary=boundary)
+    reset = sim_reset(sim, g0)
+    for _ in range(warmup):
+        reset()
+        sim.step(steps)
+    times = time_reps(sim.stream, lambda: sim.step(steps), reset, reps, torch)
+    final = sim.read()
+    tun = sim.tuning()
+    sim.close()
+    return statistics.median(times), final, tun, times
+
+
+# ------------------------------------------------------------------------------ CPU oracle
+def oracle_rates(oracle, inputs, grid_fn, rule, steps_all, steps_one, rows_one=None):
+    """Cell-updates/s of the oracle on all host threads (steps_all steps of grid_fn()) and on one
+    thread (steps_one steps of the first rows_one rows, extrapolated per cell-update)."""
+    import numpy as np
+
+    g = grid_fn()
+    threads = oracle.set_threads(0)
+    t0 = time.perf_counter()
+    res = oracle.run(g, rule, steps_all)
+    t_all = time.perf_counter() - t0
+    sub = np.ascontiguousarray(g[:rows_one]) if rows_one else g
+    oracle.set_threads(1)
+    t0 = time.perf_counter()
+    oracle.run(sub, rule, steps_one)
+    t_one = time.perf_counter() - t0
+    oracle.set_threads(threads)
+    return {"value": g.size * steps_all / t_all, "unit": "cell-updates/s", "cores": threads, "kind": "oracle",
+            "single_thread_value": sub.size * steps_one / t_one, "seconds_all_cores": t_all,
+            "seconds_single_thread": t_one}, res
+
+
+# ------------------------------------------------------------------------------ legs
+def bench_sweep(args, ltl, inputs, torch, digests, oracle):
+    side, steps, reps = args.sweep_side, 50, 5
+    g = inputs.bernoulli_grid_torch(side, side, 0.5, 3, device="cuda")
+    cells = side * side
+    per_r = {}
+    t1_shape = dict(steps_per_launch=1, tile_rows=160, tile_cols=224, waves=8)
+    for r in range(1, args.sweep_rmax + 1):
+        w = inputs.sweep_workload(r, side)
+        ref = golden(digests, w.name, steps) if side == 16384 else None
+        row = {}
+        for method in ("cat_i8", "cat_i8_T1", "cat_f16", "cat_f8", "direct"):
+            m = "cat_i8" if method == "cat_i8_T1" else method
+            if (m == "cat_f8" and r > 7) or (m == "cat_f16" and r > 16):
+                continue
+            med, final, tun, _ = sim_rate(ltl, torch, g, w.rule, m, steps, reps if m != "direct" else 3,
+                                          tuning=t1_shape if method == "cat_i8_T1" else None)
+            rate = cells * steps / med
+            ent = {"cell_updates_per_s": rate, "ms_per_run": med * 1e3}
+            if m in PEAK_TOPS:
+                launches = math.ceil(steps / tun["steps_per_launch"])
+                ent["frac"] = OPS_PER_CELL * rate / (PEAK_TOPS[m] * 1e12)
+                ent["avg_launch_us"] = med / launches * 1e6
+                ent["tuning"] = [tun[k] for k in SHAPE_KEYS]
+            else:
+                ent["frac_valu"] = (2 * r + 1) ** 2 * rate / VALU_PEAK_OPS
+            ent["bit_exact"] = None if ref is None else digest_of(final) == ref
+            row[method] = ent
+            del final
+        row["cat_over_direct"] = row["cat_i8"]["cell_updates_per_s"] / row["direct"]["cell_updates_per_s"]
+        per_r[str(r)] = row
+        log(f"sweep r={r}: int8 {row['cat_i8']['cell_updates_per_s']:.3e}, direct "
+            f"{row['direct']['cell_updates_per_s']:.3e}, exact {row['cat_i8']['bit_exact']}")
+    i8 = [per_r[k]["cat_i8"]["cell_updates_per_s"] for k in per_r]
+    t1 = [per_r[k]["cat_i8_T1"]["cell_updates_per_s"] for k in per_r]
+    wins = [int(k) for k in per_r if per_r[k]["cat_over_direct"] > 1]
+    exact = [v.get("bit_exact") for k in per_r for v in per_r[k].values() if isinstance(v, dict)]
+    res = {"workload": f"sweep{side}: {side}x{side}, r=1..{args.sweep_rmax} sweep rules (S=[0.25,0.45]N, "
+                       f"B=[0.27,0.34]N floored), Bernoulli(0.5) seed 3, dead halo, {steps} steps per run",
+           "reps": reps, "per_r": per_r,
+           "int8_max_over_min": max(i8) / min(i8), "int8_T1_max_over_min": max(t1) / min(t1),
+           "int8_T1_shape": [t1_shape.get(k, 0) for k in SHAPE_KEYS],
+           "cat_beats_direct_from_r": min(wins) if wins else None,
+           "cat_beats_direct_at_every_r": len(wins) == len(per_r),
+           "bit_exact_all": (all(e is True for e in exact) if all(e is not None for e in exact) else None)}
+    del g
+    if oracle is not None:
+        # all cores: 2 steps of a 2048-row strip of the sweep grid per sampled radius; one
+        # thread: 1 step of its first 128 rows (extrapolated per cell-update)
+        cpu = {}
+        for r in (1, 5, 9, 16):
+            rule = inputs.sweep_rule(r)
+            rates, _ = oracle_rates(oracle, inputs, lambda: inputs.bernoulli_grid(2048, side, 0.5, 3), rule, 2, 1,
+                                    rows_one=128)
+            cpu[str(r)] = rates
+        res["cpu_baseline"] = {"per_r": cpu, "kind": "oracle", "unit": "cell-updates/s",
+                               "cores": cpu["1"]["cores"], "cpu_model": cpu_model(),
+                               "sample": "per r in {1, 5, 9, 16}: all cores = 2 steps of a 2048 x 16384 strip; one "
+                                         "thread = 1 step of a 128 x 16384 strip, extrapolated per cell-update"}
     return res
 
 
-def bench_life(ltl, inputs, torch):
-    """The small workload: Life (R1 C0 M1 S3..4 B3..3) on 256^2, 64 steps per run, autotuned;
-    launch-latency bound (one 256^2 grid is a few tiles). Returns the result object, the
-    initial grid and the GPU grid after one run (for the oracle check)."""
+def bench_life(args, ltl, inputs, torch, digests):
     w = inputs.WORKLOADS["life256"]
-    g_np = inputs.bernoulli_grid(w.H, w.W, w.p, w.seed)
-    g = torch.from_numpy(g_np).cuda()
-    s = ltl.Simulation(g, w.rule, "cat_i8")
-    tuning = s.autotune(probe_steps=w.steps)
-    s.step(w.steps)
-    runs = 20
-    secs, _ = timed_runs(s, w.steps, runs, torch)
-    s.close()
-    s = ltl.Simulation(g, w.rule, "cat_i8", tuning={k: tuning[k] for k in SHAPE_KEYS})
-    s.step(w.steps)
-    final = s.read().cpu().numpy()
-    s.close()
-    res = {"workload": f"life256: R1 C0 M1 S3..4 B3..3 N_M, 256x256, Bernoulli(0.5) seed {w.seed}, "
-                       f"{w.steps} steps per run", "tuning": tuning, "us_per_run": secs / runs * 1e6,
-           "value": w.H * w.W * w.steps * runs / secs, "unit": "cell-updates/s"}
-    return res, g_np, final
+    g = torch.from_numpy(inputs.bernoulli_grid(w.H, w.W, w.p, w.seed)).cuda()
+    med, final, tun, _ = sim_rate(ltl, torch, g, w.rule, "cat_i8", w.steps, 20, warmup=3)
+    return {"workload": f"life256: R1 C0 M1 S3..4 B3..3 N_M, 256x256, Bernoulli(0.5) seed {w.seed}, dead halo, "
+                        f"{w.steps} steps per run", "reps": 20, "tuning": [tun[k] for k in SHAPE_KEYS],
+            "us_per_run": med * 1e6, "value": w.H * w.W * w.steps / med, "unit": "cell-updates/s"}, final
 
 
-def bench_decay(args, ltl, inputs, torch):
-    """The multi-state workload: R16 C8 M0 S300..500 B330..420, 32768^2, 20 steps per bench step
-    (the CAT step time does not depend on the grid's contents)."""
+def bench_batch(args, ltl, inputs, torch, digests, oracle):
+    insts = inputs.batch_instances()
+    steps, reps = 32, 5
+    dev = [inputs.bernoulli_grid_torch(x.H, x.W, 0.5, x.seed, device="cuda") for x in insts]
+    rules = [x.rule for x in insts]
+    cells = sum(x.H * x.W for x in insts)
+    res = {"workload": "batch512: 512 instances, sides log-uniform in [128, 2048], r uniform in 1..16, S/B uniform "
+                       "in [0.2, 0.5] x (2r+1)^2, M1, Bernoulli(0.5), dead halo, 32 steps per run (one hipGraph)",
+           "cells": cells, "reps": reps}
+    out = {}
+    for method in ("cat_i8", "direct"):
+        b = ltl.Batch(dev, rules, method)
+        reset = batch_reset(b, dev)
+        reset()
+        b.step(steps)
+        times = time_reps(b.stream, lambda: b.step(steps), reset, reps if method == "cat_i8" else 2, torch)
+        med = statistics.median(times)
+        out[method] = cells * steps / med
+        if method == "cat_i8":
+            res["ms_per_run"] = med * 1e3
+            res["tuning"] = [b.tuning()[k] for k in SHAPE_KEYS]
+            gold = digests.get("batch512", {}).get("instances")
+            if gold:
+                res["bit_exact"] = all(digest_of(b.read(i)) == gold[i]["digest"] for i in range(len(insts)))
+            else:
+                res["bit_exact"] = None
+        b.close()
+    res["value"] = out["cat_i8"]
+    res["unit"] = "cell-updates/s"
+    res["frac"] = OPS_PER_CELL * out["cat_i8"] / (PEAK_TOPS["cat_i8"] * 1e12)
+    res["direct_stencil_cell_updates_per_s"] = out["direct"]
+    res["cat_over_direct"] = out["cat_i8"] / out["direct"]
+    if oracle is not None:
+        import numpy as np
+
+        # the first 16 instances: all cores over 32 steps, one thread over 2 steps
+        sample = list(range(16))
+        threads = oracle.set_threads(0)
+        grids = [inputs.bernoulli_grid(insts[i].H, insts[i].W, 0.5, insts[i].seed) for i in sample]
+        n = sum(g.size for g in grids)
+        t0 = time.perf_counter()
+        for g, i in zip(grids, sample):
+            oracle.run(g, insts[i].rule, steps)
+        t_all = time.perf_counter() - t0
+        oracle.set_threads(1)
+        t0 = time.perf_counter()
+        for g, i in zip(grids, sample):
+            oracle.run(np.ascontiguousarray(g), insts[i].rule, 2)
+        t_one = time.perf_counter() - t0
+        oracle.set_threads(threads)
+        res["cpu_baseline"] = {"value": n * steps / t_all, "unit": "cell-updates/s", "cores": threads, "kind": "oracle",
+                               "single_thread_value": n * 2 / t_one, "cpu_model": cpu_model(),
+                               "sample": "instances 0..15 of the batch: all cores over 32 steps; one thread over 2 "
+                                         "steps, extrapolated per cell-update"}
+    return res
+
+
+def bench_decay(args, ltl, inputs, torch, digests, oracle):
     w = inputs.WORKLOADS["decay32768"]
     g = inputs.bernoulli_grid_torch(w.H, w.W, w.p, w.seed, device="cuda")
-    res = {"workload": "decay32768: R16 C8 M0 S300..500 B330..420 N_M, 32768x32768, Bernoulli(0.5), 20 steps"}
-    for method in ("cat_i8", "direct"):
-        s = ltl.Simulation(g, w.rule, method)
-        if method == "cat_i8":
-            s.autotune(probe_steps=4)
-            res["tuning"] = s.tuning()
-        s.step(w.steps)
-        secs, _ = timed_runs(s, w.steps, 1 if method == "direct" else max(1, min(args.steps, 3)), torch)
-        runs = 1 if method == "direct" else max(1, min(args.steps, 3))
-        res[method] = w.H * w.W * w.steps * runs / secs
-        s.close()
+    cells = w.H * w.W
+    res = {"workload": f"decay32768: R16 C8 M0 S300..500 B330..420 N_M, 32768x32768, Bernoulli(0.5) seed {w.seed}, "
+                       f"dead halo, {w.steps} steps per run", "reps": 5}
+    ref = golden(digests, "decay32768", w.steps)
+    med, final, tun, _ = sim_rate(ltl, torch, g, w.rule, "cat_i8", w.steps, 5)
+    res["value"] = cells * w.steps / med
     res["unit"] = "cell-updates/s"
+    res["ms_per_run"] = med * 1e3
+    res["frac"] = OPS_PER_CELL * res["value"] / (PEAK_TOPS["cat_i8"] * 1e12)
+    res["tuning"] = [tun[k] for k in SHAPE_KEYS]
+    res["bit_exact"] = None if ref is None else digest_of(final) == ref
+    del final
+    med_d, final_d, _, _ = sim_rate(ltl, torch, g, w.rule, "direct", w.steps, 1, warmup=0)
+    res["direct_stencil_cell_updates_per_s"] = cells * w.steps / med_d
+    res["direct_bit_exact"] = None if ref is None else digest_of(final_d) == ref
+    res["cat_over_direct"] = res["value"] / res["direct_stencil_cell_updates_per_s"]
+    del g, final_d
+    if oracle is not None:
+        rates, _ = oracle_rates(oracle, inputs, lambda: inputs.bernoulli_grid(1024, w.W, 0.5, w.seed), w.rule, 2, 1,
+                                rows_one=64)
+        res["cpu_baseline"] = dict(rates, cpu_model=cpu_model(),
+                                   sample="all cores = 2 steps of a 1024 x 32768 strip of the grid; one thread = 1 "
+                                          "step of a 64 x 32768 strip, extrapolated per cell-update")
     return res
 
 
@@ -197,10 +375,10 @@ XGMI_LINK_GBS = 153.0   # one xGMI link of an MI355X, one direction (published f
 
 def bench_shard(args, ltl, inputs, torch):
     """One GPU's share of the radius-sweep grid split N = `args.shard` ways: the CAT int8 rate on
-    a (side/N) x side row strip and on a 2-D block of the same size (side/a x side/b, a * b = N,
-    a >= b closest) next to the whole grid's, and the halo a strip would trade with each
-    neighbour per launch (r * T rows of `side` bytes, one xGMI link per neighbour). The exchange
-    time is the link model, not a measurement: this library runs on one GPU."""
+    a (side/N) x side row strip and on a 2-D block of the same size next to the whole grid's, and
+    the halo a strip would trade with each neighbour per launch (r * T rows of `side` bytes, one
+    xGMI link per neighbour). The exchange time is the link model, not a measurement: this
+    library runs on one GPU."""
     side, n = args.sweep_side, args.shard
     rows = side // n
     b = max(d for d in range(1, n + 1) if n % d == 0 and d * d <= n)
@@ -215,37 +393,18 @@ def bench_shard(args, ltl, inputs, torch):
         rule = inputs.sweep_rule(r)
         row = {}
         for name, g in (("strip", strip), ("block", block), ("whole", full)):
-            s = ltl.Simulation(g, rule, "cat_i8")
-            s.autotune(probe_steps=10)
-            s.step(50)
-            secs, _ = timed_runs(s, 50, 1, torch)
-            row[name + "_cell_updates_per_s"] = g.shape[0] * g.shape[1] * 50 / secs
+            med, _, tun, _ = sim_rate(ltl, torch, g, rule, "cat_i8", 50, 3)
+            row[name + "_cell_updates_per_s"] = g.shape[0] * g.shape[1] * 50 / med
             if name == "strip":
-                T = s.tuning()["steps_per_launch"]
-                row["strip_tuning"] = s.tuning()
-                launch_s = secs / (50 / T)
-            s.close()
+                T = tun["steps_per_launch"]
+                row["strip_tuning"] = [tun[k] for k in SHAPE_KEYS]
+                launch_s = med / (50 / T)
         halo = r * T * side
         row["halo_bytes_per_edge_per_launch"] = halo
         row["launch_us"] = launch_s * 1e6
         row["exchange_us_model"] = halo / (XGMI_LINK_GBS * 1e9) * 1e6
         res["per_r"][str(r)] = row
     return res
-
-
-def mfma_issued(tuning, avg_launch_s, cells, r):
-    """Counter-measured MFMA utilisation of the timed kernel: int8 ops the MFMAs issue per
-    launch (committed SQ counter record) over launch time x peak, and the useful fraction:
-    the band non-zeros, 4(2r+1) ops per cell-update, over the ops issued per cell-update."""
-    ops = recorded_mfma_ops(tuning)
-    if ops is None:
-        return None
-    steps = tuning["steps_per_launch"]
-    issued_per_cell = ops / (cells * steps)
-    return {"ops_per_launch": ops, "frac_of_peak": ops / avg_launch_s / (INT8_PEAK_TOPS * 1e12),
-            "issued_ops_per_cell_update": issued_per_cell,
-            "useful_ops_per_cell_update": 4 * (2 * r + 1),
-            "useful_frac": 4 * (2 * r + 1) / issued_per_cell}
 
 
 def gpu_energy_reader(torch):
@@ -291,8 +450,6 @@ def bench_energy(args, ltl, inputs, torch):
     res["idle_W"] = (e1 - e0) / (t1 - t0)
     for method, steps, reps in (("cat_i8", 1000, 3), ("direct", 100, 2)):
         s = ltl.Simulation(g, rule, method)
-        if method == "cat_i8":
-            s.set_tuning(**parse_tuning(args.tuning))
         s.step(steps // 10)
         torch.cuda.synchronize()
         e0, t0 = energy(), time.perf_counter()
@@ -313,25 +470,23 @@ def bench_energy(args, ltl, inputs, torch):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=20)   # long enough for the GPU clocks to settle
-    ap.add_argument("--sweep", action="store_true", help="also time the radius sweep r=1..16 on 16384^2")
+    ap.add_argument("--steps", type=int, default=20, help="timed repetitions of the headline run (median reported)")
+    ap.add_argument("--warmup", type=int, default=20, help="untimed headline runs first (GPU clocks settle)")
+    ap.add_argument("--no-sweep", action="store_true", help="skip the radius sweep r=1..16 on 16384^2")
     ap.add_argument("--sweep-side", type=int, default=16384)
-    ap.add_argument("--sweep-rmax", type=int, default=16, help="largest radius of the sweep (int8 and direct reach 32)")
-    ap.add_argument("--life", action="store_true",
-                    help="also time the Life 256^2 workload (64 steps per run; its autotuning launches the "
-                         "benchmark's kernel at other shapes, so it is off in the profiled default run)")
+    ap.add_argument("--sweep-rmax", type=int, default=16)
+    ap.add_argument("--no-life", action="store_true", help="skip the Life 256^2 workload")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 512-instance batched workload")
+    ap.add_argument("--no-decay", action="store_true", help="skip the C=8 R16 decay workload on 32768^2")
+    ap.add_argument("--no-periodic", action="store_true", help="skip the headline workload on a torus")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baselines")
     ap.add_argument("--shard", type=int, default=0, metavar="N",
                     help="also time one GPU's row strip (1/N) of the sweep grid and the halo it would exchange")
-    ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--no-batch", action="store_true", help="skip the 512-instance batched workload")
-    ap.add_argument("--decay", action="store_true", help="also time the C=8 R16 decay workload on 32768^2")
     ap.add_argument("--energy", action="store_true",
                     help="also measure cell-updates per joule (CAT int8 and direct, Bosco R5 on 32768^2)")
-    ap.add_argument("--batch-tuning", type=str, default=BATCH_TUNING, help="T,tile_rows,tile_cols,waves of the batch")
-    ap.add_argument("--autotune", action="store_true", help="pick the launch shape with ltl_autotune")
-    ap.add_argument("--tuning", type=str, default=DEFAULT_TUNING,
-                    help="T,tile_rows,tile_cols,waves[,persistent] (default: the autotuner's pick on MI355X)")
+    ap.add_argument("--tuning", type=str, default="",
+                    help="T,tile_rows,tile_cols,waves[,persistent[,lds_pad]] for the headline (default: the "
+                         "library's own pick from its tuning table)")
     ap.add_argument("--calib-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (HBM counter calibration) and exit")
     args = ap.parse_args()
@@ -350,53 +505,49 @@ def main():
         print(json.dumps({"error": "this library runs on one GPU per process; --gpus must be 1"}))
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     from paper_2406_17284_amd import inputs, ltl
 
+    oracle = None
+    if not args.no_cpu:
+        import oracle as oracle_mod
+
+        oracle_mod.use_native()   # the oracle as it stands, compiled -O3 -march=native for this host
+        oracle = oracle_mod
+
     torch.cuda.set_device(0)
+    digests = load_digests()
     w = inputs.WORKLOADS["bosco4096"]
     g0_np = inputs.bernoulli_grid(w.H, w.W, w.p, w.seed)
     g0 = torch.from_numpy(g0_np).cuda()
     cells = w.H * w.W
+    t_wall0 = time.perf_counter()
 
-    # ---- CAT int8
-    sim = ltl.Simulation(g0, w.rule, "cat_i8")
-    if args.autotune:
-        sim.autotune(probe_steps=20)
-    else:
-        sim.set_tuning(**parse_tuning(args.tuning))
+    # ---- headline: CAT int8 on the Bosco workload
+    sim = ltl.Simulation(g0, w.rule, "cat_i8", tuning=parse_tuning(args.tuning) if args.tuning else None)
     tuning = sim.tuning()
     for _ in range(args.warmup):
         sim.step(w.steps)
-    secs, wall = timed_runs(sim, w.steps, args.steps, torch)
-    value = cells * w.steps * args.steps / secs
+    reset = sim_reset(sim, g0)
+    times = time_reps(sim.stream, lambda: sim.step(w.steps), reset, args.steps, torch)
+    secs = statistics.median(times)
+    cat_final = sim.read()
+    sim.close()
+    value = cells * w.steps / secs
     launches_per_run = math.ceil(w.steps / tuning["steps_per_launch"])
-    avg_launch_s = secs / (args.steps * launches_per_run)
+    avg_launch_s = secs / launches_per_run
     ops_per_launch = OPS_PER_CELL * cells * w.steps / launches_per_run
     achieved_tops = ops_per_launch / avg_launch_s / 1e12
-    sim.close()
+    ref100 = golden(digests, "bosco4096", w.steps)
+    log(f"headline: {value:.4e} cell-updates/s, {avg_launch_s * 1e6:.2f} us per launch")
 
     # ---- direct stencil, same workload
-    simd = ltl.Simulation(g0, w.rule, "direct")
-    simd.step(w.steps)
-    dsteps = max(1, min(args.steps, 3))
-    dsecs, _ = timed_runs(simd, w.steps, dsteps, torch)
-    direct_value = cells * w.steps * dsteps / dsecs
-    simd.close()
-
-    # ---- parity at the workload's own length: CAT vs direct on the GPU (and the oracle below)
-    a = ltl.Simulation(g0, w.rule, "cat_i8")
-    a.set_tuning(**{k: tuning[k] for k in SHAPE_KEYS})
-    a.step(w.steps)
-    b = ltl.Simulation(g0, w.rule, "direct")
-    b.step(w.steps)
-    cat_final = a.read().cpu().numpy()
-    direct_final = b.read().cpu().numpy()
-    a.close()
-    b.close()
-    parity = {"cat_vs_direct_equal": bool(np.array_equal(cat_final, direct_final))}
+    dsecs, direct_final, _, _ = sim_rate(ltl, torch, g0, w.rule, "direct", w.steps, 3)
+    direct_value = cells * w.steps / dsecs
+    parity = {"cat_vs_direct_equal": bool(torch.equal(cat_final, direct_final)),
+              "cat_vs_oracle_digest": None if ref100 is None else digest_of(cat_final) == ref100}
+    del direct_final
 
     out = {
         "metric": METRIC,
@@ -405,7 +556,7 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": secs / args.steps * 1e3,
+        "ms_per_step": secs * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -415,18 +566,22 @@ def main():
             "workload": "bosco4096: R5 C0 M1 S34..58 B34..45 N_M, 4096x4096 uint8, Bernoulli(0.5) seed 2, "
                         "dead ghost halo, 100 LTL steps per bench step",
             "method": "cat_i8",
-            "tuning": tuning,
+            "timing": f"median of {args.steps} runs, each restarting from the initial grid, after {args.warmup} "
+                      "untimed runs; HIP events on the simulation's stream",
+            "tuning": [tuning[k] for k in SHAPE_KEYS],
+            "tuning_source": "--tuning" if args.tuning else "library default (tuning table)",
+            "run_ms_min_max": [min(times) * 1e3, max(times) * 1e3],
             "direct_stencil_cell_updates_per_s": direct_value,
             "direct_stencil_algorithmic_GBs": 2 * direct_value / 1e9,   # one byte read + one written per cell-update
+            "direct_stencil_frac_valu": (2 * w.rule.R + 1) ** 2 * direct_value / VALU_PEAK_OPS,
             "cat_over_direct": value / direct_value,
-            "wall_s": wall,
         },
         "roofline": {
             "bound": "mfma",
             "achieved": achieved_tops,
-            "peak": INT8_PEAK_TOPS,
+            "peak": PEAK_TOPS["cat_i8"],
             "unit": "TFLOP/s",
-            "frac": achieved_tops / INT8_PEAK_TOPS,
+            "frac": achieved_tops / PEAK_TOPS["cat_i8"],
             "traffic": recorded_traffic(tuning),
             "kernel": "cat_step_i8",
             "ops_per_cell_update": OPS_PER_CELL,
@@ -446,84 +601,48 @@ def main():
         "parity": parity,
     }
 
-    if args.sweep:
-        sweep = {}
-        side = args.sweep_side
-        gs = inputs.bernoulli_grid_torch(side, side, 0.5, 3, device="cuda")
-        for r in range(1, args.sweep_rmax + 1):
-            rule = inputs.sweep_rule(r)
-            row = {}
-            for method in ("cat_i8", "cat_f16", "cat_f8", "direct"):
-                if (method == "cat_f8" and r > 7) or (method == "cat_f16" and r > 16):
-                    continue   # fp8-e4m3 counts are exact only for 2r+1 <= 16; fp16 covers r <= 16
-                s = ltl.Simulation(gs, rule, method)
-                if method != "direct":
-                    s.autotune(probe_steps=10)
-                s.step(50)
-                secs_r, _ = timed_runs(s, 50, 1, torch)
-                row[method] = side * side * 50 / secs_r
-                s.close()
-            sweep[str(r)] = row
-        out["sweep"] = {"workload": f"{side}x{side}, r=1..{args.sweep_rmax} sweep rules, Bernoulli(0.5) seed 3, 50 steps",
-                        "cell_updates_per_s": sweep}
-
+    if not args.no_periodic:
+        psecs, pfinal, _, _ = sim_rate(ltl, torch, g0, w.rule, "cat_i8", w.steps, 5, boundary="periodic")
+        dpsecs, dpfinal, _, _ = sim_rate(ltl, torch, g0, w.rule, "direct", w.steps, 1, boundary="periodic", warmup=0)
+        out["periodic"] = {"workload": "bosco4096 on a torus (periodic boundary, the paper's experimental setting)",
+                           "value": cells * w.steps / psecs, "unit": "cell-updates/s",
+                           "direct_stencil_cell_updates_per_s": cells * w.steps / dpsecs,
+                           "cat_vs_direct_equal": bool(torch.equal(pfinal, dpfinal))}
+        del pfinal, dpfinal
+        log("periodic done")
+    if not args.no_life:
+        out["life256"], life_final = bench_life(args, ltl, inputs, torch, digests)
+        log("life done")
+    if not args.no_sweep:
+        out["sweep"] = bench_sweep(args, ltl, inputs, torch, digests, oracle)
+    if not args.no_batch:
+        out["batched"] = bench_batch(args, ltl, inputs, torch, digests, oracle)
+        log("batch done")
+    if not args.no_decay:
+        out["decay"] = bench_decay(args, ltl, inputs, torch, digests, oracle)
+        log("decay done")
     if args.shard > 1:
         out["shard"] = bench_shard(args, ltl, inputs, torch)
-
-    # ---- the same workload on a torus (the paper's experimental boundary condition)
-    sp = ltl.Simulation(g0, w.rule, "cat_i8", boundary="periodic")
-    sp.set_tuning(**{k: tuning[k] for k in SHAPE_KEYS})
-    sp.step(w.steps)
-    psecs, _ = timed_runs(sp, w.steps, max(1, min(args.steps, 5)), torch)
-    pd = ltl.Simulation(g0, w.rule, "direct", boundary="periodic")
-    pc = ltl.Simulation(g0, w.rule, "cat_i8", boundary="periodic")
-    pc.set_tuning(**{k: tuning[k] for k in SHAPE_KEYS})
-    pd.step(w.steps)
-    pc.step(w.steps)
-    out["periodic"] = {"workload": "bosco4096 on a torus (periodic boundary)",
-                       "value": cells * w.steps * max(1, min(args.steps, 5)) / psecs, "unit": "cell-updates/s",
-                       "cat_vs_direct_equal": bool(torch.equal(pc.read(), pd.read()))}
-    for x in (sp, pd, pc):
-        x.close()
-
-    if not args.no_batch:
-        out["batched"] = bench_batch(args, ltl, inputs, torch)
-
-    if args.life:
-        out["life256"], life_init, life_final = bench_life(ltl, inputs, torch)
-    if args.decay:
-        out["decay"] = bench_decay(args, ltl, inputs, torch)
     if args.energy:
         out["energy"] = bench_energy(args, ltl, inputs, torch)
 
-    if not args.no_cpu:
-        import oracle
+    if oracle is not None:
+        # the headline workload: all 100 steps on every host thread (also the parity of the timed
+        # grid against the oracle itself), one thread over 2 steps (extrapolated per cell-update)
+        rates, ref = oracle_rates(oracle, inputs, lambda: g0_np, w.rule, w.steps, 2)
+        import numpy as np
 
-        threads = oracle.set_threads(0)
-        t0 = time.perf_counter()
-        one = oracle.run(g0_np, w.rule, 1)
-        t1 = time.perf_counter() - t0
-        n_cpu = int(max(1, min(w.steps - 1, 15.0 // max(t1, 1e-3))))
-        t0 = time.perf_counter()
-        res = oracle.run(one, w.rule, n_cpu)
-        tc = time.perf_counter() - t0
-        sample = f"bosco4096 grid, steps 2..{n_cpu + 1} of 100 ({n_cpu} steps, {t1 + tc:.1f} s total)"
-        if n_cpu + 1 == w.steps:
-            parity["cat_vs_oracle_equal"] = bool(np.array_equal(res, cat_final))
-        # one thread, one step (the single-thread figure of the same oracle)
-        oracle.set_threads(1)
-        t0 = time.perf_counter()
-        oracle.run(one, w.rule, 1)
-        t_single = time.perf_counter() - t0
-        oracle.set_threads(threads)
-        if args.life:
+        parity["cat_vs_oracle_equal"] = bool(np.array_equal(ref, cat_final.cpu().numpy()))
+        out["cpu_baseline"] = dict(rates, cpu_model=cpu_model(),
+                                   sample="bosco4096: all cores over the 100 steps of a bench step; one thread over "
+                                          "steps 1..2, extrapolated per cell-update")
+        if not args.no_life:
             lw = inputs.WORKLOADS["life256"]
-            out["life256"]["cat_vs_oracle_equal"] = bool(np.array_equal(oracle.run(life_init, lw.rule, lw.steps),
-                                                                         life_final))
-        out["cpu_baseline"] = {"value": cells * n_cpu / tc, "unit": "cell-updates/s", "cores": threads,
-                               "kind": "oracle", "sample": sample,
-                               "single_thread_value": cells / t_single,
-                               "cpu_model": cpu_model()}
+            lrates, lref = oracle_rates(oracle, inputs, lambda: inputs.bernoulli_grid(lw.H, lw.W, lw.p, lw.seed),
+                                        lw.rule, lw.steps, lw.steps)
+            out["life256"]["cat_vs_oracle_equal"] = bool(np.array_equal(lref, life_final.cpu().numpy()))
+            out["life256"]["cpu_baseline"] = dict(lrates, sample="life256: all 64 steps, all cores and one thread")
+    out["config"]["wall_s"] = time.perf_counter() - t_wall0
     print(json.dumps(out), flush=True)
 
 

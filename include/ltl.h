@@ -80,6 +80,8 @@ typedef struct {
                                  CU slot) that each walk a contiguous run of tiles, loading tile
                                  i+1 into a second LDS buffer while tile i computes (pays off when
                                  tiles stream from HBM); 0 = one workgroup per tile. Batches take 0. */
+    int32_t lds_pad;          /* CAT methods: extra bytes per LDS tile row, a multiple of 16 in 0..128;
+                                 it moves the LDS bank each row starts in (the direct method ignores it) */
 } ltl_tuning_t;
 
 typedef enum {
@@ -90,58 +92,82 @@ typedef enum {
 typedef struct ltl_sim ltl_sim_t;
 typedef struct ltl_batch ltl_batch_t;
 
-/* Bytes of EACH of the two ping-pong buffers for an H x W grid (row pitch
- * ltl_pitch(W), H rows). Returns LTL_ERR_ARG for H < 1 or W < 1. */
-int32_t ltl_buffer_bytes(int32_t H, int32_t W, size_t *bytes);
+/* Bytes of EACH of the two ping-pong buffers of an H x W grid ("Pseudocode of CAT's Kernel":
+ * the step reads one buffer and writes the other). Layout: H rows of ltl_pitch(W) bytes, one
+ * state per byte; the ghost halo of "Formulation of CAT" is not stored (tile loads read dead
+ * cells, or the opposite edge on a torus, for positions outside the grid), so the size does
+ * not depend on R or the method, which are checked (R in 1..32, a known method) all the same.
+ * Returns 0 on an invalid argument (message in ltl_last_error). */
+size_t ltl_buffer_bytes(int32_t H, int32_t W, int32_t R, int32_t method);
 
-/* Row pitch in bytes of the library's grid layout: W rounded up to 64. */
+/* Row pitch in bytes of the library's grid layout: W rounded up to 64. LTL_ERR_ARG for W < 1. */
 int32_t ltl_pitch(int32_t W, int32_t *pitch);
 
-/* Create a simulation of an H x W grid.
+/* Create a simulation of an H x W grid under an LTL rule ("Chosen CA tests": rule notation
+ * R, C, M, S, B, N; "Experimental Design": the random initial grids it starts from).
  *  rule       host pointer, copied.
- *  method     an ltl_method_t.
- *  buf_a/b    two device buffers of buf_bytes >= ltl_buffer_bytes(H, W) each, 256-byte aligned;
- *             the library owns their contents until ltl_destroy.
+ *  method     an ltl_method_t (CAT: "Formulation of CAT"; direct: the SHARED scheme of
+ *             "Approaches Selected for Evaluation").
+ *  buf_a/b    two device buffers of buf_bytes >= ltl_buffer_bytes(H, W, R, method) each, 256-byte
+ *             aligned; owned by the caller, their contents owned by the library until ltl_destroy.
  *  init       device pointer to H rows of W uint8 states, row pitch init_pitch >= W bytes;
  *             read before ltl_create returns. Every state must be < max(C, 2) (else LTL_ERR_STATE).
  *  stream     HIP stream for all work of this handle (0 = null stream).
+ * The launch shape starts as the tuning table's entry for this rule class, radius, grid size
+ * and boundary (ltl_tuning_lookup; the environment variable LTL_TILE =
+ * "T,rows,cols,waves[,persistent[,lds_pad]]" overrides it, and a malformed or infeasible
+ * LTL_TILE is refused with LTL_ERR_ARG), else a built-in default.
  * A grid may hold at most 2^31 - 1 bytes in the library layout (H x ltl_pitch(W); e.g. up to
- * 46340 x 46340 cells); larger grids are refused with LTL_ERR_SIZE.
+ * 46340 x 46340 cells); larger grids are refused with LTL_ERR_SIZE. The handle allocates only
+ * host metadata, cached hipGraphs and a 12 KiB device block (band operands and a zero page).
  * ltl_create synchronizes `stream` once (state validation); later calls do not. */
 int32_t ltl_create(ltl_sim_t **out, int32_t H, int32_t W, const ltl_rule_t *rule, int32_t method,
                    void *buf_a, void *buf_b, size_t buf_bytes, const void *init, size_t init_pitch,
                    hipStream_t stream);
 
-/* Enqueue n_steps >= 0 synchronous steps. ltl_step(a); ltl_step(b) equals ltl_step(a + b)
- * cell for cell. With use_graph, the steps run as replays of cached hipGraphs of at most 64
- * launches each (steps_per_launch x 64 steps); the first call with a new length builds them. */
+/* Enqueue n_steps >= 0 synchronous steps (Algorithm 1 per tile: the two band products of
+ * Eq. 2-3 and the transition, ping-pong between the buffers). ltl_step(a); ltl_step(b) equals
+ * ltl_step(a + b) cell for cell. With use_graph, the steps run as replays of cached hipGraphs
+ * of at most 64 launches each (steps_per_launch x 64 steps); the first call with a new length
+ * builds them. */
 int32_t ltl_step(ltl_sim_t *sim, int32_t n_steps);
 
-/* Enqueue a copy of the current H x W states into device memory dst (row pitch dst_pitch >= W). */
+/* Enqueue a copy of the current H x W states ("Pseudocode of CAT's Kernel": the buffer the last
+ * step wrote) into device memory dst (row pitch dst_pitch >= W). */
 int32_t ltl_read(ltl_sim_t *sim, void *dst, size_t dst_pitch);
 
 /* Device buffer holding the current state in the library layout (H rows of *pitch bytes;
  * columns W..pitch-1 are always 0), and the number of steps taken so far. */
 int32_t ltl_current(ltl_sim_t *sim, void **buf, size_t *pitch, int64_t *steps_done);
 
-/* Current launch shape, and replacing it (validated; LTL_ERR_ARG on an invalid field). */
+/* Current launch shape ("Optimal Tile per CUDA block": the tile a workgroup computes), and
+ * replacing it (validated; LTL_ERR_ARG on an invalid field). set_tuning synchronizes the
+ * stream before it drops the cached graphs. */
 int32_t ltl_get_tuning(ltl_sim_t *sim, ltl_tuning_t *tuning);
 int32_t ltl_set_tuning(ltl_sim_t *sim, const ltl_tuning_t *tuning);
 
-/* Time candidate launch shapes on this simulation (each on a device copy of the current
- * state, so the simulation itself does not advance, for the whole number of its launches
- * that covers at least probe_steps steps, 1..4096), keep the fastest per step and return it
- * in *best (may be NULL). Synchronizes the stream. */
-int32_t ltl_autotune(ltl_sim_t *sim, int32_t probe_steps, ltl_tuning_t *best);
+/* Time candidate launch shapes on this simulation ("Optimal Tile per CUDA block": the tile
+ * shape is chosen by measurement) and keep the fastest per step; *best (may be NULL) receives
+ * it. The probes run on the handle's own ping-pong buffers: the current state is first copied
+ * into `scratch` (caller-owned device memory of scratch_bytes >= ltl_buffer_bytes(...), not
+ * one of the two buffers; LTL_ERR_SIZE if smaller), every candidate starts from that copy, and
+ * the state is restored from it at the end, so the simulation does not advance. Each
+ * candidate runs the whole number of its own launches that covers at least probe_steps steps
+ * (1..4096). The pick is also stored in the user tuning cache (ltl_tuning_store). Allocates
+ * no device memory; synchronizes the stream. */
+int32_t ltl_autotune(ltl_sim_t *sim, int32_t probe_steps, void *scratch, size_t scratch_bytes,
+                     ltl_tuning_t *best);
 
 /* Boundary condition of the grid (default LTL_BOUNDARY_DEAD).
- *  LTL_BOUNDARY_DEAD      ghost halo of dead cells: every cell outside the grid is 0 forever.
+ *  LTL_BOUNDARY_DEAD      ghost halo of dead cells ("Formulation of CAT"): every cell outside the
+ *                         grid is 0 forever.
  *  LTL_BOUNDARY_PERIODIC  the grid is a torus (the paper's experimental setting, "Experimental
- *                         design"): the box of a cell wraps around both edges, offset (di, dj)
+ *                         Design"): the box of a cell wraps around both edges, offset (di, dj)
  *                         reaching cell ((i + di) mod H, (j + dj) mod W); on a torus smaller
  *                         than the box a cell is counted once per offset that reaches it.
  *                         Requires W % 16 == 0 (else LTL_ERR_UNSUPPORTED).
- * Takes effect for the following steps; columns W..pitch-1 of the buffers stay 0. */
+ * Takes effect for the following steps; columns W..pitch-1 of the buffers stay 0. Synchronizes
+ * the stream before it drops the cached graphs. */
 int32_t ltl_set_boundary(ltl_sim_t *sim, int32_t boundary);
 
 /* Release the handle (graphs, descriptors). Does not free the caller's buffers and does
@@ -152,13 +178,40 @@ int32_t ltl_destroy(ltl_sim_t *sim);
 const char *ltl_last_error(void);
 
 /* ----------------------------------------------------------------------------------
+ * Tuning table ("Optimal Tile per CUDA block": the best tile depends on the radius and the
+ * grid size, and is found by measurement). Entries are keyed by method, element type
+ * ("i8", "i8w" for R > 16, "i8x" for the cross, "f16", "f8", "direct"), epilogue class
+ * ("byte", "win", "half", "decay"; "mixed" for batches), R (0 for batches), the size bucket
+ * round(log2(sqrt(cells))) (a batch: its total cells), boundary ("dead", "periodic") and
+ * batched (0/1). Two JSON files hold entries: the user cache (the environment variable
+ * LTL_TUNE_CACHE names it; default $XDG_CACHE_HOME/ltl/tuning.json or
+ * ~/.cache/ltl/tuning.json; "off" disables it), consulted first, and the table shipped next
+ * to the library (tuning.json beside libltl.so; LTL_TUNE_TABLE overrides its path). A lookup
+ * takes the exact key, else the entry of the same method, element, epilogue class, boundary
+ * and batched with the nearest R, then the nearest bucket. Host-only (no device calls). */
+
+/* Fill *out with the entry for a grid (batched = 0: H, W, rule are one grid's; batched = 1:
+ * H = total cells, W = 1, rule = the batch's largest radius). *exact (may be NULL) is 1 for an
+ * exact key. LTL_OK if an entry was found; LTL_ERR_ARG (no entry) leaves *out zeroed. Callers
+ * validate the shape for their grid before use (ltl_create falls back to the next candidate). */
+int32_t ltl_tuning_lookup(int32_t H, int32_t W, const ltl_rule_t *rule, int32_t method, int32_t boundary,
+                          int32_t batched, ltl_tuning_t *out, int32_t *exact);
+/* Insert or replace the entry of that key in the user cache file (created with its directory
+ * if missing), ms_per_step recorded beside it. LTL_ERR_ARG if the cache is "off" or unwritable. */
+int32_t ltl_tuning_store(int32_t H, int32_t W, const ltl_rule_t *rule, int32_t method, int32_t boundary,
+                         int32_t batched, const ltl_tuning_t *tuning, double ms_per_step);
+
+/* ----------------------------------------------------------------------------------
  * Batched simulation: `count` independent automata, each with its own size and rule,
- * advance together in one kernel launch per T steps (tuning.steps_per_launch). The launch
- * covers a work list with one entry per (instance, tile), sorted by decreasing estimated
- * cost, one workgroup per entry (dispatched longest first; each XCD takes contiguous blocks
- * of an instance's tiles). Multi-launch calls are replayed from a cached hipGraph. Each instance follows exactly the semantics of a single simulation of its
- * own (dead ghost halo around each grid; no interaction between instances), so instance i
- * after n batched steps equals ltl_create + ltl_step(n) of that grid and rule, cell for cell.
+ * advance together in one kernel launch per T steps (tuning.steps_per_launch). The paper
+ * simulates one grid; batching is this library's addition, and each instance runs the
+ * per-tile work of Algorithm 1 with its own band operands and rule. The launch covers a work
+ * list with one entry per (instance, tile), sorted by decreasing estimated cost, one
+ * workgroup per entry (dispatched longest first; each XCD takes contiguous blocks of an
+ * instance's tiles). Multi-launch calls are replayed from a cached hipGraph. Each instance
+ * follows exactly the semantics of a single simulation of its own (dead ghost halo around
+ * each grid; no interaction between instances), so instance i after n batched steps equals
+ * ltl_create + ltl_step(n) of that grid and rule, cell for cell.
  *
  *  H, W, rules    host arrays of `count` entries (copied).
  *  method         one ltl_method_t for every instance (LTL_CAT_F8 requires R <= 7 for all).
@@ -171,9 +224,13 @@ const char *ltl_last_error(void);
  *  stream         HIP stream for all work of this handle.
  * Errors as ltl_create, for the first failing instance (its index is in ltl_last_error).
  * The tuning's tile shape is the largest tile; each instance uses that tile grid with its
- * tiles shrunk evenly to cover its grid with the least padding. All work of a handle runs on
+ * tiles shrunk evenly to cover its grid with the least padding. The launch shape starts as
+ * the tuning table's batched entry (LTL_TILE overrides it), else a built-in default. The
+ * handle allocates host metadata, cached hipGraphs and device descriptors (band operands of
+ * every radius, per-instance launch parameters, the work list). All work of a handle runs on
  * its one stream. */
-int32_t ltl_batch_buffer_bytes(int32_t count, const int32_t *H, const int32_t *W, size_t *bytes);
+/* Bytes of each arena (0 on an invalid argument). */
+size_t ltl_batch_buffer_bytes(int32_t count, const int32_t *H, const int32_t *W);
 int32_t ltl_batch_create(ltl_batch_t **out, int32_t count, const int32_t *H, const int32_t *W,
                          const ltl_rule_t *rules, int32_t method, void *arena_a, void *arena_b,
                          size_t bytes, const void *const *init, const size_t *init_pitch,
@@ -187,15 +244,19 @@ int32_t ltl_batch_read(ltl_batch_t *batch, int32_t index, void *dst, size_t dst_
 /* Device address and row pitch of instance `index`'s current states in the arenas (columns
  * W..pitch-1 are always 0), and the number of steps taken so far. */
 int32_t ltl_batch_current(ltl_batch_t *batch, int32_t index, void **buf, size_t *pitch, int64_t *steps_done);
-/* Launch shape of the batch: zero fields take defaults (T = 1, 128 x 192 tiles, fewest waves
- * that fit every instance). Validated against every instance (LTL_ERR_ARG). set_tuning
- * synchronizes the stream (launch descriptors are rebuilt). */
+/* Launch shape of the batch ("Optimal Tile per CUDA block"): zero fields take defaults (T = 1,
+ * 128 x 192 tiles, fewest waves that fit every instance). Validated against every instance
+ * (LTL_ERR_ARG). set_tuning synchronizes the stream (launch descriptors are rebuilt). */
 int32_t ltl_batch_get_tuning(ltl_batch_t *batch, ltl_tuning_t *tuning);
 int32_t ltl_batch_set_tuning(ltl_batch_t *batch, const ltl_tuning_t *tuning);
-/* Time candidate shapes (on a device copy of the arenas, the batch itself does not advance;
- * each for the whole number of its launches that covers at least probe_steps steps,
- * 1..4096), keep the fastest per step, return it in *best (may be NULL). Synchronizes. */
-int32_t ltl_batch_autotune(ltl_batch_t *batch, int32_t probe_steps, ltl_tuning_t *best);
+/* Time candidate shapes and keep the fastest per step, as ltl_autotune: the arenas' current
+ * contents are copied into `scratch` (caller-owned, scratch_bytes >= ltl_batch_buffer_bytes),
+ * each candidate starts from that copy on the batch's own arenas, and the state is restored
+ * at the end (the batch does not advance). Each candidate runs the whole number of its
+ * launches covering at least probe_steps steps (1..4096). The pick goes to the user tuning
+ * cache. Allocates only the candidates' descriptors; synchronizes. */
+int32_t ltl_batch_autotune(ltl_batch_t *batch, int32_t probe_steps, void *scratch, size_t scratch_bytes,
+                           ltl_tuning_t *best);
 /* Release the handle; does not free the arenas or synchronize. NULL is accepted. */
 int32_t ltl_batch_destroy(ltl_batch_t *batch);
 

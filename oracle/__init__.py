@@ -35,21 +35,39 @@ _lib: Optional[ctypes.CDLL] = None
 
 
 def build(force: bool = True) -> str:
-    """Compile the C oracle with gcc (OpenMP)."""
+    """Compile the C oracle with gcc (OpenMP). -march=x86-64-v3 (AVX2) runs on every host
+    this is used on and lets gcc vectorize the box sum; the code itself is unchanged."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c11",
+        subprocess.check_call(["gcc", "-O3", "-march=x86-64-v3", "-fopenmp", "-fPIC", "-shared", "-std=c11",
                                "-Wall", "-o", tmp, _SRC])
         os.replace(tmp, _LIB)
     return _LIB
 
 
-def _load() -> ctypes.CDLL:
+def use_native() -> str:
+    """Compile the same source with -march=native for the host this runs on (into a temporary
+    directory) and use that build from here on; the CPU-baseline timing uses it. The code is
+    unchanged; only the compiler's instruction selection differs."""
+    global _lib
+    import tempfile
+
+    out = os.path.join(tempfile.mkdtemp(prefix="ltl_oracle_"), "libltl_oracle_native.so")
+    subprocess.check_call(["gcc", "-O3", "-march=native", "-fopenmp", "-fPIC", "-shared", "-std=c11",
+                           "-Wall", "-o", out, _SRC])
+    _lib = None
+    _load(out)
+    return out
+
+
+def _load(path: Optional[str] = None) -> ctypes.CDLL:
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-            build(force=True)
-        lib = ctypes.CDLL(_LIB)
+        if path is None:
+            path = _LIB
+            if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+                build(force=True)
+        lib = ctypes.CDLL(path)
         P = ctypes.c_void_p
         I64, I = ctypes.c_int64, ctypes.c_int
         lib.oracle_count.argtypes = [P, I64, I64, I, P]

@@ -14,6 +14,7 @@
 #include "host_common.h"
 #include "ltl.h"
 #include "ltl_internal.h"
+#include "tuning_cache.h"
 
 using namespace ltl;
 using namespace ltl::host;
@@ -86,7 +87,8 @@ CatParams batch_cat_params(const ltl_batch &b, int i, const ltl_tuning_t &t, int
     instance_tile(p.H, p.W, t.tile_rows, t.tile_cols, &p.TH, &p.TW);
     p.L = cat_margin(elem_of(b.method, 16, 'M'), p.r, T);
     p.lds_rows = p.TH + 2 * p.L;
-    cat_lds_layout(elem_of(b.method, 16, 'M'), b.epi[i], p.TH, p.TW, p.L, &p.PS, &p.PA, &p.lds_tile, &p.a_tile, &p.lds_total);
+    cat_lds_layout(elem_of(b.method, 16, 'M'), b.epi[i], p.TH, p.TW, p.L, t.lds_pad, &p.PS, &p.PA, &p.lds_tile,
+                   &p.a_tile, &p.lds_total);
     p.ntx = (p.W + p.TW - 1) / p.TW;
     p.nty = (p.H + p.TH - 1) / p.TH;
     p.bands = reinterpret_cast<const int32_t *>(b.dconst + (p.r - 1) * kBandBytes);
@@ -130,6 +132,7 @@ ltl_tuning_t batch_fill_tuning(const ltl_batch &b, const ltl_tuning_t &in) {
     if (t.tile_cols == 0) t.tile_cols = 192;
     if (b.method == LTL_DIRECT) {
         t.waves = direct_threads() / 64;
+        t.lds_pad = 0;
     } else if (t.waves == 0) {   // fewest waves (power of two) that fit every instance
         t.waves = 1;
         while (t.waves < 8 && !batch_fits(b, t)) t.waves *= 2;
@@ -166,6 +169,7 @@ int32_t batch_check_tuning(const ltl_batch &b, const ltl_tuning_t &t) {
     if (t.tile_rows < 16 || t.tile_rows > 512 || t.tile_rows % 16) return fail(LTL_ERR_ARG, "tile_rows must be a multiple of 16 in 16..512");
     if (t.tile_cols < 32 || t.tile_cols > 512 || t.tile_cols % 32) return fail(LTL_ERR_ARG, "tile_cols must be a multiple of 32 in 32..512");
     if (t.persistent) return fail(LTL_ERR_ARG, "batches have no persistent form (persistent must be 0)");
+    if (t.lds_pad < 0 || t.lds_pad > 128 || t.lds_pad % 16) return fail(LTL_ERR_ARG, "lds_pad must be a multiple of 16 in 0..128");
     if (b.method == LTL_DIRECT) {
         if (t.steps_per_launch != 1) return fail(LTL_ERR_ARG, "the direct method takes one step per launch");
         return LTL_OK;
@@ -179,13 +183,18 @@ int32_t batch_check_tuning(const ltl_batch &b, const ltl_tuning_t &t) {
     return LTL_OK;
 }
 
+// Executable graphs are destroyed only once the stream has drained: a replay enqueued by an
+// earlier step call may still be running.
 void batch_clear_graphs(ltl_batch &b) {
+    if (b.graphs.empty()) return;
+    (void)hipStreamSynchronize(b.stream);
     for (auto &kv : b.graphs) (void)hipGraphExecDestroy(kv.second);
     b.graphs.clear();
 }
 
 void batch_free_plans(ltl_batch &b) {
     batch_clear_graphs(b);
+    if (!b.plans.empty() || b.ditems) (void)hipStreamSynchronize(b.stream);   // descriptors in use by queued launches
     for (auto &pl : b.plans)
         if (pl.dinst) (void)hipFree(pl.dinst);
     b.plans.clear();
@@ -437,74 +446,139 @@ int32_t batch_steps(ltl_batch &b, int32_t n) {
     return LTL_OK;
 }
 
-// Time candidate launch shapes on a copy of the current arenas and keep the fastest.
-int32_t batch_autotune(ltl_batch &b, int probe_steps, ltl_tuning_t *best) {
+// Key of the batch in the tuning table: its total cells and largest radius.
+TuneKey batch_key(const ltl_batch &b) {
+    double cells = 0;
+    int rmax = 1;
+    for (int i = 0; i < b.count; ++i) {
+        cells += (double)b.H[i] * b.W[i];
+        rmax = std::max(rmax, (int)b.rule[i].R);
+    }
+    ltl_rule_t r = b.rule[0];
+    r.R = rmax;
+    TuneKey k = make_key(1, 1, r, b.method, LTL_BOUNDARY_DEAD, 1);
+    k.bucket = size_bucket(cells);
+    return k;
+}
+
+// Launch shape of a new batch: LTL_TILE if set (refused if malformed or infeasible), else the
+// first feasible tuning-table candidate, else the built-in default.
+int32_t batch_initial_tuning(ltl_batch &b, ltl_tuning_t *out) {
+    ltl_tuning_t t;
+    std::string err;
+    const int env = env_tile(&t, &err);
+    if (env < 0) return fail(LTL_ERR_ARG, err);
+    if (env > 0) {
+        if (b.method == LTL_DIRECT) t.steps_per_launch = 1;
+        t.persistent = 0;
+        t = batch_fill_tuning(b, t);
+        if (batch_check_tuning(b, t) != LTL_OK) return fail(LTL_ERR_ARG, "LTL_TILE: " + g_err);
+        *out = t;
+        return LTL_OK;
+    }
+    const std::string saved = g_err;
+    for (ltl_tuning_t c : tuning_candidates(batch_key(b), nullptr)) {
+        c = batch_fill_tuning(b, c);
+        if (batch_check_tuning(b, c) == LTL_OK) {
+            *out = c;
+            g_err = saved;
+            return LTL_OK;
+        }
+    }
+    g_err = saved;
+    *out = batch_default_tuning(b);
+    return batch_check_tuning(b, *out);
+}
+
+// Time candidate launch shapes on the batch's own arenas (the current state saved in the
+// caller's scratch and restored before each candidate and at the end); keep the fastest.
+int32_t batch_autotune(ltl_batch &b, int probe_steps, void *scratch, size_t scratch_bytes, ltl_tuning_t *best) {
     if (b.method == LTL_DIRECT) {
         if (best) *best = b.tuning;
         return LTL_OK;
     }
+    if (!scratch) return fail(LTL_ERR_ARG, "scratch is NULL");
+    if (scratch_bytes < b.arena_bytes) return fail(LTL_ERR_SIZE, "scratch needs " + std::to_string(b.arena_bytes) + " bytes");
+    if (scratch == b.arena[0] || scratch == b.arena[1]) return fail(LTL_ERR_ARG, "scratch must not be one of the arenas");
+    HIP_TRY(hipMemcpyAsync(scratch, b.arena[b.cur], b.arena_bytes, hipMemcpyDeviceToDevice, b.stream), "hipMemcpyAsync");
     HIP_TRY(hipStreamSynchronize(b.stream), "hipStreamSynchronize");
     ltl_batch probe;
     probe.count = b.count; probe.method = b.method; probe.H = b.H; probe.W = b.W; probe.pitch = b.pitch;
     probe.rule = b.rule; probe.epi = b.epi; probe.rc = b.rc; probe.off = b.off; probe.arena_bytes = b.arena_bytes;
     probe.stream = b.stream; probe.owns_shared = false;
     probe.dconst = b.dconst; probe.dflag = b.dflag;
-    for (int a = 0; a < 2; ++a) {
-        hipError_t e = hipMalloc(&probe.arena[a], b.arena_bytes);
-        if (e != hipSuccess) {
-            if (probe.arena[0]) (void)hipFree(probe.arena[0]);
-            return hip_fail(e, "hipMalloc (autotune scratch)");
-        }
-    }
+    probe.arena[0] = b.arena[0];
+    probe.arena[1] = b.arena[1];
     hipEvent_t ev0, ev1;
-    (void)hipEventCreate(&ev0);
-    (void)hipEventCreate(&ev1);
+    HIP_TRY(hipEventCreate(&ev0), "hipEventCreate");
+    if (hipEventCreate(&ev1) != hipSuccess) { (void)hipEventDestroy(ev0); return fail(LTL_ERR_HIP, "hipEventCreate"); }
+    float best_ms = 1e30f;
+    ltl_tuning_t best_t = b.tuning;
+    int32_t rc = LTL_OK;
+    auto time_one = [&](ltl_tuning_t t, float *ms_out) -> int32_t {
+        *ms_out = -1.f;
+        t = batch_fill_tuning(probe, t);
+        std::string saved = g_err;
+        if (batch_check_tuning(probe, t) != LTL_OK) { g_err = saved; return LTL_OK; }
+        // each candidate runs a whole number of its own launches (no shorter remainder launch
+        // to bias it) covering at least probe_steps steps; candidates compare per step
+        const int T = t.steps_per_launch;
+        const int n = T * ((probe_steps + T - 1) / T);
+        probe.tuning = t;
+        int32_t r2 = batch_prepare(probe);
+        if (r2 != LTL_OK) return r2;
+        HIP_TRY(hipMemcpyAsync(b.arena[b.cur], scratch, b.arena_bytes, hipMemcpyDeviceToDevice, b.stream), "hipMemcpyAsync");
+        probe.cur = b.cur;
+        if ((r2 = batch_steps(probe, n)) != LTL_OK) return r2;   // warm-up + graph build
+        float ms = 1e30f;
+        for (int rep = 0; rep < 2; ++rep) {   // the faster of two timed runs
+            HIP_TRY(hipEventRecord(ev0, b.stream), "hipEventRecord");
+            if ((r2 = batch_steps(probe, n)) != LTL_OK) return r2;
+            HIP_TRY(hipEventRecord(ev1, b.stream), "hipEventRecord");
+            HIP_TRY(hipEventSynchronize(ev1), "autotune sync");
+            float m = 0;
+            HIP_TRY(hipEventElapsedTime(&m, ev0, ev1), "hipEventElapsedTime");
+            ms = std::min(ms, m);
+        }
+        *ms_out = ms / (float)n;
+        return LTL_OK;
+    };
     const int Ts[] = {1, 2, 3, 4};
     const int tiles[][2] = {{64, 64}, {64, 128}, {128, 128}, {128, 192}, {192, 128}, {128, 224}, {160, 160},
                             {192, 192}, {160, 224}, {176, 224}};
     const int wavess[] = {0, 8};
-    float best_ms = 1e30f;
-    ltl_tuning_t best_t = b.tuning;
-    int32_t rc = LTL_OK;
-    for (int T : Ts) {
-        // each candidate runs a whole number of its own launches (no shorter remainder launch
-        // to bias it) covering at least probe_steps steps; candidates compare per step
-        const int n = T * ((probe_steps + T - 1) / T);
-        for (auto &tl : tiles) {
+    for (int T : Ts)
+        for (auto &tl : tiles)
             for (int wv : wavess) {
                 ltl_tuning_t t;
                 std::memset(&t, 0, sizeof(t));
                 t.steps_per_launch = T; t.tile_rows = tl[0]; t.tile_cols = tl[1]; t.waves = wv; t.use_graph = 1;
-                t = batch_fill_tuning(probe, t);
-                std::string saved = g_err;
-                if (batch_check_tuning(probe, t) != LTL_OK) { g_err = saved; continue; }
-                probe.tuning = t;
-                if ((rc = batch_prepare(probe)) != LTL_OK) goto done;
-                (void)hipMemcpyAsync(probe.arena[0], b.arena[b.cur], b.arena_bytes, hipMemcpyDeviceToDevice, b.stream);
-                probe.cur = 0;
-                if ((rc = batch_steps(probe, n)) != LTL_OK) goto done;   // warm-up + graph build
-                (void)hipEventRecord(ev0, b.stream);
-                if ((rc = batch_steps(probe, n)) != LTL_OK) goto done;
-                (void)hipEventRecord(ev1, b.stream);
-                if (hipEventSynchronize(ev1) != hipSuccess) { rc = fail(LTL_ERR_HIP, "autotune sync"); goto done; }
-                float ms = 0;
-                (void)hipEventElapsedTime(&ms, ev0, ev1);
-                ms /= (float)n;
-                if (ms < best_ms) { best_ms = ms; best_t = t; }
+                float ms;
+                if ((rc = time_one(t, &ms)) != LTL_OK) goto done;
+                if (ms >= 0 && ms < best_ms) { best_ms = ms; best_t = batch_fill_tuning(probe, t); }
             }
-        }
+    for (int pad : {16, 32, 64}) {
+        ltl_tuning_t t = best_t;
+        t.lds_pad = pad;
+        float ms;
+        if ((rc = time_one(t, &ms)) != LTL_OK) goto done;
+        if (ms >= 0 && ms < best_ms) { best_ms = ms; best_t = t; }
     }
 done:
-    (void)hipStreamSynchronize(b.stream);
-    batch_release(probe);
-    (void)hipEventDestroy(ev0);
-    (void)hipEventDestroy(ev1);
-    (void)hipFree(probe.arena[0]);
-    (void)hipFree(probe.arena[1]);
-    if (rc != LTL_OK) return rc;
+    {
+        hipError_t re = hipMemcpyAsync(b.arena[b.cur], scratch, b.arena_bytes, hipMemcpyDeviceToDevice, b.stream);
+        if (re == hipSuccess) re = hipStreamSynchronize(b.stream);
+        batch_release(probe);
+        (void)hipEventDestroy(ev0);
+        (void)hipEventDestroy(ev1);
+        if (rc != LTL_OK) return rc;
+        if (re != hipSuccess) return hip_fail(re, "autotune restore");
+    }
     b.tuning = best_t;
     if ((rc = batch_prepare(b)) != LTL_OK) return rc;
     if (best) *best = best_t;
+    std::string err;
+    if (best_ms < 1e29f && !user_cache_path().empty()) (void)store_tuning(batch_key(b), best_t, best_ms, &err);
     return LTL_OK;
 }
 
@@ -513,15 +587,14 @@ done:
 extern "C" {
 
 // ---------------------------------------------------------------------- batched API
-int32_t ltl_batch_buffer_bytes(int32_t count, const int32_t *H, const int32_t *W, size_t *bytes) {
-    if (!bytes || !H || !W || count < 1) return fail(LTL_ERR_ARG, "count must be >= 1 and arrays non-NULL");
+size_t ltl_batch_buffer_bytes(int32_t count, const int32_t *H, const int32_t *W) {
+    if (!H || !W || count < 1) { fail(LTL_ERR_ARG, "count must be >= 1 and arrays non-NULL"); return 0; }
     size_t total = 0;
     for (int i = 0; i < count; ++i) {
-        if (H[i] < 1 || W[i] < 1) return fail(LTL_ERR_ARG, "every H and W must be >= 1");
+        if (H[i] < 1 || W[i] < 1) { fail(LTL_ERR_ARG, "every H and W must be >= 1"); return 0; }
         total += arena_slot_bytes(H[i], W[i]);
     }
-    *bytes = total;
-    return LTL_OK;
+    return total;
 }
 
 int32_t ltl_batch_create(ltl_batch_t **out, int32_t count, const int32_t *H, const int32_t *W,
@@ -534,9 +607,9 @@ int32_t ltl_batch_create(ltl_batch_t **out, int32_t count, const int32_t *H, con
     if (!arena_a || !arena_b) return fail(LTL_ERR_ARG, "NULL arena");
     if (arena_a == arena_b) return fail(LTL_ERR_ARG, "the two arenas must differ");
     if (((uintptr_t)arena_a & 255) || ((uintptr_t)arena_b & 255)) return fail(LTL_ERR_ARG, "arenas must be 256-byte aligned");
-    size_t need = 0;
-    int32_t rc = ltl_batch_buffer_bytes(count, H, W, &need);
-    if (rc != LTL_OK) return rc;
+    const size_t need = ltl_batch_buffer_bytes(count, H, W);
+    if (need == 0) return LTL_ERR_ARG;
+    int32_t rc = LTL_OK;
     for (int i = 0; i < count; ++i) {
         if ((rc = validate_rule(rules + i, method)) != LTL_OK) return fail(rc, "instance " + std::to_string(i) + ": " + g_err);
         if (method != LTL_DIRECT && rules[i].R > 16)
@@ -549,6 +622,11 @@ int32_t ltl_batch_create(ltl_batch_t **out, int32_t count, const int32_t *H, con
             return fail(LTL_ERR_SIZE, "instance " + std::to_string(i) + ": grid larger than 2^31 - 1 bytes");
     }
     if (bytes < need) return fail(LTL_ERR_SIZE, "arenas need " + std::to_string(need) + " bytes each");
+    {
+        ltl_tuning_t t;
+        std::string err;
+        if (env_tile(&t, &err) < 0) return fail(LTL_ERR_ARG, err);   // malformed LTL_TILE, before any device work
+    }
 
     ltl_batch *b = new (std::nothrow) ltl_batch();
     if (!b) return fail(LTL_ERR_ARG, "out of host memory");
@@ -602,8 +680,8 @@ int32_t ltl_batch_create(ltl_batch_t **out, int32_t count, const int32_t *H, con
         if ((e = hipMemcpy2DAsync(b->arena[0] + b->off[i], b->pitch[i], init[i], init_pitch[i], W[i], H[i],
                                   hipMemcpyDeviceToDevice, stream)) != hipSuccess)
             return bail(hip_fail(e, "hipMemcpy2DAsync"));
-    ltl_tuning_t t = batch_default_tuning(*b);
-    if ((rc = batch_check_tuning(*b, t)) != LTL_OK) return bail(rc);
+    ltl_tuning_t t;
+    if ((rc = batch_initial_tuning(*b, &t)) != LTL_OK) return bail(rc);
     b->tuning = t;
     if ((rc = batch_prepare(*b)) != LTL_OK) return bail(rc);
     *out = b;
@@ -651,10 +729,11 @@ int32_t ltl_batch_set_tuning(ltl_batch_t *batch, const ltl_tuning_t *tuning) {
     return batch_prepare(*batch);
 }
 
-int32_t ltl_batch_autotune(ltl_batch_t *batch, int32_t probe_steps, ltl_tuning_t *best) {
+int32_t ltl_batch_autotune(ltl_batch_t *batch, int32_t probe_steps, void *scratch, size_t scratch_bytes,
+                           ltl_tuning_t *best) {
     if (!batch) return fail(LTL_ERR_ARG, "batch is NULL");
     if (probe_steps < 1 || probe_steps > 4096) return fail(LTL_ERR_ARG, "probe_steps must be in 1..4096");
-    return batch_autotune(*batch, probe_steps, best);
+    return batch_autotune(*batch, probe_steps, scratch, scratch_bytes, best);
 }
 
 int32_t ltl_batch_destroy(ltl_batch_t *batch) {

@@ -19,6 +19,7 @@
 #include "ltl.h"
 #include "host_common.h"
 #include "ltl_internal.h"
+#include "tuning_cache.h"
 
 using namespace ltl;
 
@@ -193,6 +194,7 @@ struct ltl_sim {
     uint32_t *dflag = nullptr;
     uint8_t *dconst = nullptr;   // band tables for r = 1..16, then a zero page
     int periodic = 0;            // LTL_BOUNDARY_PERIODIC: the grid is a torus
+    bool user_tuned = false;     // the launch shape came from set_tuning / autotune (not the table)
     std::map<std::pair<int32_t, int>, hipGraphExec_t> graphs;
 };
 
@@ -220,6 +222,7 @@ ltl_tuning_t default_tuning(const ltl_sim &s) {
         t.waves *= 2;
     t.use_graph = 1;
     t.persistent = 0;
+    t.lds_pad = 0;
     return t;
 }
 
@@ -236,7 +239,8 @@ CatParams cat_params(const ltl_sim &s, const ltl_tuning_t &t, int T, const uint8
     p.TW = t.tile_cols;
     p.L = cat_margin(elem_of(s.method, s.rule.R, s.rule.N), p.r, T);
     p.lds_rows = p.TH + 2 * p.L;
-    cat_lds_layout(elem_of(s.method, s.rule.R, s.rule.N), s.epi, p.TH, p.TW, p.L, &p.PS, &p.PA, &p.lds_tile, &p.a_tile, &p.lds_total);
+    cat_lds_layout(elem_of(s.method, s.rule.R, s.rule.N), s.epi, p.TH, p.TW, p.L, t.lds_pad, &p.PS, &p.PA, &p.lds_tile,
+                   &p.a_tile, &p.lds_total);
     p.ntx = (s.W + p.TW - 1) / p.TW;
     p.nty = (s.H + p.TH - 1) / p.TH;
     p.bands = reinterpret_cast<const int32_t *>(s.dconst);
@@ -269,6 +273,7 @@ int32_t check_tuning(const ltl_sim &s, const ltl_tuning_t &t) {
     if (t.tile_rows < 16 || t.tile_rows > 512 || t.tile_rows % 16) return fail(LTL_ERR_ARG, "tile_rows must be a multiple of 16 in 16..512");
     if (t.tile_cols < 32 || t.tile_cols > 512 || t.tile_cols % 32) return fail(LTL_ERR_ARG, "tile_cols must be a multiple of 32 in 32..512");
     if (t.waves < 1 || t.waves > (s.method == LTL_DIRECT ? 16 : 8)) return fail(LTL_ERR_ARG, "waves must be in 1..8 (1..16 for the direct method)");
+    if (t.lds_pad < 0 || t.lds_pad > 128 || t.lds_pad % 16) return fail(LTL_ERR_ARG, "lds_pad must be a multiple of 16 in 0..128");
     if (s.method != LTL_DIRECT) {
         CatParams p = cat_params(s, t, t.steps_per_launch, nullptr, nullptr);
         size_t lds = cat_lds_bytes(p, elem_of(s.method, s.rule.R, s.rule.N), s.epi, t.persistent);
@@ -330,7 +335,11 @@ hipError_t enqueue_one(ltl_sim &s, const PlannedLaunch &pl) {
     return hipLaunchKernel(pl.k.func, pl.k.grid, pl.k.block, args, pl.k.lds, s.stream);
 }
 
+// Executable graphs are destroyed only once the stream has drained: a replay enqueued by an
+// earlier step call may still be running.
 void clear_graphs(ltl_sim &s) {
+    if (s.graphs.empty()) return;
+    (void)hipStreamSynchronize(s.stream);
     for (auto &kv : s.graphs) (void)hipGraphExecDestroy(kv.second);
     s.graphs.clear();
 }
@@ -410,6 +419,33 @@ int32_t do_steps(ltl_sim &s, int32_t n) {
     return LTL_OK;
 }
 
+// Launch shape of a new handle: LTL_TILE if set (refused if malformed or infeasible), else the
+// first tuning-table candidate (nearest radius, then size bucket) that is feasible for this
+// grid, else the built-in default.
+int32_t initial_tuning(ltl_sim &s) {
+    ltl_tuning_t t;
+    std::string err;
+    const int env = env_tile(&t, &err);
+    if (env < 0) return fail(LTL_ERR_ARG, err);
+    if (env > 0) {
+        if (s.method == LTL_DIRECT) { t.steps_per_launch = 1; t.persistent = 0; }
+        if (check_tuning(s, t) != LTL_OK) return fail(LTL_ERR_ARG, "LTL_TILE: " + g_err);
+        s.tuning = t;
+        return LTL_OK;
+    }
+    const std::string saved = g_err;
+    for (const ltl_tuning_t &c : tuning_candidates(make_key(s.H, s.W, s.rule, s.method, s.periodic, 0), nullptr)) {
+        if (check_tuning(s, c) == LTL_OK) {
+            s.tuning = c;
+            g_err = saved;
+            return LTL_OK;
+        }
+    }
+    g_err = saved;
+    s.tuning = default_tuning(s);
+    return LTL_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -422,10 +458,11 @@ int32_t ltl_pitch(int32_t W, int32_t *pitch) {
     return LTL_OK;
 }
 
-int32_t ltl_buffer_bytes(int32_t H, int32_t W, size_t *bytes) {
-    if (!bytes || H < 1 || W < 1) return fail(LTL_ERR_ARG, "H and W must be >= 1 and bytes non-NULL");
-    *bytes = (size_t)H * (size_t)pitch_of(W);
-    return LTL_OK;
+size_t ltl_buffer_bytes(int32_t H, int32_t W, int32_t R, int32_t method) {
+    if (H < 1 || W < 1) { fail(LTL_ERR_ARG, "H and W must be >= 1"); return 0; }
+    if (R < 1 || R > 32) { fail(LTL_ERR_RULE, "radius R must be in 1..32"); return 0; }
+    if (method < LTL_CAT_I8 || method > LTL_DIRECT) { fail(LTL_ERR_ARG, "unknown method"); return 0; }
+    return (size_t)H * (size_t)pitch_of(W);
 }
 
 int32_t ltl_create(ltl_sim_t **out, int32_t H, int32_t W, const ltl_rule_t *rule, int32_t method,
@@ -443,6 +480,11 @@ int32_t ltl_create(ltl_sim_t **out, int32_t H, int32_t W, const ltl_rule_t *rule
     if (rc != LTL_OK) return rc;
     size_t need = (size_t)H * (size_t)pitch_of(W);
     if (buf_bytes < need) return fail(LTL_ERR_SIZE, "buffers need " + std::to_string(need) + " bytes each");
+    {
+        ltl_tuning_t t;
+        std::string err;
+        if (env_tile(&t, &err) < 0) return fail(LTL_ERR_ARG, err);   // malformed LTL_TILE, before any device work
+    }
 
     ltl_sim *s = new (std::nothrow) ltl_sim();
     if (!s) return fail(LTL_ERR_ARG, "out of host memory");
@@ -456,7 +498,7 @@ int32_t ltl_create(ltl_sim_t **out, int32_t H, int32_t W, const ltl_rule_t *rule
     s->buf[0] = (uint8_t *)buf_a;
     s->buf[1] = (uint8_t *)buf_b;
     s->stream = stream;
-    s->tuning = default_tuning(*s);
+    s->tuning = default_tuning(*s);   // replaced below, once the device constants exist
 
     auto bail = [&](int32_t code) {
         if (s->dflag) (void)hipFree(s->dflag);
@@ -484,6 +526,7 @@ int32_t ltl_create(ltl_sim_t **out, int32_t H, int32_t W, const ltl_rule_t *rule
         if ((e = hipMemsetAsync(s->buf[b], 0, need, stream)) != hipSuccess) return bail(hip_fail(e, "hipMemsetAsync"));
     if ((e = hipMemcpy2DAsync(s->buf[0], s->pitch, init, init_pitch, W, H, hipMemcpyDeviceToDevice, stream)) != hipSuccess)
         return bail(hip_fail(e, "hipMemcpy2DAsync"));
+    if ((rc = initial_tuning(*s)) != LTL_OK) return bail(rc);
     *out = s;
     return LTL_OK;
 }
@@ -534,14 +577,16 @@ int32_t ltl_set_tuning(ltl_sim_t *sim, const ltl_tuning_t *tuning) {
     }
     t.use_graph = t.use_graph ? 1 : 0;
     t.persistent = t.persistent ? 1 : 0;
+    if (sim->method == LTL_DIRECT) t.lds_pad = 0;
     int32_t rc = check_tuning(*sim, t);
     if (rc != LTL_OK) return rc;
     clear_graphs(*sim);
     sim->tuning = t;
+    sim->user_tuned = true;
     return LTL_OK;
 }
 
-int32_t ltl_autotune(ltl_sim_t *sim, int32_t probe_steps, ltl_tuning_t *best) {
+int32_t ltl_autotune(ltl_sim_t *sim, int32_t probe_steps, void *scratch, size_t scratch_bytes, ltl_tuning_t *best) {
     if (!sim) return fail(LTL_ERR_ARG, "sim is NULL");
     if (probe_steps < 1 || probe_steps > 4096) return fail(LTL_ERR_ARG, "probe_steps must be in 1..4096");
     ltl_sim &s = *sim;
@@ -549,75 +594,98 @@ int32_t ltl_autotune(ltl_sim_t *sim, int32_t probe_steps, ltl_tuning_t *best) {
         if (best) *best = s.tuning;
         return LTL_OK;
     }
-    size_t bytes = (size_t)s.H * s.pitch;
-    uint8_t *scratch[2] = {nullptr, nullptr};
-    for (int b = 0; b < 2; ++b) {
-        hipError_t e = hipMalloc(&scratch[b], bytes);
-        if (e != hipSuccess) {
-            if (scratch[0]) (void)hipFree(scratch[0]);
-            return hip_fail(e, "hipMalloc (autotune scratch)");
-        }
-    }
+    const size_t bytes = (size_t)s.H * s.pitch;
+    if (!scratch) return fail(LTL_ERR_ARG, "scratch is NULL");
+    if (scratch_bytes < bytes) return fail(LTL_ERR_SIZE, "scratch needs " + std::to_string(bytes) + " bytes");
+    if (scratch == s.buf[0] || scratch == s.buf[1]) return fail(LTL_ERR_ARG, "scratch must not be one of the grid buffers");
+    // The probes run on the handle's own buffers (a probe handle sharing them, with its own graph
+    // cache); the current state is saved in the caller's scratch, every candidate starts from it
+    // and it is restored at the end.
+    HIP_TRY(hipMemcpyAsync(scratch, s.buf[s.cur], bytes, hipMemcpyDeviceToDevice, s.stream), "hipMemcpyAsync");
     ltl_sim probe;
     probe.H = s.H; probe.W = s.W; probe.pitch = s.pitch; probe.rule = s.rule; probe.method = s.method;
-    probe.epi = s.epi; probe.rc = s.rc; probe.buf[0] = scratch[0]; probe.buf[1] = scratch[1];
+    probe.epi = s.epi; probe.rc = s.rc; probe.buf[0] = s.buf[0]; probe.buf[1] = s.buf[1];
     probe.periodic = s.periodic;
     probe.dconst = s.dconst;
     probe.stream = s.stream;
     hipEvent_t ev0, ev1;
-    (void)hipEventCreate(&ev0);
-    (void)hipEventCreate(&ev1);
+    HIP_TRY(hipEventCreate(&ev0), "hipEventCreate");
+    if (hipEventCreate(&ev1) != hipSuccess) { (void)hipEventDestroy(ev0); return fail(LTL_ERR_HIP, "hipEventCreate"); }
+    float best_ms = 1e30f;
+    ltl_tuning_t best_t = s.tuning;
+    int32_t rc = LTL_OK;
+    // time one candidate: ms per step, or a negative value if it is infeasible
+    auto time_one = [&](const ltl_tuning_t &t, float *ms_out) -> int32_t {
+        *ms_out = -1.f;
+        std::string saved = g_err;
+        if (check_tuning(s, t) != LTL_OK) { g_err = saved; return LTL_OK; }
+        // each candidate runs a whole number of its own launches (no shorter remainder launch
+        // to bias it) covering at least probe_steps steps; candidates compare per step
+        const int T = t.steps_per_launch;
+        const int n = T * ((probe_steps + T - 1) / T);
+        clear_graphs(probe);
+        probe.tuning = t;
+        HIP_TRY(hipMemcpyAsync(s.buf[s.cur], scratch, bytes, hipMemcpyDeviceToDevice, s.stream), "hipMemcpyAsync");
+        probe.cur = s.cur;
+        int32_t r2 = do_steps(probe, n);   // warm-up + graph build
+        if (r2 != LTL_OK) return r2;
+        float ms = 1e30f;
+        for (int rep = 0; rep < 2; ++rep) {   // the faster of two timed runs
+            HIP_TRY(hipEventRecord(ev0, s.stream), "hipEventRecord");
+            if ((r2 = do_steps(probe, n)) != LTL_OK) return r2;
+            HIP_TRY(hipEventRecord(ev1, s.stream), "hipEventRecord");
+            HIP_TRY(hipEventSynchronize(ev1), "autotune sync");
+            float m = 0;
+            HIP_TRY(hipEventElapsedTime(&m, ev0, ev1), "hipEventElapsedTime");
+            ms = std::min(ms, m);
+        }
+        *ms_out = ms / (float)n;
+        return LTL_OK;
+    };
     const int Ts[] = {1, 2, 3, 4, 5, 6, 8};
     const int tiles[][2] = {{64, 64}, {96, 96}, {128, 128}, {128, 192}, {160, 160}, {192, 128}, {192, 192},
                             {192, 224}, {128, 224}, {160, 224}, {176, 224}, {224, 224}, {64, 128}, {128, 96}};
     const int wavess[] = {0, 8};  // 0: fewest waves that fit every step
-    float best_ms = 1e30f;
-    ltl_tuning_t best_t = s.tuning;
-    int32_t rc = LTL_OK;
-    for (int T : Ts) {
-        // each candidate runs a whole number of its own launches (no shorter remainder launch
-        // to bias it) covering at least probe_steps steps; candidates compare per step
-        const int n = T * ((probe_steps + T - 1) / T);
-        for (auto &tl : tiles) {
-            for (int wv : wavess) {
-              for (int pers = 0; pers < 2; ++pers) {
-                ltl_tuning_t t;
-                t.steps_per_launch = T; t.tile_rows = tl[0]; t.tile_cols = tl[1]; t.waves = wv; t.use_graph = 1;
-                t.persistent = pers;
-                if (wv == 0) {
-                    t.waves = 1;
-                    while (t.waves < 8 && s_fits(s, t)) t.waves *= 2;
+    for (int T : Ts)
+        for (auto &tl : tiles)
+            for (int wv : wavess)
+                for (int pers = 0; pers < 2; ++pers) {
+                    ltl_tuning_t t;
+                    t.steps_per_launch = T; t.tile_rows = tl[0]; t.tile_cols = tl[1]; t.waves = wv; t.use_graph = 1;
+                    t.persistent = pers;
+                    t.lds_pad = 0;
+                    if (wv == 0) {
+                        t.waves = 1;
+                        while (t.waves < 8 && s_fits(s, t)) t.waves *= 2;
+                    }
+                    float ms;
+                    if ((rc = time_one(t, &ms)) != LTL_OK) goto done;
+                    if (ms >= 0 && ms < best_ms) { best_ms = ms; best_t = t; }
                 }
-                std::string saved = g_err;
-                if (check_tuning(s, t) != LTL_OK) { g_err = saved; continue; }
-                clear_graphs(probe);
-                probe.tuning = t;
-                (void)hipMemcpyAsync(scratch[0], s.buf[s.cur], bytes, hipMemcpyDeviceToDevice, s.stream);
-                probe.cur = 0;
-                if ((rc = do_steps(probe, n)) != LTL_OK) goto done;   // warm-up + graph build
-                (void)hipEventRecord(ev0, s.stream);
-                if ((rc = do_steps(probe, n)) != LTL_OK) goto done;
-                (void)hipEventRecord(ev1, s.stream);
-                if (hipEventSynchronize(ev1) != hipSuccess) { rc = fail(LTL_ERR_HIP, "autotune sync"); goto done; }
-                float ms = 0;
-                (void)hipEventElapsedTime(&ms, ev0, ev1);
-                ms /= (float)n;
-                if (ms < best_ms) { best_ms = ms; best_t = t; }
-              }
-            }
-        }
+    // second stage: LDS row padding of the best shape
+    for (int pad : {16, 32, 48, 64, 96}) {
+        ltl_tuning_t t = best_t;
+        t.lds_pad = pad;
+        float ms;
+        if ((rc = time_one(t, &ms)) != LTL_OK) goto done;
+        if (ms >= 0 && ms < best_ms) { best_ms = ms; best_t = t; }
     }
 done:
     clear_graphs(probe);
-    (void)hipStreamSynchronize(s.stream);
+    // restore the state the probes started from (also after a failed probe)
+    hipError_t re = hipMemcpyAsync(s.buf[s.cur], scratch, bytes, hipMemcpyDeviceToDevice, s.stream);
+    if (re == hipSuccess) re = hipStreamSynchronize(s.stream);
     (void)hipEventDestroy(ev0);
     (void)hipEventDestroy(ev1);
-    (void)hipFree(scratch[0]);
-    (void)hipFree(scratch[1]);
     if (rc != LTL_OK) return rc;
+    if (re != hipSuccess) return hip_fail(re, "autotune restore");
     clear_graphs(s);
     s.tuning = best_t;
+    s.user_tuned = true;
     if (best) *best = best_t;
+    std::string err;
+    if (best_ms < 1e29f && !user_cache_path().empty())
+        (void)store_tuning(make_key(s.H, s.W, s.rule, s.method, s.periodic, 0), best_t, best_ms, &err);
     return LTL_OK;
 }
 
@@ -628,6 +696,8 @@ int32_t ltl_set_boundary(ltl_sim_t *sim, int32_t boundary) {
         return fail(LTL_ERR_UNSUPPORTED, "a periodic grid needs W divisible by 16");
     clear_graphs(*sim);
     sim->periodic = (boundary == LTL_BOUNDARY_PERIODIC) ? 1 : 0;
+    // a shape taken from the tuning table follows the boundary's own entry
+    if (!sim->user_tuned) return initial_tuning(*sim);
     return LTL_OK;
 }
 

@@ -93,81 +93,77 @@ struct CatParams {
 #define LTL_BAND_OPS 8
 #define LTL_BAND_TABLE_INTS (LTL_BAND_OPS * 64 * 4)   // per (element type, radius)
 
-inline bool band_hit(int dist, int r) { return dist >= -r && dist <= r; }
+__host__ __device__ inline bool band_hit(int dist, int r) { return dist >= -r && dist <= r; }
 
-inline void band_table(int elem, int r, int32_t *out) {
-    for (int i = 0; i < LTL_BAND_TABLE_INTS; ++i) out[i] = 0;
-    for (int lane = 0; lane < 64; ++lane) {
-        const int n = lane & 15, g = lane >> 4;
-        auto put_byte = [&](int op, int d, int e, bool on) {
-            if (on) out[(op * 64 + lane) * 4 + d] |= 1 << (8 * e);
-        };
-        auto put_half = [&](int op, int j, bool on) {
-            if (on) out[(op * 64 + lane) * 4 + j / 2] |= 0x3C00 << (16 * (j & 1));
-        };
+// Dword d (0..3) of lane `lane` of band operand `op` for an element type and radius, in the
+// layout described above (host tables and the device-side fill of the allocation-free entry
+// point both evaluate it). Bytes hold 0/1 (int8, fp8), halves 0 / 0x3C00 (fp16).
+__host__ __device__ inline uint32_t band_dword(int elem, int r, int op, int lane, int d) {
+    const int n = lane & 15, g = lane >> 4;
+    uint32_t v = 0;
+    if (elem == ELEM_F16) {
+        for (int q = 0; q < 2; ++q) {   // halves j = 2d, 2d + 1 of the lane's 8 K slots
+            const int j = 2 * d + q;
+            bool on = false;
+            if (op < 4) on = band_hit(32 * (op & 1) + 8 * g + j - 16 - 16 * (op >> 1) - n, r);
+            else if (op < 6) on = band_hit(16 * ((op == 4 ? -1 : 1) + j / 4) + 4 * g + (j % 4) - n, r);
+            v |= on ? (0x3C00u << (16 * q)) : 0u;
+        }
+        return v;
+    }
+    for (int e = 0; e < 4; ++e) {
+        const int k = 16 * g + 4 * d + e;   // K slot of a 16-byte int8 operand
+        const int j = 4 * d + e;            // K slot of an 8-byte operand (d < 2)
+        bool on = false;
         if (elem == ELEM_I8X) {
-            for (int d = 0; d < 4; ++d)
-                for (int e = 0; e < 4; ++e) {
-                    const int k = 16 * g + 4 * d + e;
-                    put_byte(0, d, e, band_hit(k - 16 - n, r));
-                    put_byte(1, d, e, band_hit(k - 32 - n, r));
-                    put_byte(2, d, e, k - 16 == n);
-                    put_byte(3, d, e, k - 32 == n);
-                    const int row1 = 16 * (d - 1) + 4 * g + e - n, row2 = 16 * (d - 2) + 4 * g + e - n;
-                    put_byte(4, d, e, row1 != 0 && band_hit(row1, r));
-                    put_byte(5, d, e, row2 != 0 && band_hit(row2, r));
-                    put_byte(6, d, e, row1 == 0);
-                    put_byte(7, d, e, row2 == 0);
-                }
-        } else if (elem == ELEM_I8W) {
-            for (int h = 0; h < 2; ++h) {
-                for (int d = 0; d < 4; ++d)
-                    for (int e = 0; e < 4; ++e)
-                        put_byte(2 * h, d, e, band_hit(16 * g + 4 * d + e - 32 - 16 * h - n, r));
-                for (int j = 0; j < 8; ++j)
-                    put_byte(2 * h + 1, j / 4, j % 4, band_hit(32 + 8 * g + j - 16 * h - n, r));
+            const int row1 = 16 * (d - 1) + 4 * g + e - n, row2 = 16 * (d - 2) + 4 * g + e - n;
+            switch (op) {
+                case 0: on = band_hit(k - 16 - n, r); break;
+                case 1: on = band_hit(k - 32 - n, r); break;
+                case 2: on = (k - 16 == n); break;
+                case 3: on = (k - 32 == n); break;
+                case 4: on = row1 != 0 && band_hit(row1, r); break;
+                case 5: on = row2 != 0 && band_hit(row2, r); break;
+                case 6: on = (row1 == 0); break;
+                default: on = (row2 == 0); break;
             }
-            for (int d = 0; d < 4; ++d)
-                for (int e = 0; e < 4; ++e) {
-                    put_byte(4, d, e, band_hit(16 * (d - 2) + 4 * g + e - n, r));
-                    put_byte(6, d, e, band_hit(16 * (d - 3) + 4 * g + e - n, r));
-                }
-            for (int j = 0; j < 8; ++j) {
-                put_byte(5, j / 4, j % 4, band_hit(16 * (2 + j / 4) + 4 * g + (j % 4) - n, r));
-                put_byte(7, j / 4, j % 4, band_hit(16 * (1 + j / 4) + 4 * g + (j % 4) - n, r));
+        } else if (elem == ELEM_I8W) {
+            switch (op) {
+                case 0: case 2: on = band_hit(k - 32 - 16 * (op >> 1) - n, r); break;
+                case 1: case 3: on = d < 2 && band_hit(32 + 8 * g + j - 16 * (op >> 1) - n, r); break;
+                case 4: on = band_hit(16 * (d - 2) + 4 * g + e - n, r); break;
+                case 6: on = band_hit(16 * (d - 3) + 4 * g + e - n, r); break;
+                case 5: on = d < 2 && band_hit(16 * (2 + d) + 4 * g + e - n, r); break;
+                default: on = d < 2 && band_hit(16 * (1 + d) + 4 * g + e - n, r); break;
             }
         } else if (elem == ELEM_I8) {
-            for (int d = 0; d < 4; ++d)
-                for (int e = 0; e < 4; ++e) {
-                    const int k = 16 * g + 4 * d + e;
-                    put_byte(0, d, e, band_hit(k - 16 - n, r));
-                    put_byte(1, d, e, band_hit(k - 32 - n, r));
-                    // window slot d of a window starting at block m-1 (op 2) or m-2 (op 3)
-                    put_byte(2, d, e, band_hit(16 * (d - 1) + 4 * g + e - n, r));
-                    put_byte(3, d, e, band_hit(16 * (d - 2) + 4 * g + e - n, r));
+            switch (op) {
+                case 0: on = band_hit(k - 16 - n, r); break;
+                case 1: on = band_hit(k - 32 - n, r); break;
+                // window slot d of a window starting at block m-1 (op 2) or m-2 (op 3)
+                case 2: on = band_hit(16 * (d - 1) + 4 * g + e - n, r); break;
+                case 3: on = band_hit(16 * (d - 2) + 4 * g + e - n, r); break;
+                default: break;
+            }
+        } else {   // ELEM_F8: 8-byte operands (dwords 0, 1)
+            if (d < 2) {
+                if (op < 4) {
+                    on = band_hit(32 * (op & 1) + 8 * g + j - 16 - 16 * (op >> 1) - n, r);
+                } else {
+                    const int start = op == 4 ? -1 : op == 5 ? 1 : op == 6 ? -2 : 0;   // first block of the window
+                    on = band_hit(16 * (start + d) + 4 * g + e - n, r);
                 }
-        } else {
-            for (int h = 0; h < 2; ++h)
-                for (int c = 0; c < 2; ++c)
-                    for (int j = 0; j < 8; ++j) {
-                        const bool on = band_hit(32 * c + 8 * g + j - 16 - 16 * h - n, r);
-                        if (elem == ELEM_F8) put_byte(2 * h + c, j / 4, j % 4, on);
-                        else put_half(2 * h + c, j, on);
-                    }
-            if (elem == ELEM_F8) {
-                const int start[4] = {-1, 1, -2, 0};   // first block of each 2-block window
-                for (int w = 0; w < 4; ++w)
-                    for (int d = 0; d < 2; ++d)
-                        for (int e = 0; e < 4; ++e)
-                            put_byte(4 + w, d, e, band_hit(16 * (start[w] + d) + 4 * g + e - n, r));
-            } else {
-                const int start[2] = {-1, 1};
-                for (int w = 0; w < 2; ++w)
-                    for (int j = 0; j < 8; ++j)
-                        put_half(4 + w, j, band_hit(16 * (start[w] + j / 4) + 4 * g + (j % 4) - n, r));
             }
         }
+        v |= on ? (1u << (8 * e)) : 0u;
     }
+    return v;
+}
+
+inline void band_table(int elem, int r, int32_t *out) {
+    for (int op = 0; op < LTL_BAND_OPS; ++op)
+        for (int lane = 0; lane < 64; ++lane)
+            for (int d = 0; d < 4; ++d) out[(op * 64 + lane) * 4 + d] = (int32_t)band_dword(elem, r, op, lane, d);
 }
 
 struct DirectParams {
@@ -222,16 +218,17 @@ inline bool cat_shape_fits(int elem, int r, int T, int TH, int TW, int waves) {
 // multiple of 32) plus 16 more bytes per row, so its pitch is = 16 (mod 32) and the 16 rows of
 // a 16-byte-per-lane operand read fall into distinct bank groups; rows are dense so 1 KiB of
 // consecutive LDS maps to consecutive window bytes (one direct global->LDS load per wave).
-// The alive tile is the state tile itself, except for decay rules on fp8 and on the wide and
-// cross int8 elements, which keep a second tile in the element encoding.
-inline void cat_lds_layout(int elem, int epi, int TH, int TW, int L, int *PS, int *PA, int *lds_tile, int *a_tile,
-                           int *lds_total) {
+// `pad` (a tuning knob, multiple of 16 bytes) widens every row further, which moves the bank
+// each row starts in. The alive tile is the state tile itself, except for decay rules on fp8
+// and on the wide and cross int8 elements, which keep a second tile in the element encoding.
+inline void cat_lds_layout(int elem, int epi, int TH, int TW, int L, int pad, int *PS, int *PA, int *lds_tile,
+                           int *a_tile, int *lds_total) {
     const int rows = TH + 2 * L;
-    *PS = TW + 2 * L + 16;
+    *PS = TW + 2 * L + 16 + pad;
     *lds_tile = roundup(rows * *PS, 1024);
     // int8 Moore and fp16 derive the alive bits from the states as they read them (no second tile)
     const bool separate = epi == EPI_DECAY && elem != ELEM_I8 && elem != ELEM_F16;
-    *PA = cat_cell_bytes(elem) * (TW + 2 * L) + 16;
+    *PA = cat_cell_bytes(elem) * (TW + 2 * L) + 16 + pad;
     *a_tile = separate ? *lds_tile : 0;
     *lds_total = *lds_tile + (separate ? roundup(rows * *PA, 1024) : 0);
 }

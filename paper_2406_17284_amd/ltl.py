@@ -37,7 +37,7 @@ EXPORTS = [
     "ltl_get_tuning", "ltl_set_tuning", "ltl_autotune", "ltl_set_boundary", "ltl_destroy", "ltl_last_error",
     "ltl_batch_buffer_bytes", "ltl_batch_create", "ltl_batch_step", "ltl_batch_read",
     "ltl_batch_current", "ltl_batch_get_tuning", "ltl_batch_set_tuning", "ltl_batch_autotune",
-    "ltl_batch_destroy",
+    "ltl_batch_destroy", "ltl_tuning_lookup", "ltl_tuning_store",
 ]
 
 
@@ -47,7 +47,7 @@ class ltl_rule_t(ctypes.Structure):
 
 class ltl_tuning_t(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int32) for n in ("steps_per_launch", "tile_rows", "tile_cols", "waves", "use_graph",
-                                                   "persistent")]
+                                                   "persistent", "lds_pad")]
 
     def as_dict(self):
         return {n: int(getattr(self, n)) for n, _ in self._fields_}
@@ -73,7 +73,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     P, I32, SZ = ctypes.c_void_p, ctypes.c_int32, ctypes.c_size_t
     PSZ = ctypes.POINTER(ctypes.c_size_t)
     sig = {
-        "ltl_buffer_bytes": ([I32, I32, PSZ], I32),
+        "ltl_buffer_bytes": ([I32, I32, I32, I32], SZ),
         "ltl_pitch": ([I32, ctypes.POINTER(ctypes.c_int32)], I32),
         "ltl_create": ([ctypes.POINTER(P), I32, I32, ctypes.POINTER(ltl_rule_t), I32, P, P, SZ, P, SZ, P], I32),
         "ltl_step": ([P, I32], I32),
@@ -81,19 +81,23 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "ltl_current": ([P, ctypes.POINTER(P), PSZ, ctypes.POINTER(ctypes.c_int64)], I32),
         "ltl_get_tuning": ([P, ctypes.POINTER(ltl_tuning_t)], I32),
         "ltl_set_tuning": ([P, ctypes.POINTER(ltl_tuning_t)], I32),
-        "ltl_autotune": ([P, I32, ctypes.POINTER(ltl_tuning_t)], I32),
+        "ltl_autotune": ([P, I32, P, SZ, ctypes.POINTER(ltl_tuning_t)], I32),
         "ltl_set_boundary": ([P, I32], I32),
         "ltl_destroy": ([P], I32),
         "ltl_last_error": ([], ctypes.c_char_p),
-        "ltl_batch_buffer_bytes": ([I32, P, P, PSZ], I32),
+        "ltl_batch_buffer_bytes": ([I32, P, P], SZ),
         "ltl_batch_create": ([ctypes.POINTER(P), I32, P, P, P, I32, P, P, SZ, P, P, P], I32),
         "ltl_batch_step": ([P, I32], I32),
         "ltl_batch_read": ([P, I32, P, SZ], I32),
         "ltl_batch_current": ([P, I32, ctypes.POINTER(P), PSZ, ctypes.POINTER(ctypes.c_int64)], I32),
         "ltl_batch_get_tuning": ([P, ctypes.POINTER(ltl_tuning_t)], I32),
         "ltl_batch_set_tuning": ([P, ctypes.POINTER(ltl_tuning_t)], I32),
-        "ltl_batch_autotune": ([P, I32, ctypes.POINTER(ltl_tuning_t)], I32),
+        "ltl_batch_autotune": ([P, I32, P, SZ, ctypes.POINTER(ltl_tuning_t)], I32),
         "ltl_batch_destroy": ([P], I32),
+        "ltl_tuning_lookup": ([I32, I32, ctypes.POINTER(ltl_rule_t), I32, I32, I32, ctypes.POINTER(ltl_tuning_t),
+                               ctypes.POINTER(ctypes.c_int32)], I32),
+        "ltl_tuning_store": ([I32, I32, ctypes.POINTER(ltl_rule_t), I32, I32, I32, ctypes.POINTER(ltl_tuning_t),
+                              ctypes.c_double], I32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -111,6 +115,13 @@ def _check(rc: int) -> int:
     if rc != LTL_OK:
         raise LtlError(rc, last_error())
     return rc
+
+
+def _check_size(n: int) -> int:
+    """Size-returning calls give 0 on an invalid argument (message in ltl_last_error)."""
+    if n == 0:
+        raise LtlError(LTL_ERR_ARG, last_error())
+    return n
 
 
 def make_rule(rule) -> ltl_rule_t:
@@ -135,10 +146,8 @@ def _stream_handle(stream) -> int:
 
 
 # ----------------------------------------------------------------- C-named calls
-def ltl_buffer_bytes(H: int, W: int) -> int:
-    out = ctypes.c_size_t(0)
-    _check(load().ltl_buffer_bytes(H, W, ctypes.byref(out)))
-    return out.value
+def ltl_buffer_bytes(H: int, W: int, R: int, method: int) -> int:
+    return _check_size(load().ltl_buffer_bytes(int(H), int(W), int(R), int(method)))
 
 
 def ltl_pitch(W: int) -> int:
@@ -180,14 +189,15 @@ def ltl_get_tuning(sim: int) -> ltl_tuning_t:
 
 
 def ltl_set_tuning(sim: int, steps_per_launch=0, tile_rows=0, tile_cols=0, waves=0, use_graph=1,
-                   persistent=0) -> None:
-    t = ltl_tuning_t(steps_per_launch, tile_rows, tile_cols, waves, use_graph, persistent)
+                   persistent=0, lds_pad=0) -> None:
+    t = ltl_tuning_t(steps_per_launch, tile_rows, tile_cols, waves, use_graph, persistent, lds_pad)
     _check(load().ltl_set_tuning(ctypes.c_void_p(sim), ctypes.byref(t)))
 
 
-def ltl_autotune(sim: int, probe_steps: int) -> ltl_tuning_t:
+def ltl_autotune(sim: int, probe_steps: int, scratch: int, scratch_bytes: int) -> ltl_tuning_t:
     t = ltl_tuning_t()
-    _check(load().ltl_autotune(ctypes.c_void_p(sim), int(probe_steps), ctypes.byref(t)))
+    _check(load().ltl_autotune(ctypes.c_void_p(sim), int(probe_steps), ctypes.c_void_p(scratch), int(scratch_bytes),
+                               ctypes.byref(t)))
     return t
 
 
@@ -203,9 +213,7 @@ def ltl_batch_buffer_bytes(H: Sequence[int], W: Sequence[int]) -> int:
     n = len(H)
     ha = (ctypes.c_int32 * n)(*H)
     wa = (ctypes.c_int32 * n)(*W)
-    out = ctypes.c_size_t(0)
-    _check(load().ltl_batch_buffer_bytes(n, ha, wa, ctypes.byref(out)))
-    return out.value
+    return _check_size(load().ltl_batch_buffer_bytes(n, ha, wa))
 
 
 def ltl_batch_create(H: Sequence[int], W: Sequence[int], rules, method: int, arena_a: int, arena_b: int,
@@ -247,19 +255,41 @@ def ltl_batch_get_tuning(batch: int) -> ltl_tuning_t:
 
 
 def ltl_batch_set_tuning(batch: int, steps_per_launch=0, tile_rows=0, tile_cols=0, waves=0, use_graph=1,
-                   persistent=0) -> None:
-    t = ltl_tuning_t(steps_per_launch, tile_rows, tile_cols, waves, use_graph, persistent)
+                         persistent=0, lds_pad=0) -> None:
+    t = ltl_tuning_t(steps_per_launch, tile_rows, tile_cols, waves, use_graph, persistent, lds_pad)
     _check(load().ltl_batch_set_tuning(ctypes.c_void_p(batch), ctypes.byref(t)))
 
 
-def ltl_batch_autotune(batch: int, probe_steps: int) -> ltl_tuning_t:
+def ltl_batch_autotune(batch: int, probe_steps: int, scratch: int, scratch_bytes: int) -> ltl_tuning_t:
     t = ltl_tuning_t()
-    _check(load().ltl_batch_autotune(ctypes.c_void_p(batch), int(probe_steps), ctypes.byref(t)))
+    _check(load().ltl_batch_autotune(ctypes.c_void_p(batch), int(probe_steps), ctypes.c_void_p(scratch),
+                                     int(scratch_bytes), ctypes.byref(t)))
     return t
 
 
 def ltl_batch_destroy(batch: int) -> None:
     _check(load().ltl_batch_destroy(ctypes.c_void_p(batch)))
+
+
+def ltl_tuning_lookup(H: int, W: int, rule, method: int, boundary: int = LTL_BOUNDARY_DEAD, batched: int = 0):
+    """(tuning, exact) from the tuning table, or None when no entry of the class exists."""
+    t = ltl_tuning_t()
+    exact = ctypes.c_int32(0)
+    r = make_rule(rule)
+    rc = load().ltl_tuning_lookup(int(H), int(W), ctypes.byref(r), int(method), int(boundary), int(batched),
+                                  ctypes.byref(t), ctypes.byref(exact))
+    if rc == LTL_ERR_ARG and "no tuning table entry" in last_error():
+        return None
+    _check(rc)
+    return t, bool(exact.value)
+
+
+def ltl_tuning_store(H: int, W: int, rule, method: int, boundary: int, batched: int, tuning: dict,
+                     ms_per_step: float) -> None:
+    t = ltl_tuning_t(*[int(tuning.get(n, 0)) for n, _ in ltl_tuning_t._fields_])
+    r = make_rule(rule)
+    _check(load().ltl_tuning_store(int(H), int(W), ctypes.byref(r), int(method), int(boundary), int(batched),
+                                   ctypes.byref(t), float(ms_per_step)))
 
 
 # ------------------------------------------------------------ torch-owned memory
@@ -286,6 +316,16 @@ def _join_current(stream, device, tensors) -> None:
             t.record_stream(stream)
 
 
+def _current_after(stream, device) -> None:
+    """Order torch's current stream after the work queued on `stream` (a read's copy), so torch
+    ops on the result see it complete."""
+    import torch
+
+    cur = torch.cuda.current_stream(device)
+    if stream.cuda_stream != cur.cuda_stream:
+        cur.wait_stream(stream)
+
+
 def _check_out(out, H: int, W: int, device) -> None:
     import torch
 
@@ -305,7 +345,8 @@ class Simulation:
               current stream); it is ordered after the current stream where it reads tensors
               made there (``init``, a default ``out``).
     tuning    launch shape, the ltl_tuning_t fields as keywords: steps_per_launch, tile_rows,
-              tile_cols, waves, use_graph, persistent (0 = library default for the first four).
+              tile_cols, waves, use_graph, persistent, lds_pad (0 = library default for the first four;
+              without `tuning` the shape comes from the tuning table, or LTL_TILE).
     boundary  "dead" (ghost halo of dead cells) or "periodic" (torus; W must be a multiple of 16).
     The results never depend on `tuning`; unsupported or infeasible combinations raise LtlError.
     """
@@ -321,7 +362,8 @@ class Simulation:
         init = init.contiguous()
         self.H, self.W = int(init.shape[0]), int(init.shape[1])
         self.stream = _torch_stream(stream, init.device)
-        nbytes = ltl_buffer_bytes(self.H, self.W)
+        self.rule = rule
+        nbytes = ltl_buffer_bytes(self.H, self.W, make_rule(rule).R, method)
         # 256-byte aligned: torch's caching allocator hands out 512-byte aligned blocks
         self.bufs = [torch.empty(nbytes, dtype=torch.uint8, device=init.device) for _ in range(2)]
         _join_current(self.stream, init.device, [init] + self.bufs)
@@ -349,12 +391,15 @@ class Simulation:
         _check_out(out, self.H, self.W, self.device)
         _join_current(self.stream, self.device, [out])
         ltl_read(self.handle, out.data_ptr(), out.stride(0))
+        _current_after(self.stream, self.device)
         return out
 
     def current_padded(self):
-        """The library-layout buffer holding the current state (H rows x pitch)."""
+        """The library-layout buffer holding the current state (H rows x pitch); torch's current
+        stream is ordered after the work queued on the simulation's stream."""
         ptr, pitch, _ = ltl_current(self.handle)
         idx = 0 if ptr == self.bufs[0].data_ptr() else 1
+        _current_after(self.stream, self.device)
         return self.bufs[idx][: self.H * pitch].view(self.H, pitch)
 
     @property
@@ -368,7 +413,13 @@ class Simulation:
         ltl_set_tuning(self.handle, **kw)
 
     def autotune(self, probe_steps: int = 8) -> dict:
-        return ltl_autotune(self.handle, probe_steps).as_dict()
+        """Pick the fastest launch shape by timing on the device (the state does not advance).
+        The probe's save copy is a torch tensor made here."""
+        import torch
+
+        scratch = torch.empty(self.bufs[0].numel(), dtype=torch.uint8, device=self.device)
+        _join_current(self.stream, self.device, [scratch])
+        return ltl_autotune(self.handle, probe_steps, scratch.data_ptr(), scratch.numel()).as_dict()
 
     def close(self) -> None:
         if self.handle:
@@ -431,11 +482,13 @@ class Batch:
         _check_out(out, self.H[index], self.W[index], self.device)
         _join_current(self.stream, self.device, [out])
         ltl_batch_read(self.handle, index, out.data_ptr(), out.stride(0))
+        _current_after(self.stream, self.device)
         return out
 
     def current_padded(self, index: int):
         """Instance `index`'s current state in the library layout (H rows x pitch), a view."""
         ptr, pitch, _ = ltl_batch_current(self.handle, index)
+        _current_after(self.stream, self.device)
         for a in self.arenas:
             off = ptr - a.data_ptr()
             if 0 <= off < self.nbytes:
@@ -453,7 +506,12 @@ class Batch:
         ltl_batch_set_tuning(self.handle, **kw)
 
     def autotune(self, probe_steps: int = 4) -> dict:
-        return ltl_batch_autotune(self.handle, probe_steps).as_dict()
+        """Pick the fastest launch shape by timing on the device (the state does not advance)."""
+        import torch
+
+        scratch = torch.empty(self.nbytes, dtype=torch.uint8, device=self.device)
+        _join_current(self.stream, self.device, [scratch])
+        return ltl_batch_autotune(self.handle, probe_steps, scratch.data_ptr(), scratch.numel()).as_dict()
 
     def close(self) -> None:
         if self.handle:

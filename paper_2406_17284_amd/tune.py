@@ -1,0 +1,87 @@
+"""Build the tuning table shipped beside ``libltl.so`` by running the library's autotuner on
+the benchmark workloads (needs the GPU).
+
+  python -m paper_2406_17284_amd.tune --out PATH [--only name,...]
+
+Each autotune call stores its pick in the user tuning cache; this script points that cache at
+PATH, so PATH ends up holding one entry per workload class (method, element type, epilogue
+class, radius, size bucket, boundary, batched) in the table format ``ltl.h`` describes. Copy
+it to ``paper_2406_17284_amd/tuning.json`` to ship it. Workloads: Life 256^2, Bosco R5 4096^2
+(dead and periodic), the radius sweep on 16384^2 for r = 1..16 (int8, fp16; fp8 for r <= 7),
+the C = 8 R16 decay rule on 32768^2 and the 512-instance batch.
+"""
+from __future__ import annotations
+
+import argparse
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+
+def main(argv=None) -> None:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--out", required=True)
+    ap.add_argument("--only", default="", help="comma-separated subset: life, bosco, periodic, sweep, decay, batch")
+    a = ap.parse_args(argv)
+    os.environ["LTL_TUNE_CACHE"] = os.path.abspath(a.out)
+    only = set(x for x in a.only.split(",") if x)
+
+    import torch
+
+    from paper_2406_17284_amd import inputs, ltl
+
+    torch.cuda.set_device(0)
+    t_start = time.time()
+
+    def tune_one(name, g, rule, method, probe, boundary="dead"):
+        t0 = time.time()
+        sim = ltl.Simulation(g, rule, method, boundary=boundary)
+        best = sim.autotune(probe_steps=probe)
+        sim.close()
+        print(f"{name} {method} {boundary}: {best} ({time.time() - t0:.1f} s, {time.time() - t_start:.0f} s total)",
+              flush=True)
+
+    if not only or "life" in only:
+        w = inputs.WORKLOADS["life256"]
+        tune_one("life256", torch.from_numpy(inputs.bernoulli_grid(w.H, w.W, w.p, w.seed)).cuda(), w.rule, "cat_i8",
+                 w.steps)
+    if not only or "bosco" in only or "periodic" in only:
+        w = inputs.WORKLOADS["bosco4096"]
+        g = inputs.bernoulli_grid_torch(w.H, w.W, w.p, w.seed, device="cuda")
+        if not only or "bosco" in only:
+            tune_one("bosco4096", g, w.rule, "cat_i8", 20)
+        if not only or "periodic" in only:
+            tune_one("bosco4096", g, w.rule, "cat_i8", 20, boundary="periodic")
+        del g
+    if not only or "sweep" in only:
+        g = inputs.bernoulli_grid_torch(16384, 16384, 0.5, 3, device="cuda")
+        for r in range(1, 17):
+            w = inputs.sweep_workload(r)
+            for method in ("cat_i8", "cat_f16", "cat_f8"):
+                if method == "cat_f8" and r > 7:
+                    continue
+                tune_one(w.name, g, w.rule, method, 10)
+        del g
+    if not only or "decay" in only:
+        w = inputs.WORKLOADS["decay32768"]
+        g = inputs.bernoulli_grid_torch(w.H, w.W, w.p, w.seed, device="cuda")
+        tune_one("decay32768", g, w.rule, "cat_i8", 4)
+        del g
+    if not only or "batch" in only:
+        insts = inputs.batch_instances()
+        grids = [inputs.bernoulli_grid_torch(x.H, x.W, 0.5, x.seed, device="cuda") for x in insts]
+        t0 = time.time()
+        b = ltl.Batch(grids, [x.rule for x in insts], "cat_i8")
+        best = b.autotune(probe_steps=4)
+        b.close()
+        print(f"batch512 cat_i8: {best} ({time.time() - t0:.1f} s)", flush=True)
+    torch.cuda.synchronize()
+    print(f"tuning table written to {a.out} ({time.time() - t_start:.0f} s)", flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -30,11 +30,15 @@ def test_pitch_and_buffer_bytes():
     assert ltl.ltl_pitch(1) == 64
     assert ltl.ltl_pitch(64) == 64
     assert ltl.ltl_pitch(65) == 128
-    assert ltl.ltl_buffer_bytes(3, 100) == 3 * 128
-    for bad in [(0, 5), (5, 0), (-1, 3)]:
+    # the halo is not stored: the size depends on neither the radius nor the method
+    for R in (1, 16, 32):
+        for m in (ltl.LTL_CAT_I8, ltl.LTL_CAT_F16, ltl.LTL_CAT_F8, ltl.LTL_DIRECT):
+            assert ltl.ltl_buffer_bytes(3, 100, R, m) == 3 * 128
+    for bad in [(0, 5, 1, 0), (5, 0, 1, 0), (-1, 3, 1, 0), (3, 3, 0, 0), (3, 3, 33, 0), (3, 3, 1, 4), (3, 3, 1, -1)]:
         with pytest.raises(ltl.LtlError) as e:
             ltl.ltl_buffer_bytes(*bad)
         assert e.value.code == ltl.LTL_ERR_ARG
+        assert ltl.last_error()
 
 
 def _create(H=8, W=8, rule=(1, 0, 1, 3, 4, 3, 3), method=ltl.LTL_CAT_I8, a=256, b=512, nbytes=1 << 20, init=1024,
@@ -81,6 +85,17 @@ def test_null_handles():
     assert lib.ltl_set_boundary(None, ltl.LTL_BOUNDARY_PERIODIC) == ltl.LTL_ERR_ARG
     t = ltl.ltl_tuning_t()
     assert lib.ltl_get_tuning(None, ctypes.byref(t)) == ltl.LTL_ERR_ARG
+    assert lib.ltl_autotune(None, 1, None, 0, None) == ltl.LTL_ERR_ARG
+
+
+def test_malformed_tile_override_is_refused_before_device_work(monkeypatch):
+    """LTL_TILE is parsed before ltl_create touches the device: a malformed value is LTL_ERR_ARG."""
+    for bad in ("4,160", "a,b,c,d", "4,160,224,8,0,0,9", "4;160;224;8", "-1,16,32,1"):
+        monkeypatch.setenv("LTL_TILE", bad)
+        with pytest.raises(ltl.LtlError) as e:
+            _create()
+        assert e.value.code == ltl.LTL_ERR_ARG
+        assert "LTL_TILE" in ltl.last_error()
 
 
 def test_batch_buffer_bytes():
@@ -129,4 +144,4 @@ def test_batch_null_handles():
     t = ltl.ltl_tuning_t()
     assert lib.ltl_batch_get_tuning(None, ctypes.byref(t)) == ltl.LTL_ERR_ARG
     assert lib.ltl_batch_set_tuning(None, ctypes.byref(t)) == ltl.LTL_ERR_ARG
-    assert lib.ltl_batch_autotune(None, 1, None) == ltl.LTL_ERR_ARG
+    assert lib.ltl_batch_autotune(None, 1, None, 0, None) == ltl.LTL_ERR_ARG

@@ -252,14 +252,6 @@ def _instance_grid(inst):
     return inputs.bernoulli_grid(inst.H, inst.W, 0.5, inst.seed)
 
 
-def bench_batch_tuning():
-    import os
-    import sys
-    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
-    import bench
-    return bench.parse_tuning(bench.BATCH_TUNING)
-
-
 @pytest.mark.parametrize("method", ["cat_i8"])
 def test_batch_512_instances(ltl, method):
     """The batched workload at full size (512 instances, 32 steps, one hipGraph): the cheapest
@@ -270,8 +262,8 @@ def test_batch_512_instances(ltl, method):
     dev = [inputs.bernoulli_grid_torch(x.H, x.W, 0.5, x.seed, device="cuda") for x in insts]
     grids = [g.cpu().numpy() for g in dev]
     assert np.array_equal(grids[0], _instance_grid(insts[0]))   # same cells as the numpy generator
-    # the launch shape the benchmark times
-    batch = ltl.Batch(dev, [x.rule for x in insts], method, tuning=bench_batch_tuning())
+    # the launch shape the benchmark times: the library's own pick (tuning table)
+    batch = ltl.Batch(dev, [x.rule for x in insts], method)
     batch.step(steps)
     torch.cuda.synchronize()
     got = [batch.read(i).cpu().numpy() for i in range(len(insts))]

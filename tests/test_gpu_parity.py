@@ -303,18 +303,17 @@ def test_life_patterns_on_gpu(ltl):
 
 def test_bosco_4096_full(ltl):
     """The Bosco workload in full (4096^2, 100 steps) against the oracle: CAT int8 in the launch
-    shape the benchmark times, in its persistent form and at the library default, and the
-    direct stencil."""
-    import os
-    import sys
-    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
-    import bench
+    shape the benchmark times (the library's own pick), the same shape in its persistent form,
+    a fixed T = 4 160 x 224 shape, and the direct stencil."""
     w = inputs.WORKLOADS["bosco4096"]
     g0 = inputs.bernoulli_grid(w.H, w.W, w.p, w.seed)
     oracle.set_threads(0)
     ref = oracle.run(g0, w.rule, w.steps)
-    timed = bench.parse_tuning(bench.DEFAULT_TUNING)
-    for method, tuning in (("cat_i8", timed), ("cat_i8", dict(timed, persistent=1)), ("cat_i8", None),
+    probe = ltl.Simulation(gpu_grid(g0), w.rule, "cat_i8")
+    timed = probe.tuning()
+    probe.close()
+    fixed = dict(steps_per_launch=4, tile_rows=160, tile_cols=224, waves=8)
+    for method, tuning in (("cat_i8", timed), ("cat_i8", dict(timed, persistent=1)), ("cat_i8", fixed),
                            ("direct", None)):
         sim = ltl.Simulation(gpu_grid(g0), w.rule, method, tuning=tuning)
         sim.step(w.steps)
