@@ -220,11 +220,14 @@ def bench_sweep(args, ltl, inputs, torch, digests, oracle):
     cells = side * side
     per_r = {}
     t1_shape = dict(steps_per_launch=1, tile_rows=160, tile_cols=224, waves=8)
-    for r in range(1, args.sweep_rmax + 1):
+    radii = [int(x) for x in args.sweep_radii.split(",")] if args.sweep_radii else range(1, args.sweep_rmax + 1)
+    methods = args.sweep_methods.split(",") if args.sweep_methods else ("cat_i8", "cat_i8_T1", "cat_f16", "cat_f8",
+                                                                          "direct")
+    for r in radii:
         w = inputs.sweep_workload(r, side)
         ref = golden(digests, w.name, steps) if side == 16384 else None
         row = {}
-        for method in ("cat_i8", "cat_i8_T1", "cat_f16", "cat_f8", "direct"):
+        for method in methods:
             m = "cat_i8" if method == "cat_i8_T1" else method
             if (m == "cat_f8" and r > 7) or (m == "cat_f16" and r > 16):
                 continue
@@ -242,34 +245,39 @@ def bench_sweep(args, ltl, inputs, torch, digests, oracle):
             ent["bit_exact"] = None if ref is None else digest_of(final) == ref
             row[method] = ent
             del final
-        row["cat_over_direct"] = row["cat_i8"]["cell_updates_per_s"] / row["direct"]["cell_updates_per_s"]
+        if "cat_i8" in row and "direct" in row:
+            row["cat_over_direct"] = row["cat_i8"]["cell_updates_per_s"] / row["direct"]["cell_updates_per_s"]
         per_r[str(r)] = row
-        log(f"sweep r={r}: int8 {row['cat_i8']['cell_updates_per_s']:.3e}, direct "
-            f"{row['direct']['cell_updates_per_s']:.3e}, exact {row['cat_i8']['bit_exact']}")
-    i8 = [per_r[k]["cat_i8"]["cell_updates_per_s"] for k in per_r]
-    t1 = [per_r[k]["cat_i8_T1"]["cell_updates_per_s"] for k in per_r]
-    wins = [int(k) for k in per_r if per_r[k]["cat_over_direct"] > 1]
-    exact = [v.get("bit_exact") for k in per_r for v in per_r[k].values() if isinstance(v, dict)]
-    res = {"workload": f"sweep{side}: {side}x{side}, r=1..{args.sweep_rmax} sweep rules (S=[0.25,0.45]N, "
+        log(f"sweep r={r}: " + ", ".join(f"{m} {v['cell_updates_per_s']:.3e}" for m, v in row.items()
+                                          if isinstance(v, dict)))
+    res = {"workload": f"sweep{side}: {side}x{side}, radii {list(radii)} of the sweep rules (S=[0.25,0.45]N, "
                        f"B=[0.27,0.34]N floored), Bernoulli(0.5) seed 3, dead halo, {steps} steps per run",
-           "reps": reps, "per_r": per_r,
-           "int8_max_over_min": max(i8) / min(i8), "int8_T1_max_over_min": max(t1) / min(t1),
-           "int8_T1_shape": [t1_shape.get(k, 0) for k in SHAPE_KEYS],
-           "cat_beats_direct_from_r": min(wins) if wins else None,
-           "cat_beats_direct_at_every_r": len(wins) == len(per_r),
-           "bit_exact_all": (all(e is True for e in exact) if all(e is not None for e in exact) else None)}
+           "reps": reps, "per_r": per_r}
+    i8 = [per_r[k]["cat_i8"]["cell_updates_per_s"] for k in per_r if "cat_i8" in per_r[k]]
+    t1 = [per_r[k]["cat_i8_T1"]["cell_updates_per_s"] for k in per_r if "cat_i8_T1" in per_r[k]]
+    if i8:
+        res["int8_max_over_min"] = max(i8) / min(i8)
+    if t1:
+        res["int8_T1_max_over_min"] = max(t1) / min(t1)
+        res["int8_T1_shape"] = [t1_shape.get(k, 0) for k in SHAPE_KEYS]
+    if all("cat_over_direct" in per_r[k] for k in per_r):
+        wins = [int(k) for k in per_r if per_r[k]["cat_over_direct"] > 1]
+        res["cat_beats_direct_from_r"] = min(wins) if wins else None
+        res["cat_beats_direct_at_every_r"] = len(wins) == len(per_r)
+    exact = [v.get("bit_exact") for k in per_r for v in per_r[k].values() if isinstance(v, dict)]
+    res["bit_exact_all"] = all(e is True for e in exact) if all(e is not None for e in exact) else None
     del g
     if oracle is not None:
         # all cores: 2 steps of a 2048-row strip of the sweep grid per sampled radius; one
         # thread: 1 step of its first 128 rows (extrapolated per cell-update)
         cpu = {}
-        for r in (1, 5, 9, 16):
+        for r in [x for x in (1, 5, 9, 16) if x in list(radii)] or [list(radii)[0]]:
             rule = inputs.sweep_rule(r)
             rates, _ = oracle_rates(oracle, inputs, lambda: inputs.bernoulli_grid(2048, side, 0.5, 3), rule, 2, 1,
                                     rows_one=128)
             cpu[str(r)] = rates
         res["cpu_baseline"] = {"per_r": cpu, "kind": "oracle", "unit": "cell-updates/s",
-                               "cores": cpu["1"]["cores"], "cpu_model": cpu_model(),
+                               "cores": next(iter(cpu.values()))["cores"], "cpu_model": cpu_model(),
                                "sample": "per r in {1, 5, 9, 16}: all cores = 2 steps of a 2048 x 16384 strip; one "
                                          "thread = 1 step of a 128 x 16384 strip, extrapolated per cell-update"}
     return res
@@ -475,6 +483,9 @@ def main():
     ap.add_argument("--no-sweep", action="store_true", help="skip the radius sweep r=1..16 on 16384^2")
     ap.add_argument("--sweep-side", type=int, default=16384)
     ap.add_argument("--sweep-rmax", type=int, default=16)
+    ap.add_argument("--sweep-radii", type=str, default="", help="comma-separated radii of the sweep (default 1..rmax)")
+    ap.add_argument("--sweep-methods", type=str, default="",
+                    help="comma-separated subset of cat_i8, cat_i8_T1, cat_f16, cat_f8, direct")
     ap.add_argument("--no-life", action="store_true", help="skip the Life 256^2 workload")
     ap.add_argument("--no-batch", action="store_true", help="skip the 512-instance batched workload")
     ap.add_argument("--no-decay", action="store_true", help="skip the C=8 R16 decay workload on 32768^2")

@@ -174,6 +174,7 @@ int32_t ltl_set_boundary(ltl_sim_t *sim, int32_t boundary);
  * not synchronize; the caller synchronizes the stream first. NULL is accepted. */
 int32_t ltl_destroy(ltl_sim_t *sim);
 
+
 /* Message of the last failing call on this thread ("" if none). */
 const char *ltl_last_error(void);
 

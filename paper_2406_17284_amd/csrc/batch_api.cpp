@@ -110,7 +110,7 @@ DirectParams batch_direct_params(const ltl_batch &b, int i, int from) {
     p.r = b.rule[i].R;
     p.TH = direct_tile_rows();
     p.TW = direct_tile_cols();
-    p.LP = p.TW + 2 * p.r;
+    p.LP = direct_lds_pitch(p.r);
     p.cross = (b.rule[i].N == 'N') ? 1 : 0;
     p.rc = b.rc[i];
     return p;
@@ -299,7 +299,7 @@ int32_t batch_plan(ltl_batch &b, int T, BatchLaunchPlan **out) {
                     std::memset(&x, 0, sizeof(x));
                     x.p = batch_direct_params(b, i, par);
                     x.ntx = (b.W[i] + direct_tile_cols() - 1) / direct_tile_cols();
-                    lds = std::max(lds, (size_t)(x.p.TH + 2 * x.p.r) * x.p.LP);
+                    lds = std::max(lds, direct_lds_bytes(x.p.r));
                 }
             int32_t rc = upload(h, b.stream, &pl.dinst);
             if (rc != LTL_OK) return rc;

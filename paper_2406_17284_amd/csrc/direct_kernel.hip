@@ -1,90 +1,136 @@
-// Comparison method: LDS direct-stencil step (the classic shared-memory out-halo tile of
-// the paper's SHARED approach, "Approaches Selected for Evaluation"). The alive map of a
-// (TH + 2r) x (TW + 2r) tile is staged in LDS and every cell sums its (2r+1)^2 box
-// directly, so the work per cell grows as (2r+1)^2 (the Omega(r^2) cost the paper's
-// introduction attributes to this scheme). A thread computes 4 horizontally adjacent
-// cells and reads each LDS byte of their joint window once per row.
+// Comparison method: LDS direct-stencil step (the shared-memory out-halo tile of the paper's
+// SHARED approach, "Approaches Selected for Evaluation"). The alive map of a tile plus its
+// halo is staged in LDS and every cell sums its whole (2r+1)^2 box (or its 4r+1 cross), so the
+// work per cell grows as (2r+1)^2 -- the Omega(r^2) cost the paper's introduction attributes to
+// this scheme. No sum is shared between cells.
+//
+// MI355X form: 128 x 256 output tiles staged with 16-byte loads (HBM re-reads of the halo are
+// (128 + 2r)(256 + 2 roundup16(r)) / (128 x 256) of the tile, 1.21x at r = 5). A thread computes
+// four horizontally adjacent cells at once with byte-lane SWAR: for each row of the box it reads
+// the aligned LDS dwords around the four cells and adds, for every column offset, the dword of
+// the four cells' neighbours at that offset (one funnel shift to realign it, one packed add), so
+// each add performs the four cells' additions of that term. Counts up to 255 stay in the byte
+// lanes (r <= 7 and every cross); larger boxes fold each row's byte sums into 16-bit lanes. The
+// radius is a template parameter so the offsets unroll at compile time. Lanes of a wave take
+// consecutive dwords of one row: conflict-free LDS reads, coalesced stores.
+//
 // Also here: the state-range validation used at creation.
 #include "ltl_internal.h"
 
 namespace ltl {
 
-static constexpr int DIRECT_TH = 32;
-static constexpr int DIRECT_TW = 64;
-static constexpr int DIRECT_THREADS = 256;
-
+// Next state of one cell from its state s and its box count n (centre included), as selects.
 __device__ __forceinline__ int direct_next(int s, int n, const RuleConsts &rc) {
-    // n: box count including the centre
-    if (s == 0) return (rc.b1 <= n && n <= rc.b2) ? 1 : 0;
-    if (s == 1) {
-        int k = n - (rc.M == 0 ? 1 : 0);
-        if (rc.s1 <= k && k <= rc.s2) return 1;
-        return rc.C > 2 ? 2 : 0;
-    }
-    return (s + 1 < rc.C) ? s + 1 : 0;
+    const int k = n - ((s == 1 && rc.M == 0) ? 1 : 0);
+    const int born = (rc.b1 <= k && k <= rc.b2) ? 1 : 0;
+    const int stay = (rc.s1 <= k && k <= rc.s2) ? 1 : (rc.C > 2 ? 2 : 0);
+    const int decay = (s + 1 < rc.C) ? s + 1 : 0;
+    return s == 0 ? born : s == 1 ? stay : decay;
 }
 
-// One DIRECT_TH x DIRECT_TW output tile whose top-left cell is (gi0, gj0).
+// alive indicator (byte == 1) of a dword of states, any byte values
+__device__ __forceinline__ uint32_t direct_alive(uint32_t s) {
+    uint32_t x = s ^ 0x01010101u;                              // zero byte iff state == 1
+    uint32_t y = ((x & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | x;         // bit 7 iff byte != 0
+    return (~y & 0x80808080u) >> 7;
+}
+
+// Byte-lane sum over one LDS row of the 2R+1 column offsets of four cells. `row` points at the
+// first of the ND aligned dwords that cover columns j - R .. j + 3 + R of the cells j..j+3.
+template <int R>
+__device__ __forceinline__ uint32_t row_sum(const uint32_t *row) {
+    constexpr int R4 = (R + 3) & ~3;
+    constexpr int ND = (2 * R + R4 - R + 3) / 4 + 1;
+    uint32_t dw[ND];
+#pragma unroll
+    for (int k = 0; k < ND; ++k) dw[k] = row[k];
+    uint32_t acc = 0;
+#pragma unroll
+    for (int dj = 0; dj <= 2 * R; ++dj) {
+        constexpr int base = R4 - R;
+        const int o = dj + base;   // byte offset of the four cells' neighbours at column offset dj - R
+        acc += (o & 3) ? __builtin_amdgcn_alignbyte(dw[(o >> 2) + 1], dw[o >> 2], o & 3) : dw[o >> 2];
+    }
+    return acc;
+}
+
+// One kDirectTH x kDirectTW output tile whose top-left cell is (gi0, gj0).
+template <int R>
 __device__ __forceinline__ void direct_tile(const DirectParams &p, int gi0, int gj0, uint8_t *lds) {
-    const int r = p.r;
-    const int rows = DIRECT_TH + 2 * r;
-    const int cols = DIRECT_TW + 2 * r;
-    for (int idx = threadIdx.x; idx < rows * cols; idx += blockDim.x) {
-        int lr = idx / cols;
-        int lc = idx - lr * cols;
-        int gr = gi0 - r + lr;
-        int gc = gj0 - r + lc;
-        uint8_t v = 0;
-        if (p.periodic) {   // torus: wrap both coordinates
+    constexpr int R16 = (R + 15) & ~15;
+    constexpr int R4 = (R + 3) & ~3;
+    constexpr int LP = kDirectTW + 2 * R16;          // LDS pitch, multiple of 16
+    constexpr int ROWS = kDirectTH + 2 * R;
+    constexpr int VPR = LP / 16;                      // 16-byte vectors per LDS row
+    // stage the alive map of rows gi0 - R .. gi0 + TH + R - 1, columns gj0 - R16 .. gj0 + TW + R16 - 1
+    for (int v = threadIdx.x; v < ROWS * VPR; v += kDirectThreads) {
+        const int lr = v / VPR;
+        const int lc = (v - lr * VPR) * 16;
+        const int gr = gi0 - R + lr;
+        const int gc = gj0 - R16 + lc;
+        uint4 q = make_uint4(0u, 0u, 0u, 0u);
+        if (p.periodic) {   // torus: W % 16 == 0, so a 16-byte vector at a 16-aligned column wraps whole
             int wr = gr % p.H, wc = gc % p.W;
             wr += (wr < 0) ? p.H : 0;
             wc += (wc < 0) ? p.W : 0;
-            v = p.src[(size_t)wr * p.pitch + wc];
-        } else if ((unsigned)gr < (unsigned)p.H && (unsigned)gc < (unsigned)p.W) {
-            v = p.src[(size_t)gr * p.pitch + gc];
+            q = *reinterpret_cast<const uint4 *>(p.src + (size_t)wr * p.pitch + wc);
+        } else if ((unsigned)gr < (unsigned)p.H && (unsigned)gc < (unsigned)p.pitch) {
+            q = *reinterpret_cast<const uint4 *>(p.src + (size_t)gr * p.pitch + gc);   // padding columns are 0
         }
-        lds[lr * p.LP + lc] = (v == 1) ? 1 : 0;
+        q = make_uint4(direct_alive(q.x), direct_alive(q.y), direct_alive(q.z), direct_alive(q.w));
+        *reinterpret_cast<uint4 *>(lds + lr * LP + lc) = q;
     }
     __syncthreads();
 
-    const int tx = threadIdx.x & 15;       // 16 groups of 4 columns
-    const int ty = threadIdx.x >> 4;       // 16 rows per pass
-    const int w = 2 * r;
-    for (int ly = ty; ly < DIRECT_TH; ly += 16) {
-        const int lx = 4 * tx;
-        int acc0 = 0, acc1 = 0, acc2 = 0, acc3 = 0;
-        // Moore: every row of the box; cross: the centre row only, plus the centre column
-        for (int di = p.cross ? r : 0; di <= (p.cross ? r : w); ++di) {
-            const uint8_t *row = lds + (ly + di) * p.LP + lx;
-            for (int dj = 0; dj <= w + 3; ++dj) {
-                int b = row[dj];
-                acc0 += (dj <= w) ? b : 0;
-                acc1 += (dj >= 1 && dj <= w + 1) ? b : 0;
-                acc2 += (dj >= 2 && dj <= w + 2) ? b : 0;
-                acc3 += (dj >= 3) ? b : 0;
-            }
-        }
-        if (p.cross) {
-            for (int di = 0; di <= w; ++di) {
-                if (di == r) continue;
-                const uint8_t *col = lds + (ly + di) * p.LP + lx + r;
-                acc0 += col[0];
-                acc1 += col[1];
-                acc2 += col[2];
-                acc3 += col[3];
-            }
-        }
+    const int cg = threadIdx.x & 63;                  // four-cell column group
+    const int rg = threadIdx.x >> 6;                  // first row of this wave
+    const int gc = gj0 + 4 * cg;
+    if (gc >= p.pitch) return;
+    // aligned dword where the neighbourhood rows of this thread's cells begin
+    const int dbase = (4 * cg + R16 - R4) >> 2;
+    for (int ly = rg; ly < kDirectTH; ly += 4) {
         const int gr = gi0 + ly;
-        const int gc = gj0 + lx;
-        if (gr >= p.H || gc >= p.pitch) continue;
-        const uint8_t *srow = p.src + (size_t)gr * p.pitch + gc;
-        uint32_t s4 = *reinterpret_cast<const uint32_t *>(srow);
-        int acc[4] = {acc0, acc1, acc2, acc3};
+        if (gr >= p.H) break;
+        const uint32_t *w0 = reinterpret_cast<const uint32_t *>(lds + ly * LP) + dbase;
+        // centre states: two-state rules read them from the staged alive map (state == alive bit);
+        // decay rules load them from the grid, issued before the sums so the load overlaps them
+        uint32_t s4;
+        if (p.rc.C > 2) s4 = *reinterpret_cast<const uint32_t *>(p.src + (size_t)gr * p.pitch + gc);
+        else s4 = w0[R * (LP / 4) + (R4 >> 2)];
+        uint32_t n[4];
+        if (p.cross) {
+            // centre row (2R+1 cells) plus the centre column above and below (2R cells): <= 129
+            uint32_t acc = row_sum<R>(w0 + R * (LP / 4));
+            constexpr int own = R4 >> 2;               // dword of the four cells' own column
+#pragma unroll 4
+            for (int dy = 0; dy <= 2 * R; ++dy)
+                if (dy != R) acc += w0[dy * (LP / 4) + own];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) n[k] = (acc >> (8 * k)) & 0xFFu;
+        } else if constexpr ((2 * R + 1) * (2 * R + 1) <= 255) {
+            uint32_t acc = 0;
+#pragma unroll 1
+            for (int dy = 0; dy <= 2 * R; ++dy) acc += row_sum<R>(w0 + dy * (LP / 4));
+#pragma unroll
+            for (int k = 0; k < 4; ++k) n[k] = (acc >> (8 * k)) & 0xFFu;
+        } else {
+            // row sums (<= 2R+1 per byte) folded into 16-bit lanes: cells 0, 2 and cells 1, 3
+            uint32_t lo = 0, hi = 0;
+#pragma unroll 1
+            for (int dy = 0; dy <= 2 * R; ++dy) {
+                const uint32_t rs = row_sum<R>(w0 + dy * (LP / 4));
+                lo += rs & 0x00FF00FFu;
+                hi += (rs >> 8) & 0x00FF00FFu;
+            }
+            n[0] = lo & 0xFFFFu;
+            n[1] = hi & 0xFFFFu;
+            n[2] = lo >> 16;
+            n[3] = hi >> 16;
+        }
         uint32_t out = 0;
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            int s = (int)((s4 >> (8 * k)) & 0xFFu);
-            int nx = direct_next(s, acc[k], p.rc);
+            int nx = direct_next((int)((s4 >> (8 * k)) & 0xFFu), (int)n[k], p.rc);
             if (gc + k >= p.W) nx = 0;
             out |= (uint32_t)nx << (8 * k);
         }
@@ -92,38 +138,59 @@ __device__ __forceinline__ void direct_tile(const DirectParams &p, int gi0, int 
     }
 }
 
-__global__ void __launch_bounds__(DIRECT_THREADS) direct_step(DirectParams p) {
-    extern __shared__ uint8_t lds[];
-    direct_tile(p, blockIdx.y * DIRECT_TH, blockIdx.x * DIRECT_TW, lds);
+template <int R>
+__global__ void __launch_bounds__(kDirectThreads) direct_step(DirectParams p) {
+    extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
+    direct_tile<R>(p, blockIdx.y * kDirectTH, blockIdx.x * kDirectTW, lds);
 }
 
-// Batched form: one workgroup per work-list entry (instance, tile).
-__global__ void __launch_bounds__(DIRECT_THREADS) direct_batch(DirectBatchParams bp) {
-    extern __shared__ uint8_t lds[];
+// Radius dispatch over 1..32 (RADII(X) expands X(1) ... X(32)).
+#define DIRECT_RADII(X)                                                                                   \
+    X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16) X(17) X(18)   \
+    X(19) X(20) X(21) X(22) X(23) X(24) X(25) X(26) X(27) X(28) X(29) X(30) X(31) X(32)
+
+// Batched form: one workgroup per work-list entry (instance, tile), the radius of its instance.
+__global__ void __launch_bounds__(kDirectThreads) direct_batch(DirectBatchParams bp) {
+    extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
     const BatchItem item = bp.items[blockIdx.x];
     const DirectBatchInst *bi = bp.inst + item.inst;
     const DirectParams p = bi->p;
     const int ty = item.tile / bi->ntx;
     const int tx = item.tile - ty * bi->ntx;
-    direct_tile(p, ty * DIRECT_TH, tx * DIRECT_TW, lds);
+    switch (p.r) {
+#define DIRECT_CASE(RR) case RR: direct_tile<RR>(p, ty * kDirectTH, tx * kDirectTW, lds); break;
+        DIRECT_RADII(DIRECT_CASE)
+#undef DIRECT_CASE
+        default: break;
+    }
+}
+
+static const void *direct_func(int r) {
+    switch (r) {
+#define DIRECT_CASE(RR) case RR: return (const void *)&direct_step<RR>;
+        DIRECT_RADII(DIRECT_CASE)
+#undef DIRECT_CASE
+        default: return nullptr;
+    }
 }
 
 const void *direct_batch_func() { return (const void *)&direct_batch; }
-int direct_tile_rows() { return DIRECT_TH; }
-int direct_tile_cols() { return DIRECT_TW; }
-int direct_threads() { return DIRECT_THREADS; }
+int direct_tile_rows() { return kDirectTH; }
+int direct_tile_cols() { return kDirectTW; }
+int direct_threads() { return kDirectThreads; }
 
 KernelLaunch direct_launch_shape(const DirectParams &p) {
     KernelLaunch k;
-    k.func = (const void *)&direct_step;
-    k.grid = dim3((p.W + DIRECT_TW - 1) / DIRECT_TW, (p.H + DIRECT_TH - 1) / DIRECT_TH, 1);
-    k.block = dim3(DIRECT_THREADS, 1, 1);
-    k.lds = (size_t)(DIRECT_TH + 2 * p.r) * p.LP;
+    k.func = direct_func(p.r);
+    k.grid = dim3((p.W + kDirectTW - 1) / kDirectTW, (p.H + kDirectTH - 1) / kDirectTH, 1);
+    k.block = dim3(kDirectThreads, 1, 1);
+    k.lds = direct_lds_bytes(p.r);
     return k;
 }
 
 hipError_t launch_direct(const DirectParams &p, hipStream_t s) {
     KernelLaunch k = direct_launch_shape(p);
+    if (!k.func) return hipErrorInvalidValue;
     void *args[] = {(void *)&p};
     return hipLaunchKernel(k.func, k.grid, k.block, args, k.lds, s);
 }

@@ -259,9 +259,9 @@ DirectParams direct_params(const ltl_sim &s, const uint8_t *src, uint8_t *dst) {
     p.W = s.W;
     p.pitch = s.pitch;
     p.r = s.rule.R;
-    p.TH = 32;
-    p.TW = 64;
-    p.LP = 64 + 2 * p.r;
+    p.TH = kDirectTH;
+    p.TW = kDirectTW;
+    p.LP = direct_lds_pitch(p.r);
     p.periodic = s.periodic;
     p.cross = (s.rule.N == 'N') ? 1 : 0;
     p.rc = s.rc;

@@ -166,13 +166,22 @@ inline void band_table(int elem, int r, int32_t *out) {
             for (int d = 0; d < 4; ++d) out[(op * 64 + lane) * 4 + d] = (int32_t)band_dword(elem, r, op, lane, d);
 }
 
+// Direct-stencil comparison kernel: 128 x 256 output tiles, 256 threads (64 four-cell column
+// groups x 4 rows at a time); the LDS window holds the alive bytes of the tile plus r rows above
+// and below and roundup16(r) columns left and right (16-byte aligned vector loads).
+constexpr int kDirectTH = 128;
+constexpr int kDirectTW = 256;
+constexpr int kDirectThreads = 256;
+inline int direct_lds_pitch(int r) { return kDirectTW + 2 * ((r + 15) & ~15); }
+inline size_t direct_lds_bytes(int r) { return (size_t)(kDirectTH + 2 * r) * direct_lds_pitch(r); }
+
 struct DirectParams {
     const uint8_t *src;
     uint8_t *dst;
     int32_t H, W, pitch;
     int32_t r;
-    int32_t TH, TW;       // output tile of the direct kernel
-    int32_t LP;           // LDS row pitch
+    int32_t TH, TW;       // output tile of the direct kernel (kDirectTH x kDirectTW)
+    int32_t LP;           // LDS row pitch (direct_lds_pitch(r))
     int32_t periodic;     // 1: the grid is a torus; 0: dead ghost halo
     int32_t cross;        // 1: cross neighbourhood (N_N); 0: Moore box
     RuleConsts rc;
