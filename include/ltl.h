@@ -97,7 +97,7 @@ typedef struct ltl_batch ltl_batch_t;
  * state per byte; the ghost halo of "Formulation of CAT" is not stored (tile loads read dead
  * cells, or the opposite edge on a torus, for positions outside the grid), so the size does
  * not depend on R or the method, which are checked (R in 1..32, a known method) all the same.
- * Returns 0 on an invalid argument (message in ltl_last_error). */
+ * Returns 0 on an invalid argument (ltl_last_error and ltl_last_error_code say why). */
 size_t ltl_buffer_bytes(int32_t H, int32_t W, int32_t R, int32_t method);
 
 /* Row pitch in bytes of the library's grid layout: W rounded up to 64. LTL_ERR_ARG for W < 1. */
@@ -174,9 +174,11 @@ int32_t ltl_set_boundary(ltl_sim_t *sim, int32_t boundary);
  * not synchronize; the caller synchronizes the stream first. NULL is accepted. */
 int32_t ltl_destroy(ltl_sim_t *sim);
 
-
 /* Message of the last failing call on this thread ("" if none). */
 const char *ltl_last_error(void);
+/* LTL_ERR_* code of the last failing call on this thread (LTL_OK if none); the size-returning
+ * calls (ltl_buffer_bytes, ltl_batch_buffer_bytes) report their refusals this way. */
+int32_t ltl_last_error_code(void);
 
 /* ----------------------------------------------------------------------------------
  * Tuning table ("Optimal Tile per CUDA block": the best tile depends on the radius and the
@@ -230,7 +232,7 @@ int32_t ltl_tuning_store(int32_t H, int32_t W, const ltl_rule_t *rule, int32_t m
  * handle allocates host metadata, cached hipGraphs and device descriptors (band operands of
  * every radius, per-instance launch parameters, the work list). All work of a handle runs on
  * its one stream. */
-/* Bytes of each arena (0 on an invalid argument). */
+/* Bytes of each arena (0 on an invalid argument; ltl_last_error_code says why). */
 size_t ltl_batch_buffer_bytes(int32_t count, const int32_t *H, const int32_t *W);
 int32_t ltl_batch_create(ltl_batch_t **out, int32_t count, const int32_t *H, const int32_t *W,
                          const ltl_rule_t *rules, int32_t method, void *arena_a, void *arena_b,

@@ -476,16 +476,16 @@ int32_t batch_initial_tuning(ltl_batch &b, ltl_tuning_t *out) {
         *out = t;
         return LTL_OK;
     }
-    const std::string saved = g_err;
+    const SavedError saved = save_error();
     for (ltl_tuning_t c : tuning_candidates(batch_key(b), nullptr)) {
         c = batch_fill_tuning(b, c);
         if (batch_check_tuning(b, c) == LTL_OK) {
             *out = c;
-            g_err = saved;
+            restore_error(saved);
             return LTL_OK;
         }
     }
-    g_err = saved;
+    restore_error(saved);
     *out = batch_default_tuning(b);
     return batch_check_tuning(b, *out);
 }
@@ -518,8 +518,8 @@ int32_t batch_autotune(ltl_batch &b, int probe_steps, void *scratch, size_t scra
     auto time_one = [&](ltl_tuning_t t, float *ms_out) -> int32_t {
         *ms_out = -1.f;
         t = batch_fill_tuning(probe, t);
-        std::string saved = g_err;
-        if (batch_check_tuning(probe, t) != LTL_OK) { g_err = saved; return LTL_OK; }
+        const SavedError saved = save_error();
+        if (batch_check_tuning(probe, t) != LTL_OK) { restore_error(saved); return LTL_OK; }
         // each candidate runs a whole number of its own launches (no shorter remainder launch
         // to bias it) covering at least probe_steps steps; candidates compare per step
         const int T = t.steps_per_launch;

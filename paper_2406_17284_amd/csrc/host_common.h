@@ -11,8 +11,20 @@
 namespace ltl {
 namespace host {
 
-// Message of the last failing call on this thread (ltl_last_error).
+// Message and code of the last failing call on this thread (ltl_last_error, ltl_last_error_code).
 extern thread_local std::string g_err;
+extern thread_local int32_t g_code;
+
+// The error state around a probe whose failure is expected (an infeasible candidate shape).
+struct SavedError {
+    std::string msg;
+    int32_t code;
+};
+inline SavedError save_error() { return SavedError{g_err, g_code}; }
+inline void restore_error(const SavedError &e) {
+    g_err = e.msg;
+    g_code = e.code;
+}
 
 int32_t fail(int32_t code, const std::string &msg);
 int32_t hip_fail(hipError_t e, const char *what);

@@ -27,9 +27,11 @@ namespace ltl {
 namespace host {
 
 thread_local std::string g_err;
+thread_local int32_t g_code = LTL_OK;
 
 int32_t fail(int32_t code, const std::string &msg) {
     g_err = msg;
+    g_code = code;
     return code;
 }
 
@@ -433,15 +435,15 @@ int32_t initial_tuning(ltl_sim &s) {
         s.tuning = t;
         return LTL_OK;
     }
-    const std::string saved = g_err;
+    const SavedError saved = save_error();
     for (const ltl_tuning_t &c : tuning_candidates(make_key(s.H, s.W, s.rule, s.method, s.periodic, 0), nullptr)) {
         if (check_tuning(s, c) == LTL_OK) {
             s.tuning = c;
-            g_err = saved;
+            restore_error(saved);
             return LTL_OK;
         }
     }
-    g_err = saved;
+    restore_error(saved);
     s.tuning = default_tuning(s);
     return LTL_OK;
 }
@@ -451,6 +453,8 @@ int32_t initial_tuning(ltl_sim &s) {
 extern "C" {
 
 const char *ltl_last_error(void) { return g_err.c_str(); }
+
+int32_t ltl_last_error_code(void) { return g_code; }
 
 int32_t ltl_pitch(int32_t W, int32_t *pitch) {
     if (!pitch || W < 1) return fail(LTL_ERR_ARG, "W must be >= 1 and pitch non-NULL");
@@ -617,8 +621,8 @@ int32_t ltl_autotune(ltl_sim_t *sim, int32_t probe_steps, void *scratch, size_t 
     // time one candidate: ms per step, or a negative value if it is infeasible
     auto time_one = [&](const ltl_tuning_t &t, float *ms_out) -> int32_t {
         *ms_out = -1.f;
-        std::string saved = g_err;
-        if (check_tuning(s, t) != LTL_OK) { g_err = saved; return LTL_OK; }
+        const SavedError saved = save_error();
+        if (check_tuning(s, t) != LTL_OK) { restore_error(saved); return LTL_OK; }
         // each candidate runs a whole number of its own launches (no shorter remainder launch
         // to bias it) covering at least probe_steps steps; candidates compare per step
         const int T = t.steps_per_launch;

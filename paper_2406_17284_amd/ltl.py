@@ -34,7 +34,7 @@ BOUNDARIES = {"dead": LTL_BOUNDARY_DEAD, "periodic": LTL_BOUNDARY_PERIODIC}
 # every symbol the header declares
 EXPORTS = [
     "ltl_buffer_bytes", "ltl_pitch", "ltl_create", "ltl_step", "ltl_read", "ltl_current",
-    "ltl_get_tuning", "ltl_set_tuning", "ltl_autotune", "ltl_set_boundary", "ltl_destroy", "ltl_last_error",
+    "ltl_get_tuning", "ltl_set_tuning", "ltl_autotune", "ltl_set_boundary", "ltl_destroy", "ltl_last_error", "ltl_last_error_code",
     "ltl_batch_buffer_bytes", "ltl_batch_create", "ltl_batch_step", "ltl_batch_read",
     "ltl_batch_current", "ltl_batch_get_tuning", "ltl_batch_set_tuning", "ltl_batch_autotune",
     "ltl_batch_destroy", "ltl_tuning_lookup", "ltl_tuning_store",
@@ -85,6 +85,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "ltl_set_boundary": ([P, I32], I32),
         "ltl_destroy": ([P], I32),
         "ltl_last_error": ([], ctypes.c_char_p),
+        "ltl_last_error_code": ([], I32),
         "ltl_batch_buffer_bytes": ([I32, P, P], SZ),
         "ltl_batch_create": ([ctypes.POINTER(P), I32, P, P, P, I32, P, P, SZ, P, P, P], I32),
         "ltl_batch_step": ([P, I32], I32),
@@ -118,9 +119,10 @@ def _check(rc: int) -> int:
 
 
 def _check_size(n: int) -> int:
-    """Size-returning calls give 0 on an invalid argument (message in ltl_last_error)."""
+    """Size-returning calls give 0 on an invalid argument (code and message of the refusal in
+    ltl_last_error_code / ltl_last_error)."""
     if n == 0:
-        raise LtlError(LTL_ERR_ARG, last_error())
+        raise LtlError(load().ltl_last_error_code(), last_error())
     return n
 
 

@@ -34,10 +34,13 @@ def test_pitch_and_buffer_bytes():
     for R in (1, 16, 32):
         for m in (ltl.LTL_CAT_I8, ltl.LTL_CAT_F16, ltl.LTL_CAT_F8, ltl.LTL_DIRECT):
             assert ltl.ltl_buffer_bytes(3, 100, R, m) == 3 * 128
-    for bad in [(0, 5, 1, 0), (5, 0, 1, 0), (-1, 3, 1, 0), (3, 3, 0, 0), (3, 3, 33, 0), (3, 3, 1, 4), (3, 3, 1, -1)]:
+    for bad, code in [((0, 5, 1, 0), ltl.LTL_ERR_ARG), ((5, 0, 1, 0), ltl.LTL_ERR_ARG), ((-1, 3, 1, 0), ltl.LTL_ERR_ARG),
+                      ((3, 3, 0, 0), ltl.LTL_ERR_RULE), ((3, 3, 33, 0), ltl.LTL_ERR_RULE), ((3, 3, 1, 4), ltl.LTL_ERR_ARG),
+                      ((3, 3, 1, -1), ltl.LTL_ERR_ARG)]:
         with pytest.raises(ltl.LtlError) as e:
             ltl.ltl_buffer_bytes(*bad)
-        assert e.value.code == ltl.LTL_ERR_ARG
+        assert e.value.code == code, bad
+        assert ltl.load().ltl_last_error_code() == code
         assert ltl.last_error()
 
 
