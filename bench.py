@@ -18,6 +18,7 @@ Prints one JSON line on stdout (progress goes to stderr).
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-sweep] [--no-life] [--no-batch] [--no-decay]
                   [--no-cpu] [--tuning T,rows,cols,waves[,persistent[,lds_pad]]] [--energy] [--shard N]
+                  [--only sweep|batch|decay|life [--sweep-radii ...] [--sweep-methods ...]]
 """
 from __future__ import annotations
 
@@ -498,6 +499,9 @@ def main():
     ap.add_argument("--tuning", type=str, default="",
                     help="T,tile_rows,tile_cols,waves[,persistent[,lds_pad]] for the headline (default: the "
                          "library's own pick from its tuning table)")
+    ap.add_argument("--only", choices=("sweep", "batch", "decay", "life"), default="",
+                    help="run this one workload alone (no headline, no CPU baselines) and print its record; "
+                         "for profiler runs whose kernel averages must cover that workload only")
     ap.add_argument("--calib-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (HBM counter calibration) and exit")
     args = ap.parse_args()
@@ -529,6 +533,14 @@ def main():
 
     torch.cuda.set_device(0)
     digests = load_digests()
+    if args.only:
+        legs = {"sweep": bench_sweep, "batch": bench_batch, "decay": bench_decay}
+        if args.only == "life":
+            rec, _ = bench_life(args, ltl, inputs, torch, digests)
+        else:
+            rec = legs[args.only](args, ltl, inputs, torch, digests, None)
+        print(json.dumps({"only": args.only, "record": rec}), flush=True)
+        return
     w = inputs.WORKLOADS["bosco4096"]
     g0_np = inputs.bernoulli_grid(w.H, w.W, w.p, w.seed)
     g0 = torch.from_numpy(g0_np).cuda()

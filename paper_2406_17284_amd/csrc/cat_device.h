@@ -203,8 +203,13 @@ __device__ __forceinline__ StepGeom step_geom(const CatParams &p, int t) {
     g.E = (p.r * (p.T - t) + 15) & ~15;
     g.nstrips = (p.TW + 2 * g.E) >> 5;
     g.nrb = (p.TH + 2 * g.E) >> 4;
-    g.nseg = (g.nrb + MAXC - 1) / MAXC;
-    g.seglen = (g.nrb + g.nseg - 1) / g.nseg;
+    if (g.nrb <= MAXC) {   // one segment per strip (the usual case): no integer division
+        g.nseg = 1;
+        g.seglen = g.nrb;
+    } else {
+        g.nseg = (g.nrb + MAXC - 1) / MAXC;
+        g.seglen = (g.nrb + g.nseg - 1) / g.nseg;
+    }
     return g;
 }
 
@@ -356,7 +361,7 @@ __device__ __forceinline__ void phase_a(const uint8_t *At, uint32_t a_off, uint3
                 if (2 * (P) + 3 < nh) CAT_LDA(2 * (P) + 3)                                         \
             }                                                                                      \
             CAT_HB(2 * (P))                                                                        \
-            if (2 * (P) + 1 < nh) CAT_HB(2 * (P) + 1)                                              \
+            CAT_HB(2 * (P) + 1)    /* one past the item when nh is odd: zero weight */               \
         }
         CAT_LDA(0) CAT_LDA(1)
         CAT_APAIR(0) CAT_APAIR(1) CAT_APAIR(2) CAT_APAIR(3) CAT_APAIR(4) CAT_APAIR(5) CAT_APAIR(6) CAT_APAIR(7)
@@ -606,8 +611,8 @@ __device__ __forceinline__ void cat_steps(const CatParams &p, uint8_t *Qt, uint8
         const int items = g.nstrips * g.nseg;
         int j0 = 0, rb0 = 0, count = 0;
         if (wave < items) {
-            const int strip = wave % g.nstrips;
-            const int seg = wave / g.nstrips;
+            const int strip = g.nseg == 1 ? wave : wave % g.nstrips;
+            const int seg = g.nseg == 1 ? 0 : wave / g.nstrips;
             const int mb_lo = seg * g.seglen;
             const int mb_hi = min(g.nrb, mb_lo + g.seglen);
             j0 = -g.E + 32 * strip;
