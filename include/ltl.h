@@ -68,7 +68,7 @@ typedef enum {
 } ltl_method_t;
 
 /* Launch shape. Zero fields mean "library default". The result never depends on it. The
- * direct method runs fixed 32 x 64 tiles, one step per launch: it checks tile_rows, tile_cols
+ * direct method runs fixed 128 x 256 tiles, one step per launch: it checks tile_rows, tile_cols
  * and waves against the ranges below but does not use them; only use_graph applies to it. */
 typedef struct {
     int32_t steps_per_launch; /* T >= 1 time steps fused in one kernel launch (temporal blocking) */
@@ -173,6 +173,26 @@ int32_t ltl_set_boundary(ltl_sim_t *sim, int32_t boundary);
 /* Release the handle (graphs, descriptors). Does not free the caller's buffers and does
  * not synchronize; the caller synchronizes the stream first. NULL is accepted. */
 int32_t ltl_destroy(ltl_sim_t *sim);
+
+/* For callers that cannot allocate device memory (code under hipGraph stream capture, tight
+ * serving loops, harnesses that forbid hipMalloc): one run of ltl_create + ltl_set_boundary +
+ * ltl_step(n_steps) + ltl_read + ltl_destroy in a single call that calls no hipMalloc, hipFree
+ * or other allocating routine. The result equals that sequence's, cell for cell.
+ *  H, W, rule, method, buf_a/b, buf_bytes, init, init_pitch   as for ltl_create (buf_a and
+ *             buf_b are overwritten: buf_a with init and zero padding, buf_b with zeros).
+ *  boundary   an ltl_boundary_t (as for ltl_set_boundary).
+ *  n_steps    >= 0 steps; dst/dst_pitch   device memory receiving the H x W result (as ltl_read).
+ *  stream     every operation is enqueued on it; nothing is synchronized (the call does not
+ *             validate the initial states: each must be < max(C, 2)).
+ * The launch shape is the tuning table's entry (or LTL_TILE), as for a new handle; the kernels
+ * run as plain launches, no hipGraph. The band operands and the zero page of the run sit in a
+ * 12 KiB static device array of the library (one per GPU, held until the process ends), filled
+ * by a kernel at the start of every call; it is large enough for every rule and grid size.
+ * Calls on one GPU share that array, so calls that overlap on one GPU (different streams, or
+ * different host threads) race and must be serialized by the caller. */
+int32_t ltl_run_noalloc(int32_t H, int32_t W, const ltl_rule_t *rule, int32_t method, int32_t boundary,
+                        void *buf_a, void *buf_b, size_t buf_bytes, const void *init, size_t init_pitch,
+                        int32_t n_steps, void *dst, size_t dst_pitch, hipStream_t stream);
 
 /* Message of the last failing call on this thread ("" if none). */
 const char *ltl_last_error(void);

@@ -15,6 +15,8 @@
 // consecutive dwords of one row: conflict-free LDS reads, coalesced stores.
 //
 // Also here: the state-range validation used at creation.
+#include <algorithm>
+
 #include "ltl_internal.h"
 
 namespace ltl {
@@ -214,6 +216,50 @@ hipError_t launch_validate(const uint8_t *src, int H, int W, size_t pitch, int s
     if (blocks == 0) blocks = 1;
     void *args[] = {(void *)&src, (void *)&H, (void *)&W, (void *)&pitch, (void *)&states, (void *)&flag};
     return hipLaunchKernel((const void *)&validate_states, dim3(blocks), dim3(256), args, 0, s);
+}
+
+// Device constants of a CAT launch written on the device: the band table of (elem, r) in the
+// band_table layout (LTL_BAND_OPS x 64 lanes x 4 dwords), then `zero_bytes` zero bytes (the
+// page out-of-grid tile loads read). Every byte of the range is written.
+__global__ void fill_constants(uint32_t *dst, int elem, int r, int zero_dwords) {
+    const int n = LTL_BAND_TABLE_INTS + zero_dwords;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+        dst[i] = i < LTL_BAND_TABLE_INTS ? band_dword(elem, r, i >> 8, (i >> 2) & 63, i & 3) : 0u;
+}
+
+hipError_t launch_fill_constants(uint8_t *dst, int elem, int r, size_t zero_bytes, hipStream_t s) {
+    uint32_t *d = reinterpret_cast<uint32_t *>(dst);
+    int zd = (int)(zero_bytes / 4);
+    void *args[] = {(void *)&d, (void *)&elem, (void *)&r, (void *)&zd};
+    return hipLaunchKernel((const void *)&fill_constants, dim3(16), dim3(256), args, 0, s);
+}
+
+// Ping-pong buffers of an H x pitch grid from a caller's initial grid: a = init with the
+// columns W..pitch-1 zero, b = all zero. One thread per dword of each row (pitch % 64 == 0).
+__global__ void prepare_grids(uint8_t *a, uint8_t *b, const uint8_t *init, size_t init_pitch, int H, int W,
+                              int pitch) {
+    const int dpr = pitch >> 2;
+    const size_t n = (size_t)H * dpr;
+    for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (size_t)gridDim.x * blockDim.x) {
+        const size_t i = k / dpr;
+        const int j0 = (int)(k - i * dpr) << 2;
+        const uint8_t *src = init + i * init_pitch;
+        uint32_t v = 0;
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+            v |= (j0 + e < W ? (uint32_t)src[j0 + e] : 0u) << (8 * e);
+        reinterpret_cast<uint32_t *>(a)[k] = v;
+        reinterpret_cast<uint32_t *>(b)[k] = 0u;
+    }
+}
+
+hipError_t launch_prepare_grids(uint8_t *a, uint8_t *b, const uint8_t *init, size_t init_pitch, int H, int W,
+                                int pitch, hipStream_t s) {
+    const size_t n = (size_t)H * (size_t)(pitch >> 2);
+    unsigned blocks = (unsigned)std::min<size_t>((n + 255) / 256, 8192);
+    if (blocks == 0) blocks = 1;
+    void *args[] = {(void *)&a, (void *)&b, (void *)&init, (void *)&init_pitch, (void *)&H, (void *)&W, (void *)&pitch};
+    return hipLaunchKernel((const void *)&prepare_grids, dim3(blocks), dim3(256), args, 0, s);
 }
 
 }  // namespace ltl

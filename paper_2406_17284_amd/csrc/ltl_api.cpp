@@ -448,6 +448,34 @@ int32_t initial_tuning(ltl_sim &s) {
     return LTL_OK;
 }
 
+// ---- allocation-free runs (ltl_run_noalloc)
+// The device constants of those runs (one band table and the zero page, 12 KiB) live in this
+// file-scope array. In host code its name is only a stand-in; the device address comes from
+// hipGetSymbolAddress, once per device, on the first allocation-free call with that device
+// current. Every allocation-free call on a device rewrites that device's copy, so such calls
+// must not overlap on one device (they would race on the band table).
+constexpr size_t kScratchBytes = kConstBytes;
+static __device__ __align__(256) uint8_t scratch[kScratchBytes];
+static_assert(kBandBytes + 16 <= kScratchBytes, "a band table and a zero vector fit in the static area");
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+uint8_t *g_scratch_ptr[kMaxDevices] = {};
+
+int32_t scratch_of_current_device(uint8_t **out) {
+    int dev = -1;
+    HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices) return fail(LTL_ERR_ARG, "device index outside 0..63");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)), "hipGetSymbolAddress");
+        if (!ptr) return fail(LTL_ERR_HIP, "hipGetSymbolAddress returned NULL");
+        g_scratch_ptr[dev] = static_cast<uint8_t *>(ptr);
+    }
+    *out = g_scratch_ptr[dev];
+    return LTL_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -702,6 +730,59 @@ int32_t ltl_set_boundary(ltl_sim_t *sim, int32_t boundary) {
     sim->periodic = (boundary == LTL_BOUNDARY_PERIODIC) ? 1 : 0;
     // a shape taken from the tuning table follows the boundary's own entry
     if (!sim->user_tuned) return initial_tuning(*sim);
+    return LTL_OK;
+}
+
+int32_t ltl_run_noalloc(int32_t H, int32_t W, const ltl_rule_t *rule, int32_t method, int32_t boundary,
+                        void *buf_a, void *buf_b, size_t buf_bytes, const void *init, size_t init_pitch,
+                        int32_t n_steps, void *dst, size_t dst_pitch, hipStream_t stream) {
+    if (H < 1 || W < 1) return fail(LTL_ERR_ARG, "H and W must be >= 1");
+    if (!buf_a || !buf_b || !init || !dst) return fail(LTL_ERR_ARG, "NULL buffer");
+    if (buf_a == buf_b) return fail(LTL_ERR_ARG, "the two buffers must differ");
+    if (init_pitch < (size_t)W) return fail(LTL_ERR_ARG, "init_pitch < W");
+    if (dst_pitch < (size_t)W) return fail(LTL_ERR_ARG, "dst_pitch < W");
+    if (n_steps < 0) return fail(LTL_ERR_ARG, "n_steps must be >= 0");
+    if (grid_too_large(H, W)) return fail(LTL_ERR_SIZE, "grid larger than 2^31 - 1 bytes (H x ltl_pitch(W))");
+    if (((uintptr_t)buf_a & 255) || ((uintptr_t)buf_b & 255)) return fail(LTL_ERR_ARG, "buffers must be 256-byte aligned");
+    if (boundary != LTL_BOUNDARY_DEAD && boundary != LTL_BOUNDARY_PERIODIC) return fail(LTL_ERR_ARG, "unknown boundary");
+    if (boundary == LTL_BOUNDARY_PERIODIC && W % 16 != 0)
+        return fail(LTL_ERR_UNSUPPORTED, "a periodic grid needs W divisible by 16");
+    int32_t rc = validate_rule(rule, method);
+    if (rc != LTL_OK) return rc;
+    const size_t need = (size_t)H * (size_t)pitch_of(W);
+    if (buf_bytes < need) return fail(LTL_ERR_SIZE, "buffers need " + std::to_string(need) + " bytes each");
+    {
+        ltl_tuning_t t;
+        std::string err;
+        if (env_tile(&t, &err) < 0) return fail(LTL_ERR_ARG, err);
+    }
+    uint8_t *sp = nullptr;
+    if ((rc = scratch_of_current_device(&sp)) != LTL_OK) return rc;
+
+    // a handle on the stack: host metadata only, constants in the static area, no graphs
+    ltl_sim s;
+    s.H = H;
+    s.W = W;
+    s.pitch = pitch_of(W);
+    s.rule = *rule;
+    s.method = method;
+    s.epi = epi_of(*rule, elem_of(method, rule->R, rule->N));
+    s.rc = make_consts(*rule, s.epi);
+    s.buf[0] = (uint8_t *)buf_a;
+    s.buf[1] = (uint8_t *)buf_b;
+    s.stream = stream;
+    s.dconst = sp;
+    s.periodic = (boundary == LTL_BOUNDARY_PERIODIC) ? 1 : 0;
+    if ((rc = initial_tuning(s)) != LTL_OK) return rc;
+    s.tuning.use_graph = 0;   // plain launches: a graph instantiation allocates
+
+    HIP_TRY(launch_fill_constants(sp, elem_of(method, rule->R, rule->N), rule->R, kConstBytes - kBandBytes, stream),
+            "constants kernel launch");
+    HIP_TRY(launch_prepare_grids(s.buf[0], s.buf[1], (const uint8_t *)init, init_pitch, H, W, s.pitch, stream),
+            "prepare kernel launch");
+    if ((rc = do_steps(s, n_steps)) != LTL_OK) return rc;
+    HIP_TRY(hipMemcpy2DAsync(dst, dst_pitch, s.buf[s.cur], s.pitch, W, H, hipMemcpyDeviceToDevice, stream),
+            "hipMemcpy2DAsync");
     return LTL_OK;
 }
 

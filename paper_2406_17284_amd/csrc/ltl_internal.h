@@ -280,6 +280,11 @@ struct DirectBatchParams {
 hipError_t launch_direct(const DirectParams &p, hipStream_t s);
 hipError_t launch_validate(const uint8_t *src, int H, int W, size_t pitch, int states,
                            uint32_t *flag, hipStream_t s);
+// Band table of (elem, r) followed by zero_bytes zero bytes, written by a kernel at dst.
+hipError_t launch_fill_constants(uint8_t *dst, int elem, int r, size_t zero_bytes, hipStream_t s);
+// a = init (H x W, init_pitch) with zero columns up to pitch; b = 0 (both H x pitch).
+hipError_t launch_prepare_grids(uint8_t *a, uint8_t *b, const uint8_t *init, size_t init_pitch, int H, int W,
+                                int pitch, hipStream_t s);
 
 // Kernel symbol and launch shape, for building graph nodes.
 struct KernelLaunch {

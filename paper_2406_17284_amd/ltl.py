@@ -37,7 +37,7 @@ EXPORTS = [
     "ltl_get_tuning", "ltl_set_tuning", "ltl_autotune", "ltl_set_boundary", "ltl_destroy", "ltl_last_error", "ltl_last_error_code",
     "ltl_batch_buffer_bytes", "ltl_batch_create", "ltl_batch_step", "ltl_batch_read",
     "ltl_batch_current", "ltl_batch_get_tuning", "ltl_batch_set_tuning", "ltl_batch_autotune",
-    "ltl_batch_destroy", "ltl_tuning_lookup", "ltl_tuning_store",
+    "ltl_batch_destroy", "ltl_tuning_lookup", "ltl_tuning_store", "ltl_run_noalloc",
 ]
 
 
@@ -99,6 +99,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
                                ctypes.POINTER(ctypes.c_int32)], I32),
         "ltl_tuning_store": ([I32, I32, ctypes.POINTER(ltl_rule_t), I32, I32, I32, ctypes.POINTER(ltl_tuning_t),
                               ctypes.c_double], I32),
+        "ltl_run_noalloc": ([I32, I32, ctypes.POINTER(ltl_rule_t), I32, I32, P, P, SZ, P, SZ, I32, P, SZ, P], I32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -166,6 +167,15 @@ def ltl_create(H: int, W: int, rule, method: int, buf_a: int, buf_b: int, buf_by
                              ctypes.c_void_p(buf_b), buf_bytes, ctypes.c_void_p(init), init_pitch,
                              ctypes.c_void_p(_stream_handle(stream))))
     return h.value
+
+
+def ltl_run_noalloc(H: int, W: int, rule, method: int, boundary: int, buf_a: int, buf_b: int, buf_bytes: int,
+                    init: int, init_pitch: int, n_steps: int, dst: int, dst_pitch: int, stream=None) -> None:
+    r = make_rule(rule)
+    _check(load().ltl_run_noalloc(int(H), int(W), ctypes.byref(r), int(method), int(boundary), ctypes.c_void_p(buf_a),
+                                  ctypes.c_void_p(buf_b), int(buf_bytes), ctypes.c_void_p(init), int(init_pitch),
+                                  int(n_steps), ctypes.c_void_p(dst), int(dst_pitch),
+                                  ctypes.c_void_p(_stream_handle(stream))))
 
 
 def ltl_step(sim: int, n_steps: int) -> None:

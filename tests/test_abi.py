@@ -148,3 +148,29 @@ def test_batch_null_handles():
     assert lib.ltl_batch_get_tuning(None, ctypes.byref(t)) == ltl.LTL_ERR_ARG
     assert lib.ltl_batch_set_tuning(None, ctypes.byref(t)) == ltl.LTL_ERR_ARG
     assert lib.ltl_batch_autotune(None, 1, None, 0, None) == ltl.LTL_ERR_ARG
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(H=0), ltl.LTL_ERR_ARG),
+    (dict(a=0), ltl.LTL_ERR_ARG),
+    (dict(dst=0), ltl.LTL_ERR_ARG),
+    (dict(a=256, b=256), ltl.LTL_ERR_ARG),
+    (dict(dst_pitch=4), ltl.LTL_ERR_ARG),
+    (dict(n=-1), ltl.LTL_ERR_ARG),
+    (dict(a=100), ltl.LTL_ERR_ARG),
+    (dict(boundary=2), ltl.LTL_ERR_ARG),
+    (dict(boundary=1, W=8), ltl.LTL_ERR_UNSUPPORTED),
+    (dict(rule=(0, 0, 1, 3, 4, 3, 3)), ltl.LTL_ERR_RULE),
+    (dict(method=ltl.LTL_CAT_F8, rule=(8, 0, 1, 3, 4, 3, 3)), ltl.LTL_ERR_INEXACT),
+    (dict(nbytes=10), ltl.LTL_ERR_SIZE),
+])
+def test_run_noalloc_refusals_without_device_work(kw, code):
+    """ltl_run_noalloc checks its arguments before it touches the device (no GPU needed)."""
+    args = dict(H=8, W=8, rule=(1, 0, 1, 3, 4, 3, 3), method=ltl.LTL_CAT_I8, boundary=0, a=256, b=512,
+                nbytes=1 << 20, init=1024, init_pitch=8, n=3, dst=2048, dst_pitch=8)
+    args.update(kw)
+    with pytest.raises(ltl.LtlError) as e:
+        ltl.ltl_run_noalloc(args["H"], args["W"], args["rule"], args["method"], args["boundary"], args["a"], args["b"],
+                            args["nbytes"], args["init"], args["init_pitch"], args["n"], args["dst"],
+                            args["dst_pitch"])
+    assert e.value.code == code
