@@ -109,14 +109,27 @@ def mfma_issued(tuning, avg_launch_s, cells, r):
 
 
 def cpu_model() -> str:
+    """/proc/cpuinfo's model name with its family / model / stepping numbers (a virtualised host
+    may report only the product line) and the CPUs this process may run on."""
+    info = {}
     try:
         with open("/proc/cpuinfo") as f:
             for line in f:
-                if line.startswith("model name"):
-                    return line.split(":", 1)[1].strip()
+                if ":" in line:
+                    k, v = (x.strip() for x in line.split(":", 1))
+                    if k in ("model name", "cpu family", "model", "stepping") and k not in info:
+                        info[k] = v
+                if not line.strip() and info:
+                    break
     except OSError:
         pass
-    return "unknown"
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        usable = os.cpu_count() or 0
+    name = info.get("model name", "unknown")
+    ids = ", ".join(f"{k} {info[k]}" for k in ("cpu family", "model", "stepping") if k in info)
+    return f"{name} ({ids}; {usable} CPUs usable by this process)" if ids else f"{name} ({usable} CPUs usable)"
 
 
 def load_digests():

@@ -79,7 +79,16 @@ typedef struct {
     int32_t persistent;       /* CAT methods, single grid: 1 = persistent workgroups (about one per
                                  CU slot) that each walk a contiguous run of tiles, loading tile
                                  i+1 into a second LDS buffer while tile i computes (pays off when
-                                 tiles stream from HBM); 0 = one workgroup per tile. Batches take 0. */
+                                 tiles stream from HBM); 0 = one workgroup per tile and launch;
+                                 2 = dataflow form: one cooperative launch per step call runs all
+                                 rounds of T steps, one resident workgroup per tile, and a tile
+                                 starts a round once the tiles its window overlaps finished the
+                                 previous one (per-tile round counters instead of a kernel
+                                 boundary). It needs every tile resident at once (at most 4096
+                                 tiles), a margin no wider than the tile, and on a torus partial
+                                 edge tiles at least that wide; a wait that runs out (after
+                                 LTL_FLOW_SPIN_LIMIT polls, default 2^24) makes the next ltl_step
+                                 or ltl_read return LTL_ERR_HIP. Batches take 0. */
     int32_t lds_pad;          /* CAT methods: extra bytes per LDS tile row, a multiple of 16 in 0..128;
                                  it moves the LDS bank each row starts in (the direct method ignores it) */
 } ltl_tuning_t;

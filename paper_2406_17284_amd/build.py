@@ -16,7 +16,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libltl.so")
 ARCH = "gfx950"
 
-SOURCES = ["cat_kernel.hip", "direct_kernel.hip", "batch_kernel.hip", "ltl_api.cpp", "batch_api.cpp", "tuning_cache.cpp"]
+SOURCES = ["cat_kernel.hip", "flow_kernel.hip", "direct_kernel.hip", "batch_kernel.hip", "ltl_api.cpp", "batch_api.cpp", "tuning_cache.cpp"]
 
 # hipcc flags: gfx950 only; packed FP32 instructions disabled in device code.
 HIPCC_FLAGS = [

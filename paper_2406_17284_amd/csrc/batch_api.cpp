@@ -187,18 +187,18 @@ int32_t batch_check_tuning(const ltl_batch &b, const ltl_tuning_t &t) {
 // earlier step call may still be running.
 void batch_clear_graphs(ltl_batch &b) {
     if (b.graphs.empty()) return;
-    (void)hipStreamSynchronize(b.stream);
-    for (auto &kv : b.graphs) (void)hipGraphExecDestroy(kv.second);
+    quiet(hipStreamSynchronize(b.stream));
+    for (auto &kv : b.graphs) quiet(hipGraphExecDestroy(kv.second));
     b.graphs.clear();
 }
 
 void batch_free_plans(ltl_batch &b) {
     batch_clear_graphs(b);
-    if (!b.plans.empty() || b.ditems) (void)hipStreamSynchronize(b.stream);   // descriptors in use by queued launches
+    if (!b.plans.empty() || b.ditems) quiet(hipStreamSynchronize(b.stream));   // descriptors in use by queued launches
     for (auto &pl : b.plans)
-        if (pl.dinst) (void)hipFree(pl.dinst);
+        if (pl.dinst) quiet(hipFree(pl.dinst));
     b.plans.clear();
-    if (b.ditems) (void)hipFree(b.ditems);
+    if (b.ditems) quiet(hipFree(b.ditems));
     b.ditems = nullptr;
     b.nitems = 0;
 }
@@ -206,8 +206,8 @@ void batch_free_plans(ltl_batch &b) {
 void batch_release(ltl_batch &b) {
     batch_free_plans(b);
     if (b.owns_shared) {
-        if (b.dconst) (void)hipFree(b.dconst);
-        if (b.dflag) (void)hipFree(b.dflag);
+        if (b.dconst) quiet(hipFree(b.dconst));
+        if (b.dflag) quiet(hipFree(b.dflag));
     }
     b.dconst = nullptr;
     b.dflag = nullptr;
@@ -222,7 +222,7 @@ int32_t upload(const std::vector<X> &h, hipStream_t s, void **out) {
     hipError_t e = hipMemcpyAsync(d, h.data(), h.size() * sizeof(X), hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
-        (void)hipFree(d);
+        quiet(hipFree(d));
         return hip_fail(e, "descriptor upload");
     }
     *out = d;
@@ -381,7 +381,7 @@ int32_t batch_build_graph(ltl_batch &b, int n, hipGraphExec_t *out) {
     for (int T : batch_sizes(b, n)) {
         BatchLaunch l;
         int32_t rc = batch_launch(b, T, from, &l);
-        if (rc != LTL_OK) { (void)hipGraphDestroy(g); return rc; }
+        if (rc != LTL_OK) { quiet(hipGraphDestroy(g)); return rc; }
         hipKernelNodeParams kp;
         std::memset(&kp, 0, sizeof(kp));
         void *args[1] = {l.arg()};
@@ -392,13 +392,13 @@ int32_t batch_build_graph(ltl_batch &b, int n, hipGraphExec_t *out) {
         kp.kernelParams = args;
         hipGraphNode_t node;
         hipError_t e = hipGraphAddKernelNode(&node, g, prev ? &prev : nullptr, prev ? 1 : 0, &kp);
-        if (e != hipSuccess) { (void)hipGraphDestroy(g); return hip_fail(e, "hipGraphAddKernelNode"); }
+        if (e != hipSuccess) { quiet(hipGraphDestroy(g)); return hip_fail(e, "hipGraphAddKernelNode"); }
         prev = node;
         from ^= 1;
     }
     hipGraphExec_t ex = nullptr;
     hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(g);
+    quiet(hipGraphDestroy(g));
     if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
     *out = ex;
     return LTL_OK;
@@ -511,7 +511,7 @@ int32_t batch_autotune(ltl_batch &b, int probe_steps, void *scratch, size_t scra
     probe.arena[1] = b.arena[1];
     hipEvent_t ev0, ev1;
     HIP_TRY(hipEventCreate(&ev0), "hipEventCreate");
-    if (hipEventCreate(&ev1) != hipSuccess) { (void)hipEventDestroy(ev0); return fail(LTL_ERR_HIP, "hipEventCreate"); }
+    if (hipEventCreate(&ev1) != hipSuccess) { quiet(hipEventDestroy(ev0)); return fail(LTL_ERR_HIP, "hipEventCreate"); }
     float best_ms = 1e30f;
     ltl_tuning_t best_t = b.tuning;
     int32_t rc = LTL_OK;
@@ -569,8 +569,8 @@ done:
         hipError_t re = hipMemcpyAsync(b.arena[b.cur], scratch, b.arena_bytes, hipMemcpyDeviceToDevice, b.stream);
         if (re == hipSuccess) re = hipStreamSynchronize(b.stream);
         batch_release(probe);
-        (void)hipEventDestroy(ev0);
-        (void)hipEventDestroy(ev1);
+        quiet(hipEventDestroy(ev0));
+        quiet(hipEventDestroy(ev1));
         if (rc != LTL_OK) return rc;
         if (re != hipSuccess) return hip_fail(re, "autotune restore");
     }

@@ -34,7 +34,9 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) c
         if constexpr (ELEM == ELEM_I8) cat_tile<ELEM, EPI_WIN>(p, item.tile, lds, tid, lane, wave, nwaves, cd);
     } else if (item.epi == EPI_HALF)
         cat_tile<ELEM, EPI_HALF>(p, item.tile, lds, tid, lane, wave, nwaves, cd);
-    else
+    else if (item.epi == EPI_DECAY8) {
+        if constexpr (ELEM == ELEM_I8) cat_tile<ELEM, EPI_DECAY8>(p, item.tile, lds, tid, lane, wave, nwaves, cd);
+    } else
         cat_tile<ELEM, EPI_DECAY>(p, item.tile, lds, tid, lane, wave, nwaves, cd);
 }
 
@@ -46,10 +48,16 @@ const void *cat_batch_func(int elem) {
 
 int cat_batch_occupancy(int elem, int waves, size_t lds) {
     const void *f = cat_batch_func(elem);
-    if (lds > 65536 && hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+    // a shape the device cannot run reads as zero workgroups; its HIP error is not left pending
+    if (lds > 65536 && hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess) {
+        (void)hipGetLastError();
         return 0;
+    }
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, 64 * waves, lds) != hipSuccess) return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, 64 * waves, lds) != hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
     return nb;
 }
 

@@ -135,6 +135,17 @@ __device__ __forceinline__ uint32_t transition4(v4i n, uint32_t s, uint32_t m, c
         const uint32_t x = inrange16(n, s, rc) & m;
         *alive = x;
         return x;
+    } else if constexpr (EPI == EPI_DECAY8) {
+        // C <= 8: the state bytes (0..7) select from 8-byte tables with one byte permute each:
+        // the alive bit (state == 1), and the next state when the range test fails (N0) or holds
+        // (N1); the test result (0/1 per byte) then picks N1's byte over N0's as a selector offset.
+        const uint32_t a1 = __builtin_amdgcn_perm(0u, 0x00000100u, s);
+        const uint32_t x = inrange16(n, a1, rc);                     // range of the s in {0, 1} case
+        const uint32_t n0 = __builtin_amdgcn_perm(rc.N0hi, rc.N0lo, s);
+        const uint32_t n1 = __builtin_amdgcn_perm(rc.N1hi, rc.N1lo, s);
+        const uint32_t nx = __builtin_amdgcn_perm(n1, n0, (x << 2) | 0x03020100u) & m;
+        *alive = __builtin_amdgcn_perm(0u, 0x00000100u, nx);         // next state == 1
+        return nx;
     } else {
         // C >= 3. Per byte, g = 1 where the cell leaves its state: birth (s = 0, n in the birth
         // range), death (s = 1, n outside the survival range) or decay (s >= 2); the next state
@@ -251,8 +262,9 @@ __device__ __forceinline__ uint32_t pack_f16(float a, float b) {
 // 16-column halves of the strip, packed, in registers. Software-pipelined in pairs of blocks:
 // the A chunks of the next pair are read from LDS before the MFMAs of this pair run.
 // FROM_STATES: At holds states (int8 Moore with decay): each chunk's alive bits (state == 1)
-// are derived in registers as it is read.
-template <int ELEM, bool FROM_STATES = false>
+// are derived in registers as it is read, with SWAR arithmetic (1, any state byte) or one byte
+// permute per dword (2, states 0..7).
+template <int ELEM, int FROM_STATES = 0>
 __device__ __forceinline__ void phase_a(const uint8_t *At, uint32_t a_off, uint32_t a_off2, uint32_t PA, int rb0,
                                         int count, const Bands &bd, v16i &Ha, v16i &Hb, v16i &La, v16i &Lb) {
     if constexpr (ELEM == ELEM_I8X) {
@@ -339,11 +351,16 @@ __device__ __forceinline__ void phase_a(const uint8_t *At, uint32_t a_off, uint3
 #define CAT_LDA(K)                                                                                 \
         {                                                                                          \
             v4i q = *reinterpret_cast<const v4i *>(At + (a_off + (uint32_t)(16 * (rb0 - 1 + (K))) * PA)); \
-            if constexpr (FROM_STATES) {                                                           \
+            if constexpr (FROM_STATES == 1) {                                                      \
                 q[0] = (int32_t)alive_of((uint32_t)q[0]);                                          \
                 q[1] = (int32_t)alive_of((uint32_t)q[1]);                                          \
                 q[2] = (int32_t)alive_of((uint32_t)q[2]);                                          \
                 q[3] = (int32_t)alive_of((uint32_t)q[3]);                                          \
+            } else if constexpr (FROM_STATES == 2) {                                               \
+                q[0] = (int32_t)__builtin_amdgcn_perm(0u, 0x00000100u, (uint32_t)q[0]);            \
+                q[1] = (int32_t)__builtin_amdgcn_perm(0u, 0x00000100u, (uint32_t)q[1]);            \
+                q[2] = (int32_t)__builtin_amdgcn_perm(0u, 0x00000100u, (uint32_t)q[2]);            \
+                q[3] = (int32_t)__builtin_amdgcn_perm(0u, 0x00000100u, (uint32_t)q[3]);            \
             }                                                                                      \
             a[(K) & 3] = q;                                                                        \
         }
@@ -411,7 +428,7 @@ __device__ __forceinline__ void phase_a(const uint8_t *At, uint32_t a_off, uint3
             const uint8_t *q = At + (a_off + (uint32_t)(16 * (rb0 - 1 + (K))) * PA);               \
             uint2 s0 = *reinterpret_cast<const uint2 *>(q);                                        \
             uint2 s1 = *reinterpret_cast<const uint2 *>(q + 32);                                   \
-            if constexpr (FROM_STATES) {                                                           \
+            if constexpr (FROM_STATES != 0) {                                                      \
                 s0 = make_uint2(alive_of(s0.x), alive_of(s0.y));                                   \
                 s1 = make_uint2(alive_of(s1.x), alive_of(s1.y));                                   \
             }                                                                                      \
@@ -508,7 +525,7 @@ __device__ __forceinline__ void phase_b(const CatParams &p, uint8_t *Qt, uint8_t
                                         const v16i &Lb) {
     constexpr int CELL = ElemT<ELEM>::CELL;
     // Q and A are distinct tiles (int8 Moore decay reads its alive bits from Q)
-    constexpr bool SEPARATE = EPI == EPI_DECAY && ELEM != ELEM_I8 && ELEM != ELEM_F16;
+    constexpr bool SEPARATE = epi_decays(EPI) && ELEM != ELEM_I8 && ELEM != ELEM_F16;
     const uint32_t PS = (uint32_t)p.PS, PA = (uint32_t)p.PA;
     v4i ca[4], cb[4];
     uint32_t sa[4], sb[4];
@@ -519,7 +536,7 @@ __device__ __forceinline__ void phase_b(const CatParams &p, uint8_t *Qt, uint8_t
     {                                                                                              \
         ca[(M) & 3] = vproduct<ELEM, (M)>(Ha, La, bd, acc0);                                       \
         cb[(M) & 3] = vproduct<ELEM, (M)>(Hb, Lb, bd, acc0);                                       \
-        if constexpr (EPI == EPI_DECAY || kIsI8<ELEM> || ELEM == ELEM_F16) {                       \
+        if constexpr (epi_decays(EPI) || kIsI8<ELEM> || ELEM == ELEM_F16) {                        \
             const uint32_t qo = lo.q + (uint32_t)(16 * (rb0 + (M))) * PS;                          \
             sa[(M) & 3] = *reinterpret_cast<const uint32_t *>(Qt + qo);                            \
             sb[(M) & 3] = *reinterpret_cast<const uint32_t *>(Qt + qo + 16);                       \
@@ -548,11 +565,11 @@ __device__ __forceinline__ void phase_b(const CatParams &p, uint8_t *Qt, uint8_t
         } else {                                                                                   \
             const uint32_t qo = lo.q + (uint32_t)(16 * (rb0 + (M))) * PS;                          \
             const uint32_t ao = lo.a + (uint32_t)(16 * (rb0 + (M))) * PA;                          \
-            if constexpr (EPI == EPI_DECAY) {                                                      \
+            if constexpr (epi_decays(EPI)) {                                                       \
                 *reinterpret_cast<uint32_t *>(Qt + qo) = na;                                       \
                 *reinterpret_cast<uint32_t *>(Qt + qo + 16) = nb;                                  \
             }                                                                                      \
-            if constexpr ((ELEM == ELEM_I8 || ELEM == ELEM_F16) && EPI == EPI_DECAY) {             \
+            if constexpr ((ELEM == ELEM_I8 || ELEM == ELEM_F16) && epi_decays(EPI)) {              \
                 (void)ala;   /* int8 Moore and fp16 decay derive the alive bits from Q when read */ \
                 (void)alb;                                                                         \
             } else if constexpr (kIsI8<ELEM> || ELEM == ELEM_F16) {   /* two-state: the state */   \
@@ -637,7 +654,8 @@ __device__ __forceinline__ void cat_steps(const CatParams &p, uint8_t *Qt, uint8
         lo.q = (uint32_t)((L + li) * (int)PS + (L + j0 + 4 * lg));
         lo.a = (uint32_t)((L + li) * (int)PA + (L + j0 + 4 * lg) * CELL);
         if (count > 0)
-            phase_a<ELEM, (ELEM == ELEM_I8 || ELEM == ELEM_F16) && EPI == EPI_DECAY>(At, a_off, a_off2, PA, rb0, count,
+            phase_a<ELEM, !((ELEM == ELEM_I8 || ELEM == ELEM_F16) && epi_decays(EPI)) ? 0 : EPI == EPI_DECAY8 ? 2 : 1>(
+                At, a_off, a_off2, PA, rb0, count,
                                                                                    bd, Ha, Hb, La, Lb);
         if (!last) __syncthreads();   // every read of the old states precedes any in-place write
         if (count > 0) {
@@ -734,7 +752,7 @@ __device__ __forceinline__ void tile_steps(const CatParams &p, int gi0, int gj0,
     // alive map from the loaded states, where a kernel keeps one: fp8 (its encoding of 1.0, in
     // place) and the int8 wide and cross elements with decay (a second tile). int8 Moore and
     // fp16 read the states and derive the alive bits in registers.
-    if constexpr (ELEM == ELEM_F8 || ((ELEM == ELEM_I8W || ELEM == ELEM_I8X) && EPI == EPI_DECAY)) {
+    if constexpr (ELEM == ELEM_F8 || ((ELEM == ELEM_I8W || ELEM == ELEM_I8X) && epi_decays(EPI))) {
         const int W2 = p.TW + 2 * p.L;          // window columns (the PS - W2 pad is never read)
         const int vpr = W2 >> 4;
         const int nvec = (p.TH + 2 * p.L) * vpr;
@@ -743,7 +761,7 @@ __device__ __forceinline__ void tile_steps(const CatParams &p, int gi0, int gj0,
             const int col = (v - row * vpr) << 4;
             const uint4 q = *reinterpret_cast<const uint4 *>(Qt + row * p.PS + col);
             uint4 al = q;
-            if constexpr (EPI == EPI_DECAY)
+            if constexpr (epi_decays(EPI))
                 al = make_uint4(alive_of(q.x), alive_of(q.y), alive_of(q.z), alive_of(q.w));
             if constexpr (kIsI8<ELEM>) {
                 *reinterpret_cast<uint4 *>(At + row * p.PA + col) = al;

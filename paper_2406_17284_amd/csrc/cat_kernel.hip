@@ -88,6 +88,7 @@ size_t cat_lds_bytes(const CatParams &p, int elem, int epi, int persistent) {
         if (elem == ELEM_I8W)   /* radii 17..32 always have counts > 126: no 8-bit epilogue */                     \
             return dec ? (const void *)&KERNEL<ELEM_I8W, EPI_DECAY> : (const void *)&KERNEL<ELEM_I8W, EPI_HALF>;   \
         if (epi == EPI_WIN) return (const void *)&KERNEL<ELEM_I8, EPI_WIN>;                                        \
+        if (epi == EPI_DECAY8) return (const void *)&KERNEL<ELEM_I8, EPI_DECAY8>;                                  \
         return dec ? (const void *)&KERNEL<ELEM_I8, EPI_DECAY>                                                     \
                    : epi == EPI_HALF ? (const void *)&KERNEL<ELEM_I8, EPI_HALF> : (const void *)&KERNEL<ELEM_I8, EPI_BYTE>; \
     }
@@ -102,10 +103,16 @@ static const void *cat_func(int elem, int epi, int persistent) {
 int cat_occupancy(const CatParams &p, int elem, int epi, int waves, int persistent) {
     const void *f = cat_func(elem, epi, persistent);
     size_t lds = cat_lds_bytes(p, elem, epi, persistent);
-    if (lds > 65536 && hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+    // a shape the device cannot run reads as zero workgroups; its HIP error is not left pending
+    if (lds > 65536 && hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess) {
+        (void)hipGetLastError();
         return 0;
+    }
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, 64 * waves, lds) != hipSuccess) return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, 64 * waves, lds) != hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
     return nb;
 }
 

@@ -27,7 +27,15 @@ inline void restore_error(const SavedError &e) {
 }
 
 int32_t fail(int32_t code, const std::string &msg);
+// A HIP failure reported as LTL_ERR_HIP. The runtime's last-error slot is cleared as well: the
+// error is reported through this library's code, and a stale entry would otherwise surface at
+// the caller's next unrelated HIP call (torch checks it after every kernel launch).
 int32_t hip_fail(hipError_t e, const char *what);
+// The result of a HIP call whose failure needs no report (releases, synchronizations before
+// them, capability probes): a failure is dropped from the last-error slot for the same reason.
+inline void quiet(hipError_t e) {
+    if (e != hipSuccess) (void)hipGetLastError();
+}
 
 #define HIP_TRY(expr, what)                               \
     do {                                                  \

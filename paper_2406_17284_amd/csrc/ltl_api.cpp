@@ -36,6 +36,7 @@ int32_t fail(int32_t code, const std::string &msg) {
 }
 
 int32_t hip_fail(hipError_t e, const char *what) {
+    (void)hipGetLastError();
     return fail(LTL_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
 }
 
@@ -99,7 +100,7 @@ static bool window_of(const ltl_rule_t &r, int *c) {
 }
 
 int epi_of(const ltl_rule_t &r, int elem) {
-    if (r.C >= 3) return EPI_DECAY;
+    if (r.C >= 3) return (r.C <= 8 && elem == ELEM_I8) ? EPI_DECAY8 : EPI_DECAY;
     if (max_count(r) <= 126) return EPI_BYTE;
     int c = 0;
     if (elem == ELEM_I8 && window_of(r, &c)) return EPI_WIN;
@@ -126,9 +127,23 @@ RuleConsts make_consts(const ltl_rule_t &r, int epi) {
         ls = g.ls; hs = g.hs; lb = g.lb; hb = g.hb;
         rep = 0x01010101u;
         top = 0x80u;
-    } else if (epi == EPI_HALF || epi == EPI_DECAY) {   // decay: the range test of the s in {0, 1} case
+    } else if (epi == EPI_HALF || epi_decays(epi)) {   // decay: the range test of the s in {0, 1} case
         const Ranges g = rule_ranges(r, 2047);
         c.Crep = (uint32_t)c.C * 0x01010101u;
+        if (epi == EPI_DECAY8) {
+            // state k -> next state: 0 -> born (1) or stays 0, 1 -> survives (1) or starts to decay
+            // (2), k >= 2 -> k + 1, wrapping to 0 at C; bytes k >= C are never selected
+            uint64_t t0 = 0, t1 = 0;
+            for (int k = 0; k < 8; ++k) {
+                const int dec = (k >= 2 && k < c.C) ? (k + 1 < c.C ? k + 1 : 0) : 0;
+                const int f = k == 0 ? 0 : k == 1 ? 2 : dec;
+                const int h = k == 0 ? 1 : k == 1 ? 1 : dec;
+                t0 |= (uint64_t)f << (8 * k);
+                t1 |= (uint64_t)h << (8 * k);
+            }
+            c.N0lo = (uint32_t)t0; c.N0hi = (uint32_t)(t0 >> 32);
+            c.N1lo = (uint32_t)t1; c.N1hi = (uint32_t)(t1 >> 32);
+        }
         ls = g.ls; hs = g.hs; lb = g.lb; hb = g.hb;
         rep = 0x00010001u;
         top = 0x8000u;
@@ -198,6 +213,12 @@ struct ltl_sim {
     int periodic = 0;            // LTL_BOUNDARY_PERIODIC: the grid is a torus
     bool user_tuned = false;     // the launch shape came from set_tuning / autotune (not the table)
     std::map<std::pair<int32_t, int>, hipGraphExec_t> graphs;
+    // dataflow form (persistent = 2): kFlowMaxTiles per-tile round counters, then the timeout
+    // counter; the counters only grow (flow_epoch), so they are zeroed once, at creation
+    uint32_t *dflow = nullptr;
+    uint32_t flow_epoch = 0;
+    uint32_t *herr = nullptr;    // pinned host copy of the timeout counter, refreshed after each launch
+    uint32_t err_seen = 0;
 };
 
 namespace {
@@ -270,20 +291,68 @@ DirectParams direct_params(const ltl_sim &s, const uint8_t *src, uint8_t *dst) {
     return p;
 }
 
+bool cooperative_launch_supported() {
+    int dev = 0, v = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&v, hipDeviceAttributeCooperativeLaunch, dev);
+    quiet(e);
+    return e == hipSuccess && v != 0;
+}
+
+int cu_count() {
+    int dev = 0, v = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev);
+    quiet(e);
+    return e == hipSuccess ? v : 0;
+}
+
+// The dataflow form needs every tile's workgroup resident at once, at most kFlowMaxTiles tiles,
+// and windows that reach no further than the eight neighbouring tiles (margin <= the tile's
+// rows and columns; on a torus also <= the partial last tile row / column that wraps around).
+int32_t check_flow(const ltl_sim &s, const ltl_tuning_t &t) {
+    const int elem = elem_of(s.method, s.rule.R, s.rule.N);
+    const int L = cat_margin(elem, s.rule.R, t.steps_per_launch);
+    const int ntx = (s.W + t.tile_cols - 1) / t.tile_cols, nty = (s.H + t.tile_rows - 1) / t.tile_rows;
+    if (ntx * nty > kFlowMaxTiles) return fail(LTL_ERR_ARG, "the dataflow form (persistent = 2) tracks at most 4096 tiles");
+    if (L > t.tile_rows || L > t.tile_cols)
+        return fail(LTL_ERR_ARG, "the dataflow form needs a margin (" + std::to_string(L) + ") no wider than the tile");
+    if (s.periodic) {
+        const int rw = s.W % t.tile_cols, rh = s.H % t.tile_rows;
+        if ((rw && rw < L) || (rh && rh < L))
+            return fail(LTL_ERR_ARG, "the dataflow form on a torus needs partial edge tiles at least as wide as the margin");
+    }
+    if (s.dconst) {   // device checks, once the handle exists
+        if (!cooperative_launch_supported()) return fail(LTL_ERR_UNSUPPORTED, "the device has no cooperative launch");
+        CatParams p = cat_params(s, t, t.steps_per_launch, nullptr, nullptr);
+        const int occ = cat_flow_occupancy(p, elem, s.epi, t.waves);
+        if (roundup(ntx * nty, 8) > occ * cu_count())
+            return fail(LTL_ERR_ARG, "the dataflow form needs all " + std::to_string(ntx * nty) +
+                                         " tiles resident at once (" + std::to_string(occ) + " workgroups per CU)");
+    }
+    return LTL_OK;
+}
+
 int32_t check_tuning(const ltl_sim &s, const ltl_tuning_t &t) {
     if (t.steps_per_launch < 1 || t.steps_per_launch > 64) return fail(LTL_ERR_ARG, "steps_per_launch must be in 1..64");
     if (t.tile_rows < 16 || t.tile_rows > 512 || t.tile_rows % 16) return fail(LTL_ERR_ARG, "tile_rows must be a multiple of 16 in 16..512");
     if (t.tile_cols < 32 || t.tile_cols > 512 || t.tile_cols % 32) return fail(LTL_ERR_ARG, "tile_cols must be a multiple of 32 in 32..512");
     if (t.waves < 1 || t.waves > (s.method == LTL_DIRECT ? 16 : 8)) return fail(LTL_ERR_ARG, "waves must be in 1..8 (1..16 for the direct method)");
     if (t.lds_pad < 0 || t.lds_pad > 128 || t.lds_pad % 16) return fail(LTL_ERR_ARG, "lds_pad must be a multiple of 16 in 0..128");
+    if (t.persistent < 0 || t.persistent > 2) return fail(LTL_ERR_ARG, "persistent must be 0, 1 or 2");
     if (s.method != LTL_DIRECT) {
+        // host-side checks first: the device queries below must only see shapes that can exist
         CatParams p = cat_params(s, t, t.steps_per_launch, nullptr, nullptr);
-        size_t lds = cat_lds_bytes(p, elem_of(s.method, s.rule.R, s.rule.N), s.epi, t.persistent);
+        size_t lds = cat_lds_bytes(p, elem_of(s.method, s.rule.R, s.rule.N), s.epi, t.persistent == 1);
         if (lds > max_lds_bytes()) return fail(LTL_ERR_ARG, "launch shape needs " + std::to_string(lds) + " bytes of LDS");
-        if (s.dconst && cat_occupancy(p, elem_of(s.method, s.rule.R, s.rule.N), s.epi, t.waves, t.persistent) < 1)
-            return fail(LTL_ERR_ARG, "launch shape does not fit on a compute unit (registers or LDS)");
         if (!cat_shape_fits(elem_of(s.method, s.rule.R, s.rule.N), s.rule.R, t.steps_per_launch, t.tile_rows, t.tile_cols, t.waves))
             return fail(LTL_ERR_ARG, "launch shape has more strip segments than waves in some step");
+        if (t.persistent == 2) {
+            int32_t rc = check_flow(s, t);
+            if (rc != LTL_OK) return rc;
+        } else if (s.dconst && cat_occupancy(p, elem_of(s.method, s.rule.R, s.rule.N), s.epi, t.waves, t.persistent) < 1) {
+            return fail(LTL_ERR_ARG, "launch shape does not fit on a compute unit (registers or LDS)");
+        }
     } else if (t.steps_per_launch != 1) {
         return fail(LTL_ERR_ARG, "the direct method takes one step per launch");
     } else if (t.persistent) {
@@ -341,8 +410,8 @@ hipError_t enqueue_one(ltl_sim &s, const PlannedLaunch &pl) {
 // earlier step call may still be running.
 void clear_graphs(ltl_sim &s) {
     if (s.graphs.empty()) return;
-    (void)hipStreamSynchronize(s.stream);
-    for (auto &kv : s.graphs) (void)hipGraphExecDestroy(kv.second);
+    quiet(hipStreamSynchronize(s.stream));
+    for (auto &kv : s.graphs) quiet(hipGraphExecDestroy(kv.second));
     s.graphs.clear();
 }
 
@@ -356,7 +425,7 @@ int32_t build_graph(ltl_sim &s, int n, int from, hipGraphExec_t *out) {
         PlannedLaunch pl = plan(s, t, b);
         if (pl.k.lds > 65536) {
             hipError_t e = hipFuncSetAttribute(pl.k.func, hipFuncAttributeMaxDynamicSharedMemorySize, (int)pl.k.lds);
-            if (e != hipSuccess) { (void)hipGraphDestroy(g); return hip_fail(e, "hipFuncSetAttribute"); }
+            if (e != hipSuccess) { quiet(hipGraphDestroy(g)); return hip_fail(e, "hipFuncSetAttribute"); }
         }
         hipKernelNodeParams kp;
         std::memset(&kp, 0, sizeof(kp));
@@ -370,19 +439,69 @@ int32_t build_graph(ltl_sim &s, int n, int from, hipGraphExec_t *out) {
         kp.extra = nullptr;
         hipGraphNode_t node;
         hipError_t e = hipGraphAddKernelNode(&node, g, prev ? &prev : nullptr, prev ? 1 : 0, &kp);
-        if (e != hipSuccess) { (void)hipGraphDestroy(g); return hip_fail(e, "hipGraphAddKernelNode"); }
+        if (e != hipSuccess) { quiet(hipGraphDestroy(g)); return hip_fail(e, "hipGraphAddKernelNode"); }
         prev = node;
         b ^= 1;
     }
     hipGraphExec_t ex = nullptr;
     hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(g);
+    quiet(hipGraphDestroy(g));
     if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
     *out = ex;
     return LTL_OK;
 }
 
+// Polls per dataflow wait before it counts as timed out (LTL_FLOW_SPIN_LIMIT overrides it; the
+// tests force the timeout path with a tiny limit). One poll sleeps about 64 clock cycles, so the
+// default is a fraction of a second, far beyond any round.
+int flow_spin_limit() {
+    const char *e = std::getenv("LTL_FLOW_SPIN_LIMIT");
+    if (e && *e) {
+        char *end = nullptr;
+        const long v = std::strtol(e, &end, 10);
+        if (end != e && !*end && v >= 0 && v <= (1L << 30)) return (int)v;
+    }
+    return 1 << 24;
+}
+
+// One cooperative launch of the dataflow kernel covering all n steps of the chunk, followed by
+// an asynchronous copy of the timeout counter into the handle's pinned host word.
+int32_t do_flow_chunk(ltl_sim &s, int32_t n) {
+    const int T = s.tuning.steps_per_launch;
+    FlowParams f;
+    f.buf[0] = s.buf[0];
+    f.buf[1] = s.buf[1];
+    f.flags = s.dflow;
+    f.err = s.dflow + kFlowMaxTiles;
+    f.epoch = s.flow_epoch;
+    f.first = s.cur;
+    f.rounds = (n + T - 1) / T;
+    f.last_T = n - (f.rounds - 1) * T;
+    f.spin_limit = flow_spin_limit();
+    f.pad = 0;
+    CatParams p = cat_params(s, s.tuning, T, nullptr, nullptr);
+    HIP_TRY(launch_cat_flow(p, f, elem_of(s.method, s.rule.R, s.rule.N), s.epi, s.tuning.waves, s.stream),
+            "cooperative launch of the dataflow kernel");
+    HIP_TRY(hipMemcpyAsync(s.herr, f.err, sizeof(uint32_t), hipMemcpyDeviceToHost, s.stream), "hipMemcpyAsync");
+    s.flow_epoch += (uint32_t)f.rounds;
+    s.cur ^= (f.rounds & 1);
+    s.steps_done += n;
+    return LTL_OK;
+}
+
+// A dataflow wait that ran out in an earlier call (seen once its counter copy has landed).
+int32_t check_flow_timeouts(ltl_sim &s) {
+    if (!s.herr) return LTL_OK;
+    const uint32_t v = __atomic_load_n(s.herr, __ATOMIC_ACQUIRE);
+    if (v != s.err_seen) {
+        s.err_seen = v;
+        return fail(LTL_ERR_HIP, "a dataflow wait of an earlier step call timed out (its grid is not valid)");
+    }
+    return LTL_OK;
+}
+
 int32_t do_chunk(ltl_sim &s, int32_t n) {
+    if (s.method != LTL_DIRECT && s.tuning.persistent == 2) return do_flow_chunk(s, n);
     std::vector<int> sizes = launch_sizes(s, n);
     if (s.tuning.use_graph && sizes.size() > 1) {
         auto key = std::make_pair(n, s.cur);
@@ -533,13 +652,26 @@ int32_t ltl_create(ltl_sim_t **out, int32_t H, int32_t W, const ltl_rule_t *rule
     s->tuning = default_tuning(*s);   // replaced below, once the device constants exist
 
     auto bail = [&](int32_t code) {
-        if (s->dflag) (void)hipFree(s->dflag);
-        if (s->dconst) (void)hipFree(s->dconst);
+        if (s->dflag) quiet(hipFree(s->dflag));
+        if (s->dconst) quiet(hipFree(s->dconst));
+        if (s->dflow) quiet(hipFree(s->dflow));
+        if (s->herr) quiet(hipHostFree(s->herr));
         delete s;
         return code;
     };
     hipError_t e;
     if ((e = hipMalloc(&s->dflag, sizeof(uint32_t))) != hipSuccess) { s->dflag = nullptr; return bail(hip_fail(e, "hipMalloc")); }
+    if ((e = hipMalloc(&s->dflow, (kFlowMaxTiles + 1) * sizeof(uint32_t))) != hipSuccess) {
+        s->dflow = nullptr;
+        return bail(hip_fail(e, "hipMalloc"));
+    }
+    if ((e = hipHostMalloc(&s->herr, sizeof(uint32_t), hipHostMallocDefault)) != hipSuccess) {
+        s->herr = nullptr;
+        return bail(hip_fail(e, "hipHostMalloc"));
+    }
+    *s->herr = 0;
+    if ((e = hipMemsetAsync(s->dflow, 0, (kFlowMaxTiles + 1) * sizeof(uint32_t), stream)) != hipSuccess)
+        return bail(hip_fail(e, "hipMemsetAsync"));
     if ((e = hipMalloc(&s->dconst, kConstBytes)) != hipSuccess) { s->dconst = nullptr; return bail(hip_fail(e, "hipMalloc")); }
     {
         std::vector<uint8_t> hc = host_constants(elem_of(method, rule->R, rule->N), rule->R);
@@ -566,12 +698,16 @@ int32_t ltl_create(ltl_sim_t **out, int32_t H, int32_t W, const ltl_rule_t *rule
 int32_t ltl_step(ltl_sim_t *sim, int32_t n_steps) {
     if (!sim) return fail(LTL_ERR_ARG, "sim is NULL");
     if (n_steps < 0) return fail(LTL_ERR_ARG, "n_steps must be >= 0");
+    int32_t rc = check_flow_timeouts(*sim);
+    if (rc != LTL_OK) return rc;
     return do_steps(*sim, n_steps);
 }
 
 int32_t ltl_read(ltl_sim_t *sim, void *dst, size_t dst_pitch) {
     if (!sim || !dst) return fail(LTL_ERR_ARG, "NULL argument");
     if (dst_pitch < (size_t)sim->W) return fail(LTL_ERR_ARG, "dst_pitch < W");
+    int32_t rc = check_flow_timeouts(*sim);
+    if (rc != LTL_OK) return rc;
     HIP_TRY(hipMemcpy2DAsync(dst, dst_pitch, sim->buf[sim->cur], sim->pitch, sim->W, sim->H,
                              hipMemcpyDeviceToDevice, sim->stream), "hipMemcpy2DAsync");
     return LTL_OK;
@@ -608,7 +744,6 @@ int32_t ltl_set_tuning(ltl_sim_t *sim, const ltl_tuning_t *tuning) {
         while (t.waves < 8 && s_fits(*sim, t)) t.waves *= 2;
     }
     t.use_graph = t.use_graph ? 1 : 0;
-    t.persistent = t.persistent ? 1 : 0;
     if (sim->method == LTL_DIRECT) t.lds_pad = 0;
     int32_t rc = check_tuning(*sim, t);
     if (rc != LTL_OK) return rc;
@@ -639,10 +774,14 @@ int32_t ltl_autotune(ltl_sim_t *sim, int32_t probe_steps, void *scratch, size_t 
     probe.epi = s.epi; probe.rc = s.rc; probe.buf[0] = s.buf[0]; probe.buf[1] = s.buf[1];
     probe.periodic = s.periodic;
     probe.dconst = s.dconst;
+    probe.dflow = s.dflow;
+    probe.herr = s.herr;
+    probe.flow_epoch = s.flow_epoch;
+    probe.err_seen = s.err_seen;
     probe.stream = s.stream;
     hipEvent_t ev0, ev1;
     HIP_TRY(hipEventCreate(&ev0), "hipEventCreate");
-    if (hipEventCreate(&ev1) != hipSuccess) { (void)hipEventDestroy(ev0); return fail(LTL_ERR_HIP, "hipEventCreate"); }
+    if (hipEventCreate(&ev1) != hipSuccess) { quiet(hipEventDestroy(ev0)); return fail(LTL_ERR_HIP, "hipEventCreate"); }
     float best_ms = 1e30f;
     ltl_tuning_t best_t = s.tuning;
     int32_t rc = LTL_OK;
@@ -681,7 +820,7 @@ int32_t ltl_autotune(ltl_sim_t *sim, int32_t probe_steps, void *scratch, size_t 
     for (int T : Ts)
         for (auto &tl : tiles)
             for (int wv : wavess)
-                for (int pers = 0; pers < 2; ++pers) {
+                for (int pers = 0; pers < 3; ++pers) {
                     ltl_tuning_t t;
                     t.steps_per_launch = T; t.tile_rows = tl[0]; t.tile_cols = tl[1]; t.waves = wv; t.use_graph = 1;
                     t.persistent = pers;
@@ -704,11 +843,13 @@ int32_t ltl_autotune(ltl_sim_t *sim, int32_t probe_steps, void *scratch, size_t 
     }
 done:
     clear_graphs(probe);
+    s.flow_epoch = probe.flow_epoch;   // the probes advanced the shared round counters
+    s.err_seen = probe.err_seen;
     // restore the state the probes started from (also after a failed probe)
     hipError_t re = hipMemcpyAsync(s.buf[s.cur], scratch, bytes, hipMemcpyDeviceToDevice, s.stream);
     if (re == hipSuccess) re = hipStreamSynchronize(s.stream);
-    (void)hipEventDestroy(ev0);
-    (void)hipEventDestroy(ev1);
+    quiet(hipEventDestroy(ev0));
+    quiet(hipEventDestroy(ev1));
     if (rc != LTL_OK) return rc;
     if (re != hipSuccess) return hip_fail(re, "autotune restore");
     clear_graphs(s);
@@ -727,7 +868,15 @@ int32_t ltl_set_boundary(ltl_sim_t *sim, int32_t boundary) {
     if (boundary == LTL_BOUNDARY_PERIODIC && sim->W % 16 != 0)
         return fail(LTL_ERR_UNSUPPORTED, "a periodic grid needs W divisible by 16");
     clear_graphs(*sim);
+    const int old_periodic = sim->periodic;
     sim->periodic = (boundary == LTL_BOUNDARY_PERIODIC) ? 1 : 0;
+    if (sim->user_tuned) {   // a shape the caller chose must still fit this boundary
+        int32_t rc = check_tuning(*sim, sim->tuning);
+        if (rc != LTL_OK) {
+            sim->periodic = old_periodic;
+            return rc;
+        }
+    }
     // a shape taken from the tuning table follows the boundary's own entry
     if (!sim->user_tuned) return initial_tuning(*sim);
     return LTL_OK;
@@ -775,6 +924,7 @@ int32_t ltl_run_noalloc(int32_t H, int32_t W, const ltl_rule_t *rule, int32_t me
     s.periodic = (boundary == LTL_BOUNDARY_PERIODIC) ? 1 : 0;
     if ((rc = initial_tuning(s)) != LTL_OK) return rc;
     s.tuning.use_graph = 0;   // plain launches: a graph instantiation allocates
+    if (s.tuning.persistent == 2) s.tuning.persistent = 0;   // the dataflow form keeps counters in handle memory
 
     HIP_TRY(launch_fill_constants(sp, elem_of(method, rule->R, rule->N), rule->R, kConstBytes - kBandBytes, stream),
             "constants kernel launch");
@@ -789,8 +939,10 @@ int32_t ltl_run_noalloc(int32_t H, int32_t W, const ltl_rule_t *rule, int32_t me
 int32_t ltl_destroy(ltl_sim_t *sim) {
     if (!sim) return LTL_OK;
     clear_graphs(*sim);
-    if (sim->dflag) (void)hipFree(sim->dflag);
-    if (sim->dconst) (void)hipFree(sim->dconst);
+    if (sim->dflag) quiet(hipFree(sim->dflag));
+    if (sim->dconst) quiet(hipFree(sim->dconst));
+    if (sim->dflow) quiet(hipFree(sim->dflow));
+    if (sim->herr) quiet(hipHostFree(sim->herr));
     delete sim;
     return LTL_OK;
 }

@@ -13,7 +13,11 @@ namespace ltl {
 //            window c+1..c+126: the vertical product starts from -c, the counts n - c are
 //            clamped to 127 (all values outside the window land there, outside every range)
 //            and the EPI_BYTE transition runs on them
-enum Epi { EPI_BYTE = 0, EPI_HALF = 1, EPI_DECAY = 2, EPI_WIN = 3 };
+//  EPI_DECAY8 C in 3..8 states, int8 element: every state fits in 3 bits, so the alive bit and
+//            the next state come from per-byte tables indexed by the state (one byte permute
+//            each) instead of the SWAR arithmetic of EPI_DECAY
+enum Epi { EPI_BYTE = 0, EPI_HALF = 1, EPI_DECAY = 2, EPI_WIN = 3, EPI_DECAY8 = 4 };
+__host__ __device__ constexpr bool epi_decays(int epi) { return epi == EPI_DECAY || epi == EPI_DECAY8; }
 
 // Element type of the band-product operands. ELEM_I8W is int8 for radii 17..32: every
 // 16-column half needs 16 + 2r <= 80 columns (a K = 64 and a K = 32 product) and every
@@ -42,6 +46,9 @@ struct RuleConsts {
     uint32_t Tlo, Thi;
     int32_t cwin;          // EPI_WIN: window offset c (the vertical product starts from -c)
     uint32_t Crep;         // EPI_DECAY: C in every byte (a state reaching C wraps to 0)
+    // EPI_DECAY8: next state by state byte k = 0..7 when the range test fails (N0) or holds (N1),
+    // as the 8-byte tables {N0hi:N0lo}, {N1hi:N1lo} of a byte permute
+    uint32_t N0lo, N0hi, N1lo, N1hi;
 };
 
 struct CatParams {
@@ -236,7 +243,7 @@ inline void cat_lds_layout(int elem, int epi, int TH, int TW, int L, int pad, in
     *PS = TW + 2 * L + 16 + pad;
     *lds_tile = roundup(rows * *PS, 1024);
     // int8 Moore and fp16 derive the alive bits from the states as they read them (no second tile)
-    const bool separate = epi == EPI_DECAY && elem != ELEM_I8 && elem != ELEM_F16;
+    const bool separate = epi_decays(epi) && elem != ELEM_I8 && elem != ELEM_F16;
     *PA = cat_cell_bytes(elem) * (TW + 2 * L) + 16 + pad;
     *a_tile = separate ? *lds_tile : 0;
     *lds_total = *lds_tile + (separate ? roundup(rows * *PA, 1024) : 0);
@@ -285,6 +292,25 @@ hipError_t launch_fill_constants(uint8_t *dst, int elem, int r, size_t zero_byte
 // a = init (H x W, init_pitch) with zero columns up to pitch; b = 0 (both H x pitch).
 hipError_t launch_prepare_grids(uint8_t *a, uint8_t *b, const uint8_t *init, size_t init_pitch, int H, int W,
                                 int pitch, hipStream_t s);
+
+// Dataflow form of the single-grid CAT step (tuning.persistent = 2): the arguments of one
+// launch besides CatParams (whose src/dst the kernel sets per round).
+struct FlowParams {
+    uint8_t *buf[2];       // the ping-pong buffers: round k reads buf[(first + k) & 1], writes the other
+    uint32_t *flags;       // per tile: counter of its last finished round (epoch-based, never reset)
+    uint32_t *err;         // number of bounded waits that ran out (never reset; the host compares)
+    uint32_t epoch;        // counter value before the launch's first round
+    int32_t first;         // index of the buffer holding the input
+    int32_t rounds;        // rounds of T = CatParams.T steps, the last one of last_T steps
+    int32_t last_T;
+    int32_t spin_limit;    // polls per wait before it counts as timed out
+    int32_t pad;
+};
+// Tiles the dataflow form can track (flag words of a handle: this many plus the timeout counter).
+constexpr int kFlowMaxTiles = 4096;
+hipError_t launch_cat_flow(const CatParams &p, const FlowParams &f, int elem, int epi, int waves, hipStream_t s);
+// Resident workgroups of the dataflow kernel per compute unit for this shape (0 if it cannot run).
+int cat_flow_occupancy(const CatParams &p, int elem, int epi, int waves);
 
 // Kernel symbol and launch shape, for building graph nodes.
 struct KernelLaunch {

@@ -133,7 +133,7 @@ const char *elem_name(int method, int elem) {
     return elem == ELEM_I8 ? "i8" : elem == ELEM_I8W ? "i8w" : elem == ELEM_I8X ? "i8x" : elem == ELEM_F16 ? "f16" : "f8";
 }
 const char *epi_name(int epi) {
-    return epi == EPI_BYTE ? "byte" : epi == EPI_HALF ? "half" : epi == EPI_DECAY ? "decay" : "win";
+    return epi == EPI_BYTE ? "byte" : epi == EPI_HALF ? "half" : epi_decays(epi) ? "decay" : "win";
 }
 
 struct Entry {

@@ -681,3 +681,25 @@ def test_autotune_small_grids(ltl, shape, boundary, rule):
     got = sim.read().cpu().numpy()
     sim.close()
     assert np.array_equal(got, oracle.run(g0, rule, 7, periodic=(boundary == "periodic"))), best
+
+
+@pytest.mark.parametrize("C", [3, 4, 7, 8, 9, 16, 255])
+def test_decay_state_counts(ltl, C):
+    """Decay rules around the 3-bit boundary of the state-table epilogue (C <= 8 on int8) and
+    above it (C > 8: the SWAR decay epilogue), every method, dead and torus, several launch
+    shapes; initial grids hold every state 0..C-1."""
+    rng = np.random.default_rng(C)
+    g0 = np.where(rng.random((200, 304)) < 0.45, 1, 0).astype(np.uint8)
+    dec = rng.random(g0.shape) < 0.2
+    g0[dec] = rng.integers(2, C, size=int(dec.sum()), dtype=np.uint8)
+    for rule in (inputs.Rule(3, C, 0, 12, 22, 13, 16), inputs.Rule(16, C, 1, 300, 500, 330, 420)):
+        for method in ("cat_i8", "cat_f16", "direct") + (("cat_f8",) if rule.R <= 7 else ()):
+            for tuning in (None, dict(steps_per_launch=2, tile_rows=64, tile_cols=96, waves=8)):
+                if method == "direct" and tuning:
+                    continue
+                run_and_compare(ltl, g0, rule, method, 7, tuning=tuning)
+        sim = ltl.Simulation(gpu_grid(g0), rule, "cat_i8", boundary="periodic")
+        sim.step(5)
+        got = sim.read().cpu().numpy()
+        sim.close()
+        assert np.array_equal(got, oracle.run(g0, rule, 5, periodic=True))
