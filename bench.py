@@ -229,7 +229,7 @@ def oracle_rates(oracle, inputs, grid_fn, rule, steps_all, steps_one, rows_one=N
 
 # ------------------------------------------------------------------------------ legs
 def bench_sweep(args, ltl, inputs, torch, digests, oracle):
-    side, steps, reps = args.sweep_side, 50, 5
+    side, steps, reps = args.sweep_side, 50, args.leg_reps or 5
     g = inputs.bernoulli_grid_torch(side, side, 0.5, 3, device="cuda")
     cells = side * side
     per_r = {}
@@ -237,6 +237,8 @@ def bench_sweep(args, ltl, inputs, torch, digests, oracle):
     radii = [int(x) for x in args.sweep_radii.split(",")] if args.sweep_radii else range(1, args.sweep_rmax + 1)
     methods = args.sweep_methods.split(",") if args.sweep_methods else ("cat_i8", "cat_i8_T1", "cat_f16", "cat_f8",
                                                                           "direct")
+    if args.no_direct:
+        methods = [m for m in methods if m != "direct"]
     for r in radii:
         w = inputs.sweep_workload(r, side)
         ref = golden(digests, w.name, steps) if side == 16384 else None
@@ -245,7 +247,7 @@ def bench_sweep(args, ltl, inputs, torch, digests, oracle):
             m = "cat_i8" if method == "cat_i8_T1" else method
             if (m == "cat_f8" and r > 7) or (m == "cat_f16" and r > 16):
                 continue
-            med, final, tun, _ = sim_rate(ltl, torch, g, w.rule, m, steps, reps if m != "direct" else 3,
+            med, final, tun, _ = sim_rate(ltl, torch, g, w.rule, m, steps, reps if m != "direct" else min(reps, 3),
                                           tuning=t1_shape if method == "cat_i8_T1" else None)
             rate = cells * steps / med
             ent = {"cell_updates_per_s": rate, "ms_per_run": med * 1e3}
@@ -308,7 +310,7 @@ def bench_life(args, ltl, inputs, torch, digests):
 
 def bench_batch(args, ltl, inputs, torch, digests, oracle):
     insts = inputs.batch_instances()
-    steps, reps = 32, 5
+    steps, reps = 32, args.leg_reps or 5
     dev = [inputs.bernoulli_grid_torch(x.H, x.W, 0.5, x.seed, device="cuda") for x in insts]
     rules = [x.rule for x in insts]
     cells = sum(x.H * x.W for x in insts)
@@ -316,12 +318,12 @@ def bench_batch(args, ltl, inputs, torch, digests, oracle):
                        "in [0.2, 0.5] x (2r+1)^2, M1, Bernoulli(0.5), dead halo, 32 steps per run (one hipGraph)",
            "cells": cells, "reps": reps}
     out = {}
-    for method in ("cat_i8", "direct"):
+    for method in ("cat_i8",) if args.no_direct else ("cat_i8", "direct"):
         b = ltl.Batch(dev, rules, method)
         reset = batch_reset(b, dev)
         reset()
         b.step(steps)
-        times = time_reps(b.stream, lambda: b.step(steps), reset, reps if method == "cat_i8" else 2, torch)
+        times = time_reps(b.stream, lambda: b.step(steps), reset, reps if method == "cat_i8" else min(reps, 2), torch)
         med = statistics.median(times)
         out[method] = cells * steps / med
         if method == "cat_i8":
@@ -336,8 +338,9 @@ def bench_batch(args, ltl, inputs, torch, digests, oracle):
     res["value"] = out["cat_i8"]
     res["unit"] = "cell-updates/s"
     res["frac"] = OPS_PER_CELL * out["cat_i8"] / (PEAK_TOPS["cat_i8"] * 1e12)
-    res["direct_stencil_cell_updates_per_s"] = out["direct"]
-    res["cat_over_direct"] = out["cat_i8"] / out["direct"]
+    if "direct" in out:
+        res["direct_stencil_cell_updates_per_s"] = out["direct"]
+        res["cat_over_direct"] = out["cat_i8"] / out["direct"]
     if oracle is not None:
         import numpy as np
 
@@ -368,9 +371,9 @@ def bench_decay(args, ltl, inputs, torch, digests, oracle):
     g = inputs.bernoulli_grid_torch(w.H, w.W, w.p, w.seed, device="cuda")
     cells = w.H * w.W
     res = {"workload": f"decay32768: R16 C8 M0 S300..500 B330..420 N_M, 32768x32768, Bernoulli(0.5) seed {w.seed}, "
-                       f"dead halo, {w.steps} steps per run", "reps": 5}
+                       f"dead halo, {w.steps} steps per run", "reps": args.leg_reps or 5}
     ref = golden(digests, "decay32768", w.steps)
-    med, final, tun, _ = sim_rate(ltl, torch, g, w.rule, "cat_i8", w.steps, 5)
+    med, final, tun, _ = sim_rate(ltl, torch, g, w.rule, "cat_i8", w.steps, args.leg_reps or 5)
     res["value"] = cells * w.steps / med
     res["unit"] = "cell-updates/s"
     res["ms_per_run"] = med * 1e3
@@ -378,11 +381,13 @@ def bench_decay(args, ltl, inputs, torch, digests, oracle):
     res["tuning"] = [tun[k] for k in SHAPE_KEYS]
     res["bit_exact"] = None if ref is None else digest_of(final) == ref
     del final
-    med_d, final_d, _, _ = sim_rate(ltl, torch, g, w.rule, "direct", w.steps, 1, warmup=0)
-    res["direct_stencil_cell_updates_per_s"] = cells * w.steps / med_d
-    res["direct_bit_exact"] = None if ref is None else digest_of(final_d) == ref
-    res["cat_over_direct"] = res["value"] / res["direct_stencil_cell_updates_per_s"]
-    del g, final_d
+    if not args.no_direct:
+        med_d, final_d, _, _ = sim_rate(ltl, torch, g, w.rule, "direct", w.steps, 1, warmup=0)
+        res["direct_stencil_cell_updates_per_s"] = cells * w.steps / med_d
+        res["direct_bit_exact"] = None if ref is None else digest_of(final_d) == ref
+        res["cat_over_direct"] = res["value"] / res["direct_stencil_cell_updates_per_s"]
+        del final_d
+    del g
     if oracle is not None:
         rates, _ = oracle_rates(oracle, inputs, lambda: inputs.bernoulli_grid(1024, w.W, 0.5, w.seed), w.rule, 2, 1,
                                 rows_one=64)
@@ -512,6 +517,10 @@ def main():
     ap.add_argument("--tuning", type=str, default="",
                     help="T,tile_rows,tile_cols,waves[,persistent[,lds_pad]] for the headline (default: the "
                          "library's own pick from its tuning table)")
+    ap.add_argument("--leg-reps", type=int, default=0, metavar="N",
+                    help="timed repetitions of each sweep / batch / decay measurement (default: 5)")
+    ap.add_argument("--no-direct", action="store_true",
+                    help="leave out the direct-stencil comparison runs (profiler runs of the CAT kernels)")
     ap.add_argument("--only", choices=("sweep", "batch", "decay", "life"), default="",
                     help="run this one workload alone (no headline, no CPU baselines) and print its record; "
                          "for profiler runs whose kernel averages must cover that workload only")
@@ -579,11 +588,15 @@ def main():
     log(f"headline: {value:.4e} cell-updates/s, {avg_launch_s * 1e6:.2f} us per launch")
 
     # ---- direct stencil, same workload
-    dsecs, direct_final, _, _ = sim_rate(ltl, torch, g0, w.rule, "direct", w.steps, 3)
-    direct_value = cells * w.steps / dsecs
-    parity = {"cat_vs_direct_equal": bool(torch.equal(cat_final, direct_final)),
-              "cat_vs_oracle_digest": None if ref100 is None else digest_of(cat_final) == ref100}
-    del direct_final
+    if args.no_direct:
+        direct_value = None
+        parity = {"cat_vs_direct_equal": None}
+    else:
+        dsecs, direct_final, _, _ = sim_rate(ltl, torch, g0, w.rule, "direct", w.steps, 3)
+        direct_value = cells * w.steps / dsecs
+        parity = {"cat_vs_direct_equal": bool(torch.equal(cat_final, direct_final))}
+        del direct_final
+    parity["cat_vs_oracle_digest"] = None if ref100 is None else digest_of(cat_final) == ref100
 
     out = {
         "metric": METRIC,
@@ -608,9 +621,11 @@ def main():
             "tuning_source": "--tuning" if args.tuning else "library default (tuning table)",
             "run_ms_min_max": [min(times) * 1e3, max(times) * 1e3],
             "direct_stencil_cell_updates_per_s": direct_value,
-            "direct_stencil_algorithmic_GBs": 2 * direct_value / 1e9,   # one byte read + one written per cell-update
-            "direct_stencil_frac_valu": (2 * w.rule.R + 1) ** 2 * direct_value / VALU_PEAK_OPS,
-            "cat_over_direct": value / direct_value,
+            # one byte read + one written per cell-update
+            "direct_stencil_algorithmic_GBs": None if direct_value is None else 2 * direct_value / 1e9,
+            "direct_stencil_frac_valu": None if direct_value is None else
+            (2 * w.rule.R + 1) ** 2 * direct_value / VALU_PEAK_OPS,
+            "cat_over_direct": None if direct_value is None else value / direct_value,
         },
         "roofline": {
             "bound": "mfma",
