@@ -88,7 +88,11 @@ typedef struct {
                                  tiles), a margin no wider than the tile, and on a torus partial
                                  edge tiles at least that wide; a wait that runs out (after
                                  LTL_FLOW_SPIN_LIMIT polls, default 2^24) makes the next ltl_step
-                                 or ltl_read return LTL_ERR_HIP. Batches take 0. */
+                                 or ltl_read return LTL_ERR_HIP. Batches (CAT methods) take
+                                 0 = one workgroup per work-list entry and launch, or
+                                 1 = resident workgroups (a multiple of 8, at most the
+                                 co-resident slots) that draw entries from per-XCD counters
+                                 in the handle's memory; the batched direct method takes 0. */
     int32_t lds_pad;          /* CAT methods: extra bytes per LDS tile row, a multiple of 16 in 0..128;
                                  it moves the LDS bank each row starts in (the direct method ignores it) */
 } ltl_tuning_t;

@@ -28,7 +28,7 @@ namespace {
 struct BatchLaunchPlan {
     void *dinst = nullptr;       // BatchInst[2][count] (CAT) or DirectBatchInst[2][count], by source arena
     size_t lds = 0;              // dynamic LDS bytes
-    int32_t grid = 0;            // workgroups (one per work-list entry)
+    int32_t grid = 0;            // workgroups (one per work-list entry, or the persistent grid)
 };
 
 }  // namespace
@@ -49,7 +49,8 @@ struct ltl_batch {
     ltl_tuning_t tuning{};
     bool owns_shared = true;         // false for the autotuner's probe, which borrows the below
     uint8_t *dconst = nullptr;       // band tables for r = 1..16 of the method's element type, zero page
-    uint32_t *dflag = nullptr;
+    uint32_t *dflag = nullptr;       // kFlagWords words: [0] initial-state check, [kCounters..] the
+                                     // persistent form's counters (zero between launches)
     BatchItem *ditems = nullptr;     // work list of the tuning
     int32_t nitems = 0;
     std::vector<BatchLaunchPlan> plans;
@@ -59,6 +60,8 @@ struct ltl_batch {
 namespace {
 
 constexpr int kMaxR = 16;
+constexpr int kFlagWords = 32;
+constexpr int kCounters = 16;   // 8 per-XCD next-entry counters and the finished-workgroup counter
 
 size_t batch_const_bytes() { return kMaxR * kBandBytes + 4096; }
 
@@ -168,17 +171,19 @@ int32_t batch_check_tuning(const ltl_batch &b, const ltl_tuning_t &t) {
     if (t.steps_per_launch < 1 || t.steps_per_launch > 64) return fail(LTL_ERR_ARG, "steps_per_launch must be in 1..64");
     if (t.tile_rows < 16 || t.tile_rows > 512 || t.tile_rows % 16) return fail(LTL_ERR_ARG, "tile_rows must be a multiple of 16 in 16..512");
     if (t.tile_cols < 32 || t.tile_cols > 512 || t.tile_cols % 32) return fail(LTL_ERR_ARG, "tile_cols must be a multiple of 32 in 32..512");
-    if (t.persistent) return fail(LTL_ERR_ARG, "batches have no persistent form (persistent must be 0)");
+    if (t.persistent < 0 || t.persistent > 1)
+        return fail(LTL_ERR_ARG, "batches take persistent 0 (one workgroup per entry) or 1 (resident workgroups)");
     if (t.lds_pad < 0 || t.lds_pad > 128 || t.lds_pad % 16) return fail(LTL_ERR_ARG, "lds_pad must be a multiple of 16 in 0..128");
     if (b.method == LTL_DIRECT) {
         if (t.steps_per_launch != 1) return fail(LTL_ERR_ARG, "the direct method takes one step per launch");
+        if (t.persistent) return fail(LTL_ERR_ARG, "the batched direct method has no persistent form");
         return LTL_OK;
     }
     if (t.waves < 1 || t.waves > 8) return fail(LTL_ERR_ARG, "waves must be in 1..8");
     if (!batch_fits(b, t)) return fail(LTL_ERR_ARG, "launch shape has more strip segments than waves for some instance");
     size_t lds = batch_cat_lds(b, t, t.steps_per_launch);
     if (lds > max_lds_bytes()) return fail(LTL_ERR_ARG, "launch shape needs " + std::to_string(lds) + " bytes of LDS");
-    if (b.dconst && cat_batch_occupancy(elem_of(b.method, 16, 'M'), t.waves, lds) < 1)
+    if (b.dconst && cat_batch_occupancy(elem_of(b.method, 16, 'M'), t.waves, lds, t.persistent) < 1)
         return fail(LTL_ERR_ARG, "launch shape does not fit on a compute unit (registers or LDS)");
     return LTL_OK;
 }
@@ -314,9 +319,18 @@ int32_t batch_plan(ltl_batch &b, int T, BatchLaunchPlan **out) {
                     x.p = batch_cat_params(b, i, b.tuning, T, par);
                 }
             pl.lds = batch_cat_lds(b, b.tuning, T);
-            if (cat_batch_occupancy(elem_of(b.method, 16, 'M'), b.tuning.waves, pl.lds) < 1)
-                return fail(LTL_ERR_ARG, "batched launch does not fit on a compute unit");
+            const int occ = cat_batch_occupancy(elem_of(b.method, 16, 'M'), b.tuning.waves, pl.lds, b.tuning.persistent);
+            if (occ < 1) return fail(LTL_ERR_ARG, "batched launch does not fit on a compute unit");
             pl.grid = b.nitems;
+            if (b.tuning.persistent) {   // resident workgroups, a multiple of 8 (one run per XCD)
+                int dev = 0, cus = 0;
+                if (hipGetDevice(&dev) != hipSuccess ||
+                    hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) {
+                    (void)hipGetLastError();
+                    cus = 8;
+                }
+                pl.grid = std::min(roundup(b.nitems, 8), roundup(occ * cus, 8));
+            }
             int32_t rc = upload(h, b.stream, &pl.dinst);
             if (rc != LTL_OK) return rc;
         }
@@ -351,10 +365,11 @@ int32_t batch_launch(ltl_batch &b, int T, int from, BatchLaunch *l) {
         l->dp.items = b.ditems;
         l->dp.nitems = b.nitems;
     } else {
-        l->func = cat_batch_func(elem_of(b.method, 16, 'M'));
+        l->func = cat_batch_func(elem_of(b.method, 16, 'M'), b.tuning.persistent);
         l->block = dim3((unsigned)(64 * b.tuning.waves), 1, 1);
         l->bp.inst = (const BatchInst *)pl->dinst + from * b.count;
         l->bp.items = b.ditems;
+        l->bp.counters = b.dflag + kCounters;
         l->bp.nitems = b.nitems;
     }
     if (l->lds > 65536)
@@ -549,14 +564,16 @@ int32_t batch_autotune(ltl_batch &b, int probe_steps, void *scratch, size_t scra
     const int wavess[] = {0, 8};
     for (int T : Ts)
         for (auto &tl : tiles)
-            for (int wv : wavess) {
-                ltl_tuning_t t;
-                std::memset(&t, 0, sizeof(t));
-                t.steps_per_launch = T; t.tile_rows = tl[0]; t.tile_cols = tl[1]; t.waves = wv; t.use_graph = 1;
-                float ms;
-                if ((rc = time_one(t, &ms)) != LTL_OK) goto done;
-                if (ms >= 0 && ms < best_ms) { best_ms = ms; best_t = batch_fill_tuning(probe, t); }
-            }
+            for (int wv : wavess)
+                for (int pers = 0; pers < 2; ++pers) {
+                    ltl_tuning_t t;
+                    std::memset(&t, 0, sizeof(t));
+                    t.steps_per_launch = T; t.tile_rows = tl[0]; t.tile_cols = tl[1]; t.waves = wv; t.use_graph = 1;
+                    t.persistent = pers;
+                    float ms;
+                    if ((rc = time_one(t, &ms)) != LTL_OK) goto done;
+                    if (ms >= 0 && ms < best_ms) { best_ms = ms; best_t = batch_fill_tuning(probe, t); }
+                }
     for (int pad : {16, 32, 64}) {
         ltl_tuning_t t = best_t;
         t.lds_pad = pad;
@@ -656,7 +673,7 @@ int32_t ltl_batch_create(ltl_batch_t **out, int32_t count, const int32_t *H, con
     hipError_t e;
     const size_t cbytes = batch_const_bytes();
     if ((e = hipMalloc(&b->dconst, cbytes)) != hipSuccess) { b->dconst = nullptr; return bail(hip_fail(e, "hipMalloc")); }
-    if ((e = hipMalloc(&b->dflag, sizeof(uint32_t))) != hipSuccess) { b->dflag = nullptr; return bail(hip_fail(e, "hipMalloc")); }
+    if ((e = hipMalloc(&b->dflag, kFlagWords * sizeof(uint32_t))) != hipSuccess) { b->dflag = nullptr; return bail(hip_fail(e, "hipMalloc")); }
     {
         std::vector<uint8_t> hc(cbytes, 0);
         if (method != LTL_DIRECT)
@@ -666,7 +683,7 @@ int32_t ltl_batch_create(ltl_batch_t **out, int32_t count, const int32_t *H, con
             return bail(hip_fail(e, "hipMemcpyAsync"));
         if ((e = hipStreamSynchronize(stream)) != hipSuccess) return bail(hip_fail(e, "hipStreamSynchronize"));
     }
-    if ((e = hipMemsetAsync(b->dflag, 0, sizeof(uint32_t), stream)) != hipSuccess) return bail(hip_fail(e, "hipMemsetAsync"));
+    if ((e = hipMemsetAsync(b->dflag, 0, kFlagWords * sizeof(uint32_t), stream)) != hipSuccess) return bail(hip_fail(e, "hipMemsetAsync"));
     for (int i = 0; i < count; ++i)
         if ((e = launch_validate((const uint8_t *)init[i], H[i], W[i], init_pitch[i], b->rc[i].C, b->dflag, stream)) != hipSuccess)
             return bail(hip_fail(e, "validate launch"));

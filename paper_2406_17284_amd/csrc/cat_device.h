@@ -681,22 +681,96 @@ __device__ __forceinline__ void cat_steps(const CatParams &p, uint8_t *Qt, uint8
     }
 }
 
+// One 16-byte global->LDS DMA per lane into the KiB of LDS at `chunk`: from the 64-bit address
+// g, or (second form) from the grid base `base` (scalar) plus a 32-bit byte offset.
+//
+// The loads are issued from inline assembly: the compiler cannot see which LDS bytes an LDS-DMA
+// writes, so for its own builtin it would make every later LDS access wait for all outstanding
+// vector-memory operations. The caller waits (vmcnt(0) + barrier) before the buffer is read. m0
+// (the DMA's LDS address) is a register the compiler reserves; no other code of these kernels
+// uses it (checked in the generated ISA), so clobbering it here is safe and the corresponding
+// warning is silenced for these statements only.
+__device__ __forceinline__ void lds_dma16(uint8_t *chunk, const uint8_t *g) {
+    const uint32_t lds_addr = (uint32_t)(uintptr_t)chunk;
+#pragma clang diagnostic push
+#pragma clang diagnostic ignored "-Winline-asm"
+    asm volatile("s_mov_b32 m0, %0\n\tglobal_load_lds_dwordx4 %1, off"
+                 :
+                 : "s"(__builtin_amdgcn_readfirstlane(lds_addr)), "v"(g)
+                 : "memory", "m0");
+#pragma clang diagnostic pop
+}
+__device__ __forceinline__ void lds_dma16(uint8_t *chunk, const uint8_t *base, uint32_t off) {
+    const uint32_t lds_addr = (uint32_t)(uintptr_t)chunk;
+    // the base is the same in every lane (a tile's grid); read through the first lane it sits in
+    // scalar registers also where the compiler cannot prove that (a descriptor read per entry)
+    // (the builtin returns int: each half goes back through uint32_t, so the low half is not
+    // sign-extended into the high one)
+    const uint64_t b = (uint64_t)(uintptr_t)base;
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)b);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(b >> 32));
+    const uint64_t sb = ((uint64_t)hi << 32) | (uint64_t)lo;
+#pragma clang diagnostic push
+#pragma clang diagnostic ignored "-Winline-asm"
+    asm volatile("s_mov_b32 m0, %0\n\tglobal_load_lds_dwordx4 %1, %2"
+                 :
+                 : "s"(__builtin_amdgcn_readfirstlane(lds_addr)), "v"(off), "s"(sb)
+                 : "memory", "m0");
+#pragma clang diagnostic pop
+}
+
+// Row and column of byte offset o of a buffer with rows of PS bytes: a reciprocal estimate,
+// corrected by one either way (exact for the offsets of a tile buffer).
+__device__ __forceinline__ void row_col(int o, int PS, float inv_ps, int *row, int *col) {
+    int r = (int)((float)o * inv_ps);
+    int c = o - r * PS;
+    if (c < 0) { r -= 1; c += PS; }
+    if (c >= PS) { r += 1; c -= PS; }
+    *row = r;
+    *col = c;
+}
+
 // Stream the (TH + 2L) x PS window of the tile at (gi0, gj0) into LDS at `buf` with direct
 // global->LDS loads: wave w moves KiB chunks w, w + nwaves, ...; lane l of a chunk carries
 // the 16 bytes at buffer offset 1024 c + 16 l. Cells outside the grid come from the zero page
-// (dead halo) or from the opposite edge (torus).
+// (dead halo) or from the opposite edge (torus); so do the bytes past the window's last row
+// that the KiB rounding of the buffer adds. A lane's (row, column) is computed once; each
+// later chunk of its wave lies nwaves KiB further on (dr rows and dc columns, one more row when
+// the column passes PS). When the whole window lies inside the grid (most tiles), the lane
+// advances a 32-bit offset from the grid base instead and tests no bounds.
 __device__ __forceinline__ void issue_tile_load(const CatParams &p, int gi0, int gj0, uint8_t *buf, int wave,
                                                 int nwaves, int lane, float inv_ps) {
     const int rows = p.TH + 2 * p.L;
+    const int PS = p.PS;
     const int nchunks = p.lds_tile >> 10;
+    const int gr0 = gi0 - p.L, gc0 = gj0 - p.L;
+    int lr, lc, dr, dc;
+    row_col((wave << 10) + (lane << 4), PS, inv_ps, &lr, &lc);
+    row_col(nwaves << 10, PS, inv_ps, &dr, &dc);
+    const bool inside = !p.periodic && gr0 >= 0 && gc0 >= 0 && gr0 + rows <= p.H && gc0 + PS <= p.pitch;
+    if (inside) {
+        uint32_t off = (uint32_t)((gr0 + lr) * p.pitch + gc0 + lc);
+        const uint32_t adv = (uint32_t)(dr * p.pitch + dc);
+        const uint32_t wrap = (uint32_t)(p.pitch - PS);
+        const int window = rows * PS;   // bytes of the window; the last chunk may run past it
+        for (int c = wave; c < nchunks; c += nwaves) {
+            uint8_t *chunk = buf + (c << 10);
+            if (c == nchunks - 1)
+                lds_dma16(chunk, ((c << 10) + (lane << 4) < window) ? p.src + off : p.zero);
+            else
+                lds_dma16(chunk, p.src, off);
+            off += adv;
+            lc += dc;
+            if (lc >= PS) {
+                lc -= PS;
+                off += wrap;
+            }
+        }
+        return;
+    }
     for (int c = wave; c < nchunks; c += nwaves) {
-        const int o = (c << 10) + (lane << 4);
-        int lr = (int)((float)o * inv_ps);
-        int lc = o - lr * p.PS;
-        if (lc < 0) { lr -= 1; lc += p.PS; }
-        if (lc >= p.PS) { lr += 1; lc -= p.PS; }
-        const int gr = gi0 - p.L + lr;
-        const int gc = gj0 - p.L + lc;
+        const int gr = gr0 + lr;
+        const int gc = gc0 + lc;
         const uint8_t *g = p.zero;
         if (p.periodic) {
             // torus: wrap both coordinates (W is a multiple of 16, so a 16-byte vector at a
@@ -710,20 +784,13 @@ __device__ __forceinline__ void issue_tile_load(const CatParams &p, int gi0, int
         } else if (lr < rows && (unsigned)gr < (unsigned)p.H && (unsigned)gc < (unsigned)p.pitch) {
             g = p.src + (size_t)gr * p.pitch + gc;
         }
-        // The load is issued from inline assembly: the compiler cannot see which LDS bytes an
-        // LDS-DMA writes, so for its own builtin it would make every later LDS access wait for
-        // all outstanding vector-memory operations. The caller waits (vmcnt(0) + barrier) before
-        // the buffer is read. m0 (the DMA's LDS address) is a register the compiler reserves; no
-        // other code of these kernels uses it (checked in the generated ISA), so clobbering it
-        // here is safe and the corresponding warning is silenced for this statement only.
-        const uint32_t lds_addr = (uint32_t)(uintptr_t)(buf + (c << 10));
-#pragma clang diagnostic push
-#pragma clang diagnostic ignored "-Winline-asm"
-        asm volatile("s_mov_b32 m0, %0\n\tglobal_load_lds_dwordx4 %1, off"
-                     :
-                     : "s"(__builtin_amdgcn_readfirstlane(lds_addr)), "v"(g)
-                     : "memory", "m0");
-#pragma clang diagnostic pop
+        lds_dma16(buf + (c << 10), g);
+        lr += dr;
+        lc += dc;
+        if (lc >= PS) {
+            lc -= PS;
+            lr += 1;
+        }
     }
 }
 
@@ -781,18 +848,28 @@ __device__ __forceinline__ void tile_steps(const CatParams &p, int gi0, int gj0,
         cat_steps<ELEM, EPI, true>(p, Qt, At, gi0, gj0, wave, lane, bd, cd);
 }
 
+// Work a caller overlaps with a tile's window load: issue() runs after the loads are issued,
+// land() after they (and whatever issue() started) completed, before the barrier that opens
+// the tile. The default does nothing.
+struct NoSideLoad {
+    __device__ __forceinline__ void issue(int) {}
+    __device__ __forceinline__ void land(int) {}
+};
+
 // One tile: load the window with direct LDS loads, then the alive map and T steps in place.
 // Ends without a barrier: a caller that reuses the LDS for another tile synchronizes first.
-template <int ELEM, int EPI>
+template <int ELEM, int EPI, class Side = NoSideLoad>
 __device__ __forceinline__ void cat_tile(const CatParams &p, int tile, uint8_t *lds, int tid, int lane, int wave,
-                                         int nwaves, const Codec &cd) {
+                                         int nwaves, const Codec &cd, Side &&side = Side()) {
     const int gi0 = (tile / p.ntx) * p.TH;
     const int gj0 = (tile % p.ntx) * p.TW;
     uint8_t *Qt = lds;                 // loaded window: states, one byte per cell
     uint8_t *At = lds + p.a_tile;      // alive map in the element encoding (== Qt when shared)
-    issue_tile_load(p, gi0, gj0, Qt, wave, nwaves, lane, 1.0f / (float)p.PS);
+    issue_tile_load(p, gi0, gj0, Qt, wave, nwaves, lane, __builtin_amdgcn_rcpf((float)p.PS));
     const Bands bd = load_bands<ELEM>(p, lane, cd);
+    side.issue(tid);
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    side.land(tid);
     __syncthreads();
     tile_steps<ELEM, EPI>(p, gi0, gj0, Qt, At, tid, lane, wave, nwaves, bd, cd);
 }

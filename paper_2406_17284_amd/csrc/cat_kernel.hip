@@ -45,7 +45,7 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2))) c
     const int chunk = (ntiles + 7) >> 3;
     const int t_hi = min(ntiles, ((int)blockIdx.x & 7) * chunk + chunk);
     int tile = ((int)blockIdx.x & 7) * chunk + ((int)blockIdx.x >> 3);
-    const float inv_ps = 1.0f / (float)p.PS;
+    const float inv_ps = __builtin_amdgcn_rcpf((float)p.PS);   // estimate: row_col corrects it
     const Codec cd = make_codec();
     const Bands bd = load_bands<ELEM>(p, lane, cd);
     const uint32_t bufsz = (uint32_t)p.lds_total;  // one buffer: state tile (+ alive tile)

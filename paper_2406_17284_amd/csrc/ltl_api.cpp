@@ -813,9 +813,10 @@ int32_t ltl_autotune(ltl_sim_t *sim, int32_t probe_steps, void *scratch, size_t 
         *ms_out = ms / (float)n;
         return LTL_OK;
     };
-    const int Ts[] = {1, 2, 3, 4, 5, 6, 8};
+    const int Ts[] = {1, 2, 3, 4, 5, 6, 8, 12, 16};
     const int tiles[][2] = {{64, 64}, {96, 96}, {128, 128}, {128, 192}, {160, 160}, {192, 128}, {192, 192},
-                            {192, 224}, {128, 224}, {160, 224}, {176, 224}, {224, 224}, {64, 128}, {128, 96}};
+                            {192, 224}, {128, 224}, {160, 224}, {176, 224}, {224, 224}, {64, 128}, {128, 96},
+                            {32, 64}};
     const int wavess[] = {0, 8};  // 0: fewest waves that fit every step
     for (int T : Ts)
         for (auto &tl : tiles)

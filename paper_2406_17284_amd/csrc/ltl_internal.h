@@ -264,7 +264,9 @@ struct BatchItem {
 
 struct BatchParams {
     const BatchInst *inst;     // per instance, for the arena this launch reads
-    const BatchItem *items;    // workgroup k takes items[k]
+    const BatchItem *items;    // workgroup k takes items[k] (and, persistent, the entries it draws)
+    uint32_t *counters;        // persistent form: 8 next-entry counters (one per XCD), then the
+                               // finished-workgroup counter; all zero between launches
     int32_t nitems;
     int32_t pad;
 };
@@ -324,10 +326,11 @@ KernelLaunch cat_launch_shape(const CatParams &p, int elem, int epi, int waves, 
 int cat_occupancy(const CatParams &p, int elem, int epi, int waves, int persistent);
 KernelLaunch direct_launch_shape(const DirectParams &p);
 size_t cat_lds_bytes(const CatParams &p, int elem, int epi, int persistent);
-// Batched launches. cat_batch_func: the batch kernel of an element type, launched with one
-// workgroup of 64 * waves threads per work-list entry and the batch's largest dynamic LDS.
-const void *cat_batch_func(int elem);
-int cat_batch_occupancy(int elem, int waves, size_t lds);
+// Batched launches. cat_batch_func: the batch kernel of an element type, launched with
+// workgroups of 64 * waves threads and the batch's largest dynamic LDS: one workgroup per
+// work-list entry, or (persistent = 1) resident workgroups that draw entries from a counter.
+const void *cat_batch_func(int elem, int persistent);
+int cat_batch_occupancy(int elem, int waves, size_t lds, int persistent);
 const void *direct_batch_func();
 int direct_tile_rows();
 int direct_tile_cols();

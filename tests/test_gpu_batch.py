@@ -147,6 +147,8 @@ def draw_batch_case(k):
                       use_graph=int(rng.integers(0, 2)))
     steps = int(rng.integers(1, 12))
     cut = int(rng.integers(0, steps + 1))
+    if tuning is not None:   # drawn last, so the cases' other draws are those of the per-entry form
+        tuning["persistent"] = int(rng.integers(0, 2))
     return method, grids, rules, tuning, [cut, steps - cut]
 
 
@@ -354,3 +356,65 @@ def test_batch_mixes_every_epilogue(ltl):
             refs = [oracle.run(ref, rule, 1 if tuning is None else 3) for ref, rule in zip(refs, rules)]
             check_batch(batch, refs, f"tuning={tuning} step {t + 1}")
         batch.close()
+
+
+# ------------------------------------------------------------------ the persistent form
+@pytest.mark.parametrize("method", CAT_METHODS)
+@pytest.mark.parametrize("tuning", [
+    dict(steps_per_launch=1, tile_rows=16, tile_cols=32, waves=8),
+    dict(steps_per_launch=3, tile_rows=64, tile_cols=64, waves=8),
+    dict(steps_per_launch=2, tile_rows=32, tile_cols=64),
+], ids=lambda t: "T{steps_per_launch}_{tile_rows}x{tile_cols}".format(**t))
+def test_batch_persistent_form(ltl, method, tuning):
+    """Resident workgroups drawing work-list entries from per-XCD counters: a batch with more
+    entries than resident workgroups (a 1024 x 1024 instance in small tiles next to the small
+    mixed ones), graph and eager launches, every instance against the oracle after each call."""
+    grids, rules = small_batch(8, max_r=7 if method == "cat_f8" else 12)
+    grids.append(inputs.bernoulli_grid(1024, 1024, 0.5, seed=808))
+    rules.append(inputs.Rule(2, 0, 1, 5, 12, 6, 9))
+    for use_graph in (1, 0):
+        batch = ltl.Batch([gpu_grid(g) for g in grids], rules, method,
+                          tuning=dict(tuning, persistent=1, use_graph=use_graph))
+        assert batch.tuning()["persistent"] == 1
+        refs = [g.copy() for g in grids]
+        for n in (5, 1, 4):
+            batch.step(n)
+            refs = [oracle.run(x, r, n) for x, r in zip(refs, rules)]
+            check_batch(batch, refs, f"{method} persistent {tuning} graph={use_graph} after {n}")
+        batch.close()
+
+
+def test_batch_persistent_graph_replays(ltl):
+    """Each launch resets the entry counters for the next: replays of one cached graph, with
+    eager work and synchronizations between them, equal the per-entry form every time."""
+    grids, rules = small_batch(10, max_r=9)
+    grids.append(inputs.bernoulli_grid(700, 900, 0.5, seed=909))
+    rules.append(inputs.BOSCO_M1)
+    shape = dict(steps_per_launch=2, tile_rows=32, tile_cols=64, waves=8, use_graph=1)
+    pers = ltl.Batch([gpu_grid(g) for g in grids], rules, "cat_i8", tuning=dict(shape, persistent=1))
+    base = ltl.Batch([gpu_grid(g) for g in grids], rules, "cat_i8", tuning=dict(shape, persistent=0))
+    for k in range(4):
+        pers.step(6)
+        base.step(6)
+        torch.cuda.synchronize()
+        for i in range(len(grids)):
+            assert torch.equal(pers.read(i), base.read(i)), f"replay {k} instance {i}"
+        _ = pers.read(0).sum().item()
+    check_batch(pers, [oracle.run(g, r, 24) for g, r in zip(grids, rules)], "persistent replays")
+    pers.close()
+    base.close()
+
+
+def test_batch_persistent_refusals(ltl):
+    grids, rules = small_batch(11, max_r=4)
+    batch = ltl.Batch([gpu_grid(g) for g in grids], rules, "cat_i8")
+    for bad in (2, -1):
+        with pytest.raises(ltl.LtlError) as e:
+            batch.set_tuning(steps_per_launch=1, tile_rows=64, tile_cols=64, persistent=bad)
+        assert e.value.code == ltl.LTL_ERR_ARG
+    batch.close()
+    direct = ltl.Batch([gpu_grid(g) for g in grids], rules, "direct")
+    with pytest.raises(ltl.LtlError) as e:
+        direct.set_tuning(steps_per_launch=1, persistent=1)
+    assert e.value.code == ltl.LTL_ERR_ARG
+    direct.close()

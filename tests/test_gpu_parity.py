@@ -586,12 +586,17 @@ def test_persistent_tiny_grids(ltl):
 
 
 def test_persistent_refused_where_absent(ltl):
+    """The direct method has no persistent form; batches have no dataflow form (persistent = 2)
+    and the batched direct method no persistent one."""
     g = gpu_grid(np.zeros((64, 64), dtype=np.uint8))
     with pytest.raises(ltl.LtlError) as e:
         ltl.Simulation(g, inputs.LIFE, "direct", tuning=dict(steps_per_launch=1, persistent=1))
     assert e.value.code == ltl.LTL_ERR_ARG
     with pytest.raises(ltl.LtlError) as e:
-        ltl.Batch([g, g], [inputs.LIFE, inputs.LIFE], "cat_i8", tuning=dict(persistent=1))
+        ltl.Batch([g, g], [inputs.LIFE, inputs.LIFE], "cat_i8", tuning=dict(persistent=2))
+    assert e.value.code == ltl.LTL_ERR_ARG
+    with pytest.raises(ltl.LtlError) as e:
+        ltl.Batch([g, g], [inputs.LIFE, inputs.LIFE], "direct", tuning=dict(persistent=1))
     assert e.value.code == ltl.LTL_ERR_ARG
 
 
