@@ -8,7 +8,8 @@ PATH, so PATH ends up holding one entry per workload class (method, element type
 class, radius, size bucket, boundary, batched) in the table format ``ltl.h`` describes. Copy
 it to ``paper_2406_17284_amd/tuning.json`` to ship it. Workloads: Life 256^2, Bosco R5 4096^2
 (dead and periodic), the radius sweep on 16384^2 for r = 1..16 (int8, fp16; fp8 for r <= 7),
-the C = 8 R16 decay rule on 32768^2 and the 512-instance batch.
+the sweep rules at r = 17, 20, 24, 28, 32 on 16384^2 (int8, the wide element), the C = 8 R16
+decay rule on 32768^2 and the 512-instance batch.
 """
 from __future__ import annotations
 
@@ -25,7 +26,8 @@ if ROOT not in sys.path:
 def main(argv=None) -> None:
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", required=True)
-    ap.add_argument("--only", default="", help="comma-separated subset: life, bosco, periodic, sweep, decay, batch")
+    ap.add_argument("--only", default="",
+                    help="comma-separated subset: life, bosco, periodic, sweep, wide, decay, batch")
     a = ap.parse_args(argv)
     os.environ["LTL_TUNE_CACHE"] = os.path.abspath(a.out)
     only = set(x for x in a.only.split(",") if x)
@@ -65,6 +67,12 @@ def main(argv=None) -> None:
                 if method == "cat_f8" and r > 7:
                     continue
                 tune_one(w.name, g, w.rule, method, 10)
+        del g
+    if not only or "wide" in only:
+        g = inputs.bernoulli_grid_torch(16384, 16384, 0.5, 3, device="cuda")
+        for r in (17, 20, 24, 28, 32):
+            w = inputs.sweep_workload(r)
+            tune_one(w.name, g, w.rule, "cat_i8", 6)
         del g
     if not only or "decay" in only:
         w = inputs.WORKLOADS["decay32768"]
