@@ -51,9 +51,6 @@ typedef int32_t v16i __attribute__((ext_vector_type(16)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef _Float16 v8h __attribute__((ext_vector_type(8)));
 typedef uint16_t us2 __attribute__((ext_vector_type(2)));
-// global-memory dword (explicit address space: global_store_*, not flat_* which would also
-// count against the LDS wait counter)
-typedef __attribute__((address_space(1))) uint32_t gdword;
 
 // Low bytes of the four int32 lanes of d packed into one dword (three byte permutes).
 __device__ __forceinline__ uint32_t pack_bytes(v4i d) {
@@ -514,13 +511,13 @@ struct LaneOff {
     uint32_t q, a;   // block-row-0 offset of the lane's first cell of half a (half b: +16 cells)
 };
 
-// Phase B of one item: vertical band products, transition, store (in place in LDS for an
-// intermediate step, to the output grid on the last step of the launch). Software-pipelined in
-// pairs of output blocks: the MFMAs and centre-state reads of the next pair are issued before
-// the VALU transition of this pair, so their latencies overlap it.
-template <int ELEM, int EPI, bool MASKED, bool LAST>
+// Phase B of one item: vertical band products, transition, in-place store of the new states in
+// LDS (the tile goes to the output grid after the last step, with 16-byte stores). Software-
+// pipelined in pairs of output blocks: the MFMAs and centre-state reads of the next pair are
+// issued before the VALU transition of this pair, so their latencies overlap it.
+template <int ELEM, int EPI, bool MASKED>
 __device__ __forceinline__ void phase_b(const CatParams &p, uint8_t *Qt, uint8_t *At, LaneOff lo, int rb0, int count,
-                                        int gr0, uint32_t goff0, int gca, uint32_t cma, uint32_t cmb, const Bands &bd,
+                                        int gr0, uint32_t cma, uint32_t cmb, const Bands &bd,
                                         const Codec &cd, const v16i &Ha, const v16i &Hb, const v16i &La,
                                         const v16i &Lb) {
     constexpr int CELL = ElemT<ELEM>::CELL;
@@ -556,13 +553,7 @@ __device__ __forceinline__ void phase_b(const CatParams &p, uint8_t *Qt, uint8_t
         uint32_t ala, alb;                                                                         \
         const uint32_t na = transition4<EPI>(ca[(M) & 3], sa[(M) & 3], rowm & cma, p.rc, &ala);    \
         const uint32_t nb = transition4<EPI>(cb[(M) & 3], sb[(M) & 3], rowm & cmb, p.rc, &alb);    \
-        if constexpr (LAST) {                                                                      \
-            const uint32_t go = goff0 + (uint32_t)(16 * (M)) * (uint32_t)p.pitch;                  \
-            if (rowin) {                                                                           \
-                if (!MASKED || (unsigned)gca < (unsigned)p.store_w) *(gdword *)(p.dst + go) = na;  \
-                if (!MASKED || (unsigned)(gca + 16) < (unsigned)p.store_w) *(gdword *)(p.dst + go + 16) = nb; \
-            }                                                                                      \
-        } else {                                                                                   \
+        {                                                                                          \
             const uint32_t qo = lo.q + (uint32_t)(16 * (rb0 + (M))) * PS;                          \
             const uint32_t ao = lo.a + (uint32_t)(16 * (rb0 + (M))) * PA;                          \
             if constexpr (epi_decays(EPI)) {                                                       \
@@ -613,7 +604,7 @@ __device__ __forceinline__ void phase_b(const CatParams &p, uint8_t *Qt, uint8_t
 #undef CAT_ISSUE
 }
 
-// T steps of one tile, in place in LDS (the last step writes the output grid).
+// T steps of one tile, in place in LDS; ends with a barrier after the last step's writes.
 template <int ELEM, int EPI, bool MASKED>
 __device__ __forceinline__ void cat_steps(const CatParams &p, uint8_t *Qt, uint8_t *At, int gi0, int gj0, int wave,
                                           int lane, const Bands &bd, const Codec &cd) {
@@ -623,7 +614,6 @@ __device__ __forceinline__ void cat_steps(const CatParams &p, uint8_t *Qt, uint8
     const uint32_t PS = (uint32_t)p.PS, PA = (uint32_t)p.PA;
     const int L = p.L;
     for (int t = 1; t <= p.T; ++t) {
-        const bool last = (t == p.T);
         const StepGeom g = step_geom<MAXC>(p, t);
         const int items = g.nstrips * g.nseg;
         int j0 = 0, rb0 = 0, count = 0;
@@ -657,7 +647,7 @@ __device__ __forceinline__ void cat_steps(const CatParams &p, uint8_t *Qt, uint8
             phase_a<ELEM, !((ELEM == ELEM_I8 || ELEM == ELEM_F16) && epi_decays(EPI)) ? 0 : EPI == EPI_DECAY8 ? 2 : 1>(
                 At, a_off, a_off2, PA, rb0, count,
                                                                                    bd, Ha, Hb, La, Lb);
-        if (!last) __syncthreads();   // every read of the old states precedes any in-place write
+        __syncthreads();   // every read of the old states precedes any in-place write
         if (count > 0) {
             const int gca = gj0 + j0 + 4 * lg;
             uint32_t cma = 0xFFFFFFFFu, cmb = 0xFFFFFFFFu;
@@ -668,16 +658,9 @@ __device__ __forceinline__ void cat_steps(const CatParams &p, uint8_t *Qt, uint8
                 }
             }
             const int gr0 = gi0 + 16 * rb0 + li;
-            // modular 32-bit offset: rows outside the grid (never stored) may wrap
-            const uint32_t goff0 = (uint32_t)gr0 * (uint32_t)p.pitch + (uint32_t)gca;
-            if (last)
-                phase_b<ELEM, EPI, MASKED, true>(p, Qt, At, lo, rb0, count, gr0, goff0, gca, cma, cmb, bd, cd, Ha, Hb,
-                                                 La, Lb);
-            else
-                phase_b<ELEM, EPI, MASKED, false>(p, Qt, At, lo, rb0, count, gr0, goff0, gca, cma, cmb, bd, cd, Ha, Hb,
-                                                  La, Lb);
+            phase_b<ELEM, EPI, MASKED>(p, Qt, At, lo, rb0, count, gr0, cma, cmb, bd, cd, Ha, Hb, La, Lb);
         }
-        if (!last) __syncthreads();   // new states complete before the next step reads them
+        __syncthreads();   // new states complete before the next step (or the copy-out) reads them
     }
 }
 
@@ -810,9 +793,46 @@ __device__ __forceinline__ Bands load_bands(const CatParams &p, int lane, const 
     return bd;
 }
 
+// Copy the tile's final states from LDS to the output grid with 16-byte stores: the rows inside
+// the grid and the columns below store_w (a dead halo's padding columns, which the steps kept
+// at 0, included). Consecutive threads take consecutive vectors of a row, so a wave writes whole
+// row segments instead of the 16-byte pieces of 16 rows a phase-B lane holds. fp8 two-state
+// tiles hold the fp8 encoding of the alive bit in place of the state and are decoded here.
+template <int ELEM, int EPI>
+__device__ __forceinline__ void store_tile(const CatParams &p, const uint8_t *Qt, int gi0, int gj0, int tid,
+                                           int nthreads, const Codec &cd) {
+    const int vpr = p.TW >> 4;                                   // 16-byte vectors per tile row
+    const int rows = min(p.TH, p.H - gi0);
+    const int vcols = min(p.TW, p.store_w - gj0) >> 4;           // store_w is a multiple of 16
+    const int n = rows * vpr;
+    // this thread's first vector and the per-iteration advance, as (row, vector) pairs
+    const int di = nthreads / vpr, dc = nthreads - di * vpr;
+    int i = tid / vpr;
+    int c = tid - i * vpr;
+    const uint8_t *src = Qt + p.L * p.PS + p.L;
+    for (int v = tid; v < n; v += nthreads) {
+        if (c < vcols) {
+            v4i x = *reinterpret_cast<const v4i *>(src + i * p.PS + 16 * c);
+            if constexpr (ELEM == ELEM_F8 && !epi_decays(EPI)) {
+#pragma unroll
+                for (int k = 0; k < 4; ++k) x[k] = (int32_t)dec8((uint32_t)x[k], cd);
+            }
+            // explicit global address space: global_store, not a flat store, which would also
+            // count against the LDS wait counter
+            *(__attribute__((address_space(1))) v4i *)(p.dst + (size_t)(gi0 + i) * p.pitch + gj0 + 16 * c) = x;
+        }
+        i += di;
+        c += dc;
+        if (c >= vpr) {
+            c -= vpr;
+            i += 1;
+        }
+    }
+}
+
 // The window of the tile at (gi0, gj0) is in LDS at Qt (visible to every wave): derive the
-// alive map in the element encoding at At, then run T steps in place (the last one writes the
-// output grid). Ends without a barrier.
+// alive map in the element encoding at At, run T steps in place, then copy the tile to the
+// output grid. Ends without a barrier.
 template <int ELEM, int EPI>
 __device__ __forceinline__ void tile_steps(const CatParams &p, int gi0, int gj0, uint8_t *Qt, uint8_t *At, int tid,
                                            int lane, int wave, int nwaves, const Bands &bd, const Codec &cd) {
@@ -846,6 +866,7 @@ __device__ __forceinline__ void tile_steps(const CatParams &p, int gi0, int gj0,
         cat_steps<ELEM, EPI, false>(p, Qt, At, gi0, gj0, wave, lane, bd, cd);
     else
         cat_steps<ELEM, EPI, true>(p, Qt, At, gi0, gj0, wave, lane, bd, cd);
+    store_tile<ELEM, EPI>(p, Qt, gi0, gj0, tid, 64 * nwaves, cd);
 }
 
 // Work a caller overlaps with a tile's window load: issue() runs after the loads are issued,

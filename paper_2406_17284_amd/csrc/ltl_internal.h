@@ -69,7 +69,7 @@ struct CatParams {
     int32_t lds_total;       // dynamic LDS bytes of the launch
     int32_t ntx, nty;        // tiles across / down the grid
     int32_t periodic;        // 1: the grid is a torus (W % 16 == 0); 0: dead ghost halo
-    int32_t store_w;         // columns the last step stores: W (torus) or pitch (dead halo, zero padding)
+    int32_t store_w;         // columns the copy-out stores: W (torus) or pitch (dead halo, zero padding)
     RuleConsts rc;
 };
 
