@@ -381,7 +381,18 @@ def bench_decay(args, ltl, inputs, torch, digests, oracle):
     res["frac"] = OPS_PER_CELL * res["value"] / (PEAK_TOPS["cat_i8"] * 1e12)
     res["tuning"] = [tun[k] for k in SHAPE_KEYS]
     res["bit_exact"] = None if ref is None else digest_of(final) == ref
+    res["alive_after_run"] = int((final == 1).sum().item())
     del final
+    # At density 0.5 nearly every box count exceeds both ranges: the grid decays to all-dead
+    # within about 8 steps. The kernel's work does not depend on the cells, but the same rule is
+    # also timed at density 0.42, where births, survivals and decay go on for all 20 steps.
+    g42 = inputs.bernoulli_grid_torch(w.H, w.W, 0.42, w.seed, device="cuda")
+    ref42 = golden(digests, "decay32768_p042", w.steps)
+    med42, final42, _, _ = sim_rate(ltl, torch, g42, w.rule, "cat_i8", w.steps, args.leg_reps or 5)
+    res["live_density_042"] = {"value": cells * w.steps / med42, "unit": "cell-updates/s", "ms_per_run": med42 * 1e3,
+                               "alive_after_run": int((final42 == 1).sum().item()),
+                               "bit_exact": None if ref42 is None else digest_of(final42) == ref42}
+    del final42, g42
     if not args.no_direct:
         med_d, final_d, _, _ = sim_rate(ltl, torch, g, w.rule, "direct", w.steps, 1, warmup=0)
         res["direct_stencil_cell_updates_per_s"] = cells * w.steps / med_d
