@@ -259,7 +259,7 @@ int32_t batch_prepare(ltl_batch &b) {
             cost = 0.25 * (double)(p.TH + 2 * p.L) * (p.TW + 2 * p.L);
             for (int st = 1; st <= p.T; ++st) {
                 const int E = roundup(r * (p.T - st), 16);
-                cost += (double)(p.TH + 2 * E) * (p.TW + 2 * E) * ((b.epi[i] == EPI_BYTE || b.epi[i] == EPI_WIN) ? 1.0 : 1.15);
+                cost += (double)(p.TH + 2 * E) * (p.TW + 2 * E) * ((b.epi[i] == EPI_BYTE || b.epi[i] == EPI_WIN || b.epi[i] == EPI_WIN8) ? 1.0 : 1.15);
             }
         }
         for (int k = 0; k < ntiles; ++k) list.push_back({cost, {i, k, b.epi[i], 0}});

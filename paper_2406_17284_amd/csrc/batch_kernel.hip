@@ -30,6 +30,10 @@ __device__ __forceinline__ void batch_entry(const BatchParams &bp, int k, uint8_
         cat_tile<ELEM, EPI_HALF>(p, item.tile, lds, tid, lane, wave, nwaves, cd, side);
     else if (item.epi == EPI_DECAY8) {
         if constexpr (ELEM == ELEM_I8) cat_tile<ELEM, EPI_DECAY8>(p, item.tile, lds, tid, lane, wave, nwaves, cd, side);
+    } else if (item.epi == EPI_WIN8) {
+        if constexpr (ELEM == ELEM_I8) cat_tile<ELEM, EPI_WIN8>(p, item.tile, lds, tid, lane, wave, nwaves, cd, side);
+    } else if (item.epi == EPI_DECAY8W) {
+        if constexpr (ELEM == ELEM_I8) cat_tile<ELEM, EPI_DECAY8W>(p, item.tile, lds, tid, lane, wave, nwaves, cd, side);
     } else
         cat_tile<ELEM, EPI_DECAY>(p, item.tile, lds, tid, lane, wave, nwaves, cd, side);
 }

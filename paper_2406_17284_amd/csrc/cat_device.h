@@ -96,6 +96,29 @@ __device__ __forceinline__ uint32_t inrange16(v4i n, uint32_t a, const RuleConst
     return __builtin_amdgcn_perm(x23, x01, 0x07050301u) >> 7;
 }
 
+// Counts n - c of 4 cells (int32, c the window offset) as bytes, clamped to 255: the low 16 bits
+// of each go through an unsigned 16-bit min, so values above the window and negative ones (whose
+// low halves are at least 0x8000) both become 255, which lies outside every range of the window.
+__device__ __forceinline__ uint32_t window_bytes255(v4i n) {
+    const us2 cap = {255, 255};
+    const us2 p01 = __builtin_elementwise_min(
+        __builtin_bit_cast(us2, __builtin_amdgcn_perm((uint32_t)n[1], (uint32_t)n[0], 0x05040100u)), cap);
+    const us2 p23 = __builtin_elementwise_min(
+        __builtin_bit_cast(us2, __builtin_amdgcn_perm((uint32_t)n[3], (uint32_t)n[2], 0x05040100u)), cap);
+    return __builtin_amdgcn_perm(__builtin_bit_cast(uint32_t, p23), __builtin_bit_cast(uint32_t, p01), 0x06040200u);
+}
+
+// Range test of 4 byte counts x (0..255): bit 7 of byte v of the result is set iff
+// lo(s) <= x[v] <= hi(s), with s the byte v of `s` selecting byte s of the tables Tlo = 256 - lo,
+// Thi = hi + 1 (1 <= lo, hi <= 254). v_lerp_u8 gives (a + b) >> 1 per byte from a 9-bit sum, so
+// its bit 7 is the carry out of a + b: x + 256 - lo >= 256 iff x >= lo, and
+// (255 - x) + hi + 1 >= 256 iff x <= hi.
+__device__ __forceinline__ uint32_t inrange8(uint32_t x, uint32_t s, const RuleConsts &rc) {
+    const uint32_t ge = __builtin_amdgcn_lerp(x, __builtin_amdgcn_perm(rc.Tlo, rc.Tlo, s), 0u);
+    const uint32_t le = __builtin_amdgcn_lerp(~x, __builtin_amdgcn_perm(rc.Thi, rc.Thi, s), 0u);
+    return ge & le;
+}
+
 // Next states of 4 adjacent cells from their box counts n (centre included) and states s.
 // `m` is the validity mask of the 4 cells (0xFF per byte inside the grid); cells outside get 0.
 // Returns the state dword; *alive receives the alive-indicator dword (state == 1).
@@ -128,10 +151,24 @@ __device__ __forceinline__ uint32_t transition4(v4i n, uint32_t s, uint32_t m, c
         uint32_t x = (a & b & (m & 0x80808080u)) >> 7;
         *alive = x;
         return x;
+    } else if constexpr (EPI == EPI_WIN8) {
+        // counts arrive as n - c (window up to 254 wide)
+        const uint32_t x = (inrange8(window_bytes255(n), s, rc) & (m & 0x80808080u)) >> 7;
+        *alive = x;
+        return x;
     } else if constexpr (EPI == EPI_HALF) {
         const uint32_t x = inrange16(n, s, rc) & m;
         *alive = x;
         return x;
+    } else if constexpr (EPI == EPI_DECAY8W) {
+        // as EPI_DECAY8, with the range test on the windowed bytes; the tables are read with any
+        // state byte 0..7 (states >= 2 decay whatever the test gives)
+        const uint32_t x = (inrange8(window_bytes255(n), s, rc) & 0x80808080u) >> 7;
+        const uint32_t n0 = __builtin_amdgcn_perm(rc.N0hi, rc.N0lo, s);
+        const uint32_t n1 = __builtin_amdgcn_perm(rc.N1hi, rc.N1lo, s);
+        const uint32_t nx = __builtin_amdgcn_perm(n1, n0, (x << 2) | 0x03020100u) & m;
+        *alive = __builtin_amdgcn_perm(0u, 0x00000100u, nx);         // next state == 1
+        return nx;
     } else if constexpr (EPI == EPI_DECAY8) {
         // C <= 8: the state bytes (0..7) select from 8-byte tables with one byte permute each:
         // the alive bit (state == 1), and the next state when the range test fails (N0) or holds
@@ -526,7 +563,7 @@ __device__ __forceinline__ void phase_b(const CatParams &p, uint8_t *Qt, uint8_t
     const uint32_t PS = (uint32_t)p.PS, PA = (uint32_t)p.PA;
     v4i ca[4], cb[4];
     uint32_t sa[4], sb[4];
-    const int cw = (EPI == EPI_WIN) ? -p.rc.cwin : 0;
+    const int cw = epi_windowed(EPI) ? -p.rc.cwin : 0;
     const v4i acc0 = {cw, cw, cw, cw};
     // counts and centre states of block M (slot M & 3)
 #define CAT_ISSUE(M)                                                                               \
@@ -644,7 +681,9 @@ __device__ __forceinline__ void cat_steps(const CatParams &p, uint8_t *Qt, uint8
         lo.q = (uint32_t)((L + li) * (int)PS + (L + j0 + 4 * lg));
         lo.a = (uint32_t)((L + li) * (int)PA + (L + j0 + 4 * lg) * CELL);
         if (count > 0)
-            phase_a<ELEM, !((ELEM == ELEM_I8 || ELEM == ELEM_F16) && epi_decays(EPI)) ? 0 : EPI == EPI_DECAY8 ? 2 : 1>(
+            phase_a<ELEM, !((ELEM == ELEM_I8 || ELEM == ELEM_F16) && epi_decays(EPI)) ? 0
+                                                                                  : (EPI == EPI_DECAY8 || EPI == EPI_DECAY8W) ? 2
+                                                                                                                               : 1>(
                 At, a_off, a_off2, PA, rb0, count,
                                                                                    bd, Ha, Hb, La, Lb);
         __syncthreads();   // every read of the old states precedes any in-place write

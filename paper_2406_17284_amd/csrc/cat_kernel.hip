@@ -88,7 +88,9 @@ size_t cat_lds_bytes(const CatParams &p, int elem, int epi, int persistent) {
         if (elem == ELEM_I8W)   /* radii 17..32 always have counts > 126: no 8-bit epilogue */                     \
             return dec ? (const void *)&KERNEL<ELEM_I8W, EPI_DECAY> : (const void *)&KERNEL<ELEM_I8W, EPI_HALF>;   \
         if (epi == EPI_WIN) return (const void *)&KERNEL<ELEM_I8, EPI_WIN>;                                        \
+        if (epi == EPI_WIN8) return (const void *)&KERNEL<ELEM_I8, EPI_WIN8>;                                      \
         if (epi == EPI_DECAY8) return (const void *)&KERNEL<ELEM_I8, EPI_DECAY8>;                                  \
+        if (epi == EPI_DECAY8W) return (const void *)&KERNEL<ELEM_I8, EPI_DECAY8W>;                                \
         return dec ? (const void *)&KERNEL<ELEM_I8, EPI_DECAY>                                                     \
                    : epi == EPI_HALF ? (const void *)&KERNEL<ELEM_I8, EPI_HALF> : (const void *)&KERNEL<ELEM_I8, EPI_BYTE>; \
     }

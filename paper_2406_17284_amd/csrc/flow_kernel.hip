@@ -100,7 +100,9 @@ static const void *cat_flow_func(int elem, int epi) {
     if (elem == ELEM_I8W)
         return dec ? (const void *)&cat_flow<ELEM_I8W, EPI_DECAY> : (const void *)&cat_flow<ELEM_I8W, EPI_HALF>;
     if (epi == EPI_WIN) return (const void *)&cat_flow<ELEM_I8, EPI_WIN>;
+    if (epi == EPI_WIN8) return (const void *)&cat_flow<ELEM_I8, EPI_WIN8>;
     if (epi == EPI_DECAY8) return (const void *)&cat_flow<ELEM_I8, EPI_DECAY8>;
+    if (epi == EPI_DECAY8W) return (const void *)&cat_flow<ELEM_I8, EPI_DECAY8W>;
     return dec ? (const void *)&cat_flow<ELEM_I8, EPI_DECAY>
                : epi == EPI_HALF ? (const void *)&cat_flow<ELEM_I8, EPI_HALF> : (const void *)&cat_flow<ELEM_I8, EPI_BYTE>;
 }

@@ -87,24 +87,45 @@ static Ranges rule_ranges(const ltl_rule_t &r, int cap) {
     return g;
 }
 
-// Window offset of EPI_WIN: c = (smallest lower bound) - 1, valid when every upper bound is
-// at most c + 126. Returns false when the ranges span more than that.
-static bool window_of(const ltl_rule_t &r, int *c) {
+// Window offset of the windowed epilogues: c = (smallest lower bound) - 1, valid when every
+// upper bound is at most c + width (126 for EPI_WIN's 7-bit lanes, 254 for the full bytes of
+// EPI_WIN8 and EPI_DECAY8W). Returns false when the ranges span more than that.
+static bool window_of(const ltl_rule_t &r, int width, int *c) {
     const Ranges g = rule_ranges(r, 127);
     int lo = 1 << 30, hi = -(1 << 30);
     if (!g.s_empty) { lo = std::min(lo, g.ls); hi = std::max(hi, g.hs); }
     if (!g.b_empty) { lo = std::min(lo, g.lb); hi = std::max(hi, g.hb); }
     if (g.s_empty && g.b_empty) { *c = 0; return true; }
     *c = lo - 1;
-    return hi - *c <= 126;
+    return hi - *c <= width;
 }
 
 int epi_of(const ltl_rule_t &r, int elem) {
-    if (r.C >= 3) return (r.C <= 8 && elem == ELEM_I8) ? EPI_DECAY8 : EPI_DECAY;
-    if (max_count(r) <= 126) return EPI_BYTE;
     int c = 0;
-    if (elem == ELEM_I8 && window_of(r, &c)) return EPI_WIN;
+    if (r.C >= 3) {
+        if (r.C <= 8 && elem == ELEM_I8) return window_of(r, 254, &c) ? EPI_DECAY8W : EPI_DECAY8;
+        return EPI_DECAY;
+    }
+    if (max_count(r) <= 126) return EPI_BYTE;
+    if (elem == ELEM_I8 && window_of(r, 126, &c)) return EPI_WIN;
+    if (elem == ELEM_I8 && window_of(r, 254, &c)) return EPI_WIN8;
     return EPI_HALF;
+}
+
+// Next-state tables of the C <= 8 decay epilogues: state k -> next state when the range test
+// fails (N0) or holds (N1): 0 -> born (1) or stays 0, 1 -> survives (1) or starts to decay (2),
+// k >= 2 -> k + 1, wrapping to 0 at C; bytes k >= C are never selected.
+static void decay_tables(RuleConsts &c) {
+    uint64_t t0 = 0, t1 = 0;
+    for (int k = 0; k < 8; ++k) {
+        const int dec = (k >= 2 && k < c.C) ? (k + 1 < c.C ? k + 1 : 0) : 0;
+        const int f = k == 0 ? 0 : k == 1 ? 2 : dec;
+        const int h = k == 0 ? 1 : k == 1 ? 1 : dec;
+        t0 |= (uint64_t)f << (8 * k);
+        t1 |= (uint64_t)h << (8 * k);
+    }
+    c.N0lo = (uint32_t)t0; c.N0hi = (uint32_t)(t0 >> 32);
+    c.N1lo = (uint32_t)t1; c.N1hi = (uint32_t)(t1 >> 32);
 }
 
 // Thresholds on the box count n (centre included) and the SWAR constants of the two-state
@@ -117,10 +138,26 @@ RuleConsts make_consts(const ltl_rule_t &r, int epi) {
     c.s1 = r.S1; c.s2 = r.S2; c.b1 = r.B1; c.b2 = r.B2;
     int ls, hs, lb, hb;
     uint32_t rep, top, klo_s, klo_b, khi_s, khi_b;
+    if (epi == EPI_WIN8 || epi == EPI_DECAY8W) {
+        // full-byte range tests on n - c: Tlo = 256 - lo, Thi = hi + 1 per centre state (byte 0
+        // dead, byte 1 alive), bounds relative to the window (1 <= lo, hi <= 254); an empty range
+        // becomes lo = 255, hi = 0, which no byte satisfies
+        const Ranges g = rule_ranges(r, 127);
+        (void)window_of(r, 254, &c.cwin);
+        const int lb = g.b_empty ? 255 : g.lb - c.cwin, hb = g.b_empty ? 0 : g.hb - c.cwin;
+        const int ls = g.s_empty ? 255 : g.ls - c.cwin, hs = g.s_empty ? 0 : g.hs - c.cwin;
+        c.Tlo = (uint32_t)(256 - lb) | ((uint32_t)(256 - ls) << 8);
+        c.Thi = (uint32_t)(hb + 1) | ((uint32_t)(hs + 1) << 8);
+        if (epi == EPI_DECAY8W) {
+            c.Crep = (uint32_t)c.C * 0x01010101u;
+            decay_tables(c);
+        }
+        return c;
+    }
     if (epi == EPI_BYTE || epi == EPI_WIN) {
         Ranges g = rule_ranges(r, 127);
         if (epi == EPI_WIN) {   // thresholds relative to the window offset (non-empty ranges)
-            (void)window_of(r, &c.cwin);
+            (void)window_of(r, 126, &c.cwin);
             if (!g.s_empty) { g.ls -= c.cwin; g.hs -= c.cwin; }
             if (!g.b_empty) { g.lb -= c.cwin; g.hb -= c.cwin; }
         }
@@ -130,20 +167,7 @@ RuleConsts make_consts(const ltl_rule_t &r, int epi) {
     } else if (epi == EPI_HALF || epi_decays(epi)) {   // decay: the range test of the s in {0, 1} case
         const Ranges g = rule_ranges(r, 2047);
         c.Crep = (uint32_t)c.C * 0x01010101u;
-        if (epi == EPI_DECAY8) {
-            // state k -> next state: 0 -> born (1) or stays 0, 1 -> survives (1) or starts to decay
-            // (2), k >= 2 -> k + 1, wrapping to 0 at C; bytes k >= C are never selected
-            uint64_t t0 = 0, t1 = 0;
-            for (int k = 0; k < 8; ++k) {
-                const int dec = (k >= 2 && k < c.C) ? (k + 1 < c.C ? k + 1 : 0) : 0;
-                const int f = k == 0 ? 0 : k == 1 ? 2 : dec;
-                const int h = k == 0 ? 1 : k == 1 ? 1 : dec;
-                t0 |= (uint64_t)f << (8 * k);
-                t1 |= (uint64_t)h << (8 * k);
-            }
-            c.N0lo = (uint32_t)t0; c.N0hi = (uint32_t)(t0 >> 32);
-            c.N1lo = (uint32_t)t1; c.N1hi = (uint32_t)(t1 >> 32);
-        }
+        if (epi == EPI_DECAY8) decay_tables(c);
         ls = g.ls; hs = g.hs; lb = g.lb; hb = g.hb;
         rep = 0x00010001u;
         top = 0x8000u;

@@ -16,8 +16,18 @@ namespace ltl {
 //  EPI_DECAY8 C in 3..8 states, int8 element: every state fits in 3 bits, so the alive bit and
 //            the next state come from per-byte tables indexed by the state (one byte permute
 //            each) instead of the SWAR arithmetic of EPI_DECAY
-enum Epi { EPI_BYTE = 0, EPI_HALF = 1, EPI_DECAY = 2, EPI_WIN = 3, EPI_DECAY8 = 4 };
-__host__ __device__ constexpr bool epi_decays(int epi) { return epi == EPI_DECAY || epi == EPI_DECAY8; }
+//  EPI_WIN8  as EPI_WIN with a window c+1..c+254: the counts n - c are clamped to 255 and the
+//            range tests run on full bytes with v_lerp_u8 (a per-byte (a + b) >> 1 whose top
+//            bit is the carry of a + b), so the 8-bit lanes need no spare top bit
+//  EPI_DECAY8W EPI_DECAY8 with the range test of EPI_WIN8 (both ranges inside a 254 window)
+enum Epi { EPI_BYTE = 0, EPI_HALF = 1, EPI_DECAY = 2, EPI_WIN = 3, EPI_DECAY8 = 4, EPI_WIN8 = 5, EPI_DECAY8W = 6 };
+__host__ __device__ constexpr bool epi_decays(int epi) {
+    return epi == EPI_DECAY || epi == EPI_DECAY8 || epi == EPI_DECAY8W;
+}
+// epilogues whose vertical product starts from -c (the window offset)
+__host__ __device__ constexpr bool epi_windowed(int epi) {
+    return epi == EPI_WIN || epi == EPI_WIN8 || epi == EPI_DECAY8W;
+}
 
 // Element type of the band-product operands. ELEM_I8W is int8 for radii 17..32: every
 // 16-column half needs 16 + 2r <= 80 columns (a K = 64 and a K = 32 product) and every
@@ -42,9 +52,11 @@ struct RuleConsts {
     uint32_t Klo, Dlo, Khi, Dhi;
     // BYTE lookup tables of the same offsets, indexed by the centre state (0 or 1) with one
     // byte permute per dword of four cells: byte 0 holds the dead-centre offset, byte 1 the
-    // alive-centre offset (Tlo: 0x80 - lo(s), Thi: 0x80 + hi(s)).
+    // alive-centre offset (Tlo: 0x80 - lo(s), Thi: 0x80 + hi(s); EPI_WIN8 and EPI_DECAY8W:
+    // Tlo: 256 - lo(s), Thi: hi(s) + 1, bounds relative to the window).
     uint32_t Tlo, Thi;
-    int32_t cwin;          // EPI_WIN: window offset c (the vertical product starts from -c)
+    int32_t cwin;          // EPI_WIN, EPI_WIN8, EPI_DECAY8W: window offset c (the vertical product
+                           // starts from -c)
     uint32_t Crep;         // EPI_DECAY: C in every byte (a state reaching C wraps to 0)
     // EPI_DECAY8: next state by state byte k = 0..7 when the range test fails (N0) or holds (N1),
     // as the 8-byte tables {N0hi:N0lo}, {N1hi:N1lo} of a byte permute

@@ -111,7 +111,11 @@ def sweep_rules(r):
              inputs.Rule(r, 0, 0, N // 3, N // 3 + min(100, N // 3), N // 3 + 5, N // 3 + min(60, N // 4)),  # narrow
              inputs.Rule(r, 0, 1, N // 10, (9 * N) // 10, 0, N // 6),          # wide, lower bound 0
              inputs.Rule(r, 0, 1, N - min(N // 2, 90), N, N // 2, N - 1)]      # open upper bound
+    # spans 127..254 from r = 8 on: the full-byte window
+    rules.append(inputs.Rule(r, 0, 1, N // 5, N // 5 + min(240, N // 2), N // 5 + min(10, N // 4), N // 5 + min(250, N // 2)))
     rules.append(inputs.Rule(r, 5, 0, N // 4, N // 4 + min(120, N // 3), N // 5, N // 5 + min(40, N // 4)))  # decay
+    # decay with a window wider than 254 counts (16-bit range test) where N allows it
+    rules.append(inputs.Rule(r, 6, 1, N // 10, (8 * N) // 10, N // 5, N // 5 + min(60, N // 4)))
     # decay with the fewest states and with more states than the 3-bit state tables hold
     rules.append(inputs.Rule(r, 3, 1, N // 5, N // 5 + min(110, N // 3), N // 4, N // 4 + min(50, N // 4)))
     rules.append(inputs.Rule(r, 12, 0, N // 6, N // 6 + min(100, N // 3), N // 4, N // 4 + min(30, N // 5)))

@@ -600,15 +600,16 @@ def test_persistent_refused_where_absent(ltl):
     assert e.value.code == ltl.LTL_ERR_ARG
 
 
-# ------------------------------------------------------------------ windowed byte epilogue
+# ------------------------------------------------------------------ windowed byte epilogues
 # Two-state rules whose counts exceed 126 but whose finite range bounds all lie in a window
-# c+1..c+126 run the byte epilogue on n - c clamped to 127 (int8 method); the others keep
-# 16-bit lanes. Each rule below sits on one side of that choice or at an edge of it; the
+# c+1..c+126 run the byte epilogue on n - c clamped to 127 (int8 method); with a window up to
+# c+254 the full-byte form (n - c clamped to 255, v_lerp_u8 range tests); the others keep
+# 16-bit lanes. Each rule below sits on one side of these choices or at an edge of them; the
 # grids are striped in density so that the counts sweep across the window bounds.
 WINDOW_RULES = [
     inputs.Rule(6, 0, 1, 42, 76, 45, 57),            # sweep rule r = 6 (window 41..167)
-    inputs.Rule(8, 0, 1, 100, 225, 150, 160),        # span exactly 126: windowed
-    inputs.Rule(8, 0, 1, 100, 226, 150, 160),        # span 127: 16-bit lanes
+    inputs.Rule(8, 0, 1, 100, 225, 150, 160),        # span exactly 126: 7-bit window
+    inputs.Rule(8, 0, 1, 100, 226, 150, 160),        # span 127: full-byte window
     inputs.Rule(6, 0, 1, 10, 100, 0, 50),            # lower bound 0 (c = -1)
     inputs.Rule(6, 0, 1, 150, 169, 140, 160),        # upper bound at the largest count
     inputs.Rule(7, 0, 1, 60, 120, 9, 8),             # empty birth range
@@ -616,6 +617,11 @@ WINDOW_RULES = [
     inputs.Rule(9, 0, 0, 200, 250, 190, 260),        # M = 0: survival range moves up by one
     inputs.Rule(12, 0, 1, 156, 281, 168, 212),       # sweep rule r = 12 (span 126)
     inputs.Rule(16, 0, 1, 500, 560, 480, 600),       # r = 16, narrow window
+    inputs.Rule(16, 0, 1, 272, 490, 294, 370),       # sweep rule r = 16 (full-byte window, span 219)
+    inputs.Rule(10, 0, 1, 100, 353, 120, 200),       # span exactly 254: full-byte window
+    inputs.Rule(10, 0, 1, 100, 354, 120, 200),       # span 255: 16-bit lanes
+    inputs.Rule(9, 0, 1, 0, 253, 200, 253),          # full-byte window from count 0 (c = -1, span 254)
+    inputs.Rule(11, 0, 0, 300, 529, 320, 9),         # M = 0, empty birth range, survival to the largest count
 ]
 
 

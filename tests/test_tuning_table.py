@@ -91,7 +91,8 @@ def test_user_cache_first_and_class_must_match(files):
 @pytest.mark.parametrize("rule,method,elem,epi", [
     (inputs.BOSCO_M1, ltl.LTL_CAT_I8, "i8", "byte"),           # counts <= 121 fit bytes
     (inputs.sweep_rule(6), ltl.LTL_CAT_I8, "i8", "win"),       # ranges inside a 126-wide window
-    (inputs.sweep_rule(13), ltl.LTL_CAT_I8, "i8", "half"),     # survival range wider than the window
+    (inputs.sweep_rule(13), ltl.LTL_CAT_I8, "i8", "win"),      # ranges inside a 254-wide window
+    (inputs.Rule(13, 0, 1, 100, 500, 150, 300), ltl.LTL_CAT_I8, "i8", "half"),   # wider than 254
     (inputs.DECAY_C8, ltl.LTL_CAT_I8, "i8", "decay"),
     (inputs.sweep_rule(6), ltl.LTL_CAT_F16, "f16", "half"),    # windowed bytes are int8 only
     (inputs.sweep_rule(5), ltl.LTL_CAT_F8, "f8", "byte"),
