@@ -443,6 +443,7 @@ def bench_shard(args, ltl, inputs, torch):
         row["launch_us"] = launch_s * 1e6
         row["exchange_us_model"] = halo / (XGMI_LINK_GBS * 1e9) * 1e6
         res["per_r"][str(r)] = row
+        log(f"shard r={r} done")
     return res
 
 
