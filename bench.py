@@ -13,11 +13,12 @@ initial grid, bit-exactness against the oracle's digests, and a CPU-oracle basel
   * life256: Life on 256^2, 64 steps;
   * batched: the 512-instance batch, 32 steps (one hipGraph);
   * decay: the C = 8 R16 rule on 32768^2, 20 steps;
-  * periodic: the headline workload on a torus.
+  * periodic: the headline workload on a torus;
+  * energy: cell-updates per joule of CAT int8 and the direct stencil, Bosco R5 on 32768^2.
 Prints one JSON line on stdout (progress goes to stderr).
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-sweep] [--no-life] [--no-batch] [--no-decay]
-                  [--no-cpu] [--tuning T,rows,cols,waves[,persistent[,lds_pad]]] [--energy] [--shard N]
+                  [--no-cpu] [--tuning T,rows,cols,waves[,persistent[,lds_pad]]] [--no-energy] [--shard N]
                   [--only sweep|batch|decay|life [--sweep-radii ...] [--sweep-methods ...]]
 """
 from __future__ import annotations
@@ -583,8 +584,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baselines")
     ap.add_argument("--shard", type=int, default=0, metavar="N",
                     help="also time one GPU's row strip (1/N) of the sweep grid and the halo it would exchange")
-    ap.add_argument("--energy", action="store_true",
-                    help="also measure cell-updates per joule (CAT int8 and direct, Bosco R5 on 32768^2)")
+    ap.add_argument("--no-energy", action="store_true",
+                    help="skip the cell-updates per joule leg (CAT int8 and direct, Bosco R5 on 32768^2)")
     ap.add_argument("--tuning", type=str, default="",
                     help="T,tile_rows,tile_cols,waves[,persistent[,lds_pad]] for the headline (default: the "
                          "library's own pick from its tuning table)")
@@ -745,8 +746,9 @@ def main():
         log("decay done")
     if args.shard > 1:
         out["shard"] = bench_shard(args, ltl, inputs, torch)
-    if args.energy:
+    if not args.no_energy:
         out["energy"] = bench_energy(args, ltl, inputs, torch)
+        log("energy done")
 
     if oracle is not None:
         # the headline workload: all 100 steps on every host thread (also the parity of the timed
