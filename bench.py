@@ -586,6 +586,7 @@ def main():
                     help="also time one GPU's row strip (1/N) of the sweep grid and the halo it would exchange")
     ap.add_argument("--no-energy", action="store_true",
                     help="skip the cell-updates per joule leg (CAT int8 and direct, Bosco R5 on 32768^2)")
+    ap.add_argument("--energy", action="store_true", help=argparse.SUPPRESS)   # the leg is on by default
     ap.add_argument("--tuning", type=str, default="",
                     help="T,tile_rows,tile_cols,waves[,persistent[,lds_pad]] for the headline (default: the "
                          "library's own pick from its tuning table)")
