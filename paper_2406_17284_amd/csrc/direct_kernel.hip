@@ -4,8 +4,9 @@
 // work per cell grows as (2r+1)^2 -- the Omega(r^2) cost the paper's introduction attributes to
 // this scheme. No sum is shared between cells.
 //
-// MI355X form: 128 x 256 output tiles staged with 16-byte loads (HBM re-reads of the halo are
-// (128 + 2r)(256 + 2 roundup16(r)) / (128 x 256) of the tile, 1.21x at r = 5). A thread computes
+// MI355X form: 128 x 256 output tiles staged with 16-byte loads (the halo re-reads are
+// (128 + 2r)(256 + 2 roundup16(r)) / (128 x 256) of the tile, 1.21x at r = 5; with neighbouring
+// tiles on one XCD they hit its L2, and HBM reads stay within a few per cent of the grid). A thread computes
 // four horizontally adjacent cells at once with byte-lane SWAR: for each row of the box it reads
 // the aligned LDS dwords around the four cells and adds, for every column offset, the dword of
 // the four cells' neighbours at that offset (one funnel shift to realign it, one packed add), so
@@ -140,10 +141,20 @@ __device__ __forceinline__ void direct_tile(const DirectParams &p, int gi0, int 
     }
 }
 
+// Workgroup b runs on XCD b mod 8; the grid is the tile count rounded up to a multiple of 8 and
+// XCD x takes the contiguous run of tiles x * nb/8 ... (row-major), so the tiles whose halos
+// overlap (left/right neighbours, and the tile row below) are staged through the same L2.
+// Surplus workgroups exit before the first barrier.
 template <int R>
 __global__ void __launch_bounds__(kDirectThreads) direct_step(DirectParams p) {
     extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
-    direct_tile<R>(p, blockIdx.y * kDirectTH, blockIdx.x * kDirectTW, lds);
+    const int ntx = (p.W + kDirectTW - 1) / kDirectTW;
+    const int ntiles = ntx * ((p.H + kDirectTH - 1) / kDirectTH);
+    const int b = blockIdx.x;
+    const int tile = (b & 7) * (int)(gridDim.x >> 3) + (b >> 3);
+    if (tile >= ntiles) return;
+    const int ty = tile / ntx;
+    direct_tile<R>(p, ty * kDirectTH, (tile - ty * ntx) * kDirectTW, lds);
 }
 
 // Radius dispatch over 1..32 (RADII(X) expands X(1) ... X(32)).
@@ -184,7 +195,8 @@ int direct_threads() { return kDirectThreads; }
 KernelLaunch direct_launch_shape(const DirectParams &p) {
     KernelLaunch k;
     k.func = direct_func(p.r);
-    k.grid = dim3((p.W + kDirectTW - 1) / kDirectTW, (p.H + kDirectTH - 1) / kDirectTH, 1);
+    const int ntiles = ((p.W + kDirectTW - 1) / kDirectTW) * ((p.H + kDirectTH - 1) / kDirectTH);
+    k.grid = dim3((unsigned)((ntiles + 7) & ~7), 1, 1);   // a multiple of 8 (see direct_step)
     k.block = dim3(kDirectThreads, 1, 1);
     k.lds = direct_lds_bytes(p.r);
     return k;
