@@ -245,7 +245,10 @@ struct StepGeom {
 template <int MAXC>
 __device__ __forceinline__ StepGeom step_geom(const CatParams &p, int t) {
     StepGeom g;
-    g.E = (p.r * (p.T - t) + 15) & ~15;
+    // the margin is roundup16(r (T - 1)) + 16 (+ 48 for the wide element, never 32), so a
+    // 32-cell margin means 1 <= r (T - 1) <= 16 and every step but the last extends exactly 16:
+    // the general rule's value, in a form a kernel with the margin fixed folds
+    g.E = (p.L == 32) ? ((t < p.T) ? 16 : 0) : ((p.r * (p.T - t) + 15) & ~15);
     g.nstrips = (p.TW + 2 * g.E) >> 5;
     g.nrb = (p.TH + 2 * g.E) >> 4;
     if (g.nrb <= MAXC) {   // one segment per strip (the usual case): no integer division

@@ -8,8 +8,23 @@ namespace ltl {
 
 // One workgroup per tile; workgroups of one XCD take consecutive tiles, so the halos of
 // neighbouring tiles meet in that XCD's L2.
-template <int ELEM, int EPI>
+//
+// FIXED != 0: a copy of the kernel for one launch-shape class, picked by the launcher where the
+// launch belongs to it: 224-column tiles with a 32-cell margin and no LDS padding (row pitch
+// FIXED = 304 for states and alive bits alike), and with THC != 0 also tiles of THC rows. With
+// these compile-time constants the block-row offsets of the LDS accesses become instruction
+// offsets instead of per-block address arithmetic, each step's extent is known (a 32-cell
+// margin leaves 16 for every step but the last), and with the height fixed the guards of the
+// unrolled block loops fold away.
+template <int ELEM, int EPI, int FIXED = 0, int THC = 0>
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) cat_step(CatParams p) {
+    if constexpr (FIXED != 0) {
+        p.PS = FIXED;
+        p.PA = FIXED;
+        p.TW = 224;
+        p.L = 32;
+    }
+    if constexpr (THC != 0) p.TH = THC;
     extern __shared__ __attribute__((aligned(1024))) uint8_t lds[];
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -98,12 +113,54 @@ CAT_PICK(cat_step)
 CAT_PICK(cat_persist)
 #undef CAT_PICK
 
-static const void *cat_func(int elem, int epi, int persistent) {
-    return persistent ? cat_persist_func(elem, epi) : cat_step_func(elem, epi);
+// The fixed shape class: 224-column tiles, a 32-cell margin (steps per launch T with
+// r (T - 1) <= 16), no LDS padding: row pitch TW + 2L + 16 = 304. The tuning table holds it for
+// most int8 Moore rules on large grids (192 rows) and for the Bosco rule on 4096^2 (160 rows).
+constexpr int kFixedPitch = 304;
+
+static bool fixed_class(const CatParams &p) {
+    return p.PS == kFixedPitch && p.PA == kFixedPitch && p.TW == 224 && p.L == 32;
+}
+
+static const void *cat_step_fixed_func(int epi) {
+    switch (epi) {
+        case EPI_BYTE: return (const void *)&cat_step<ELEM_I8, EPI_BYTE, kFixedPitch>;
+        case EPI_HALF: return (const void *)&cat_step<ELEM_I8, EPI_HALF, kFixedPitch>;
+        case EPI_DECAY: return (const void *)&cat_step<ELEM_I8, EPI_DECAY, kFixedPitch>;
+        case EPI_WIN: return (const void *)&cat_step<ELEM_I8, EPI_WIN, kFixedPitch>;
+        case EPI_DECAY8: return (const void *)&cat_step<ELEM_I8, EPI_DECAY8, kFixedPitch>;
+        case EPI_WIN8: return (const void *)&cat_step<ELEM_I8, EPI_WIN8, kFixedPitch>;
+        case EPI_DECAY8W: return (const void *)&cat_step<ELEM_I8, EPI_DECAY8W, kFixedPitch>;
+        default: return nullptr;
+    }
+}
+
+// 160-row tiles of the fixed class, two-state epilogues only: with the height fixed too the
+// decay epilogues and the 192-row tiles exceed the 128-register budget of two 8-wave
+// workgroups per CU and spill (measured slower), so they keep the height a launch parameter.
+static const void *cat_step_fixed160_func(int epi) {
+    switch (epi) {
+        case EPI_BYTE: return (const void *)&cat_step<ELEM_I8, EPI_BYTE, kFixedPitch, 160>;
+        case EPI_HALF: return (const void *)&cat_step<ELEM_I8, EPI_HALF, kFixedPitch, 160>;
+        case EPI_WIN: return (const void *)&cat_step<ELEM_I8, EPI_WIN, kFixedPitch, 160>;
+        case EPI_WIN8: return (const void *)&cat_step<ELEM_I8, EPI_WIN8, kFixedPitch, 160>;
+        default: return nullptr;
+    }
+}
+
+static const void *cat_func(const CatParams &p, int elem, int epi, int persistent) {
+    if (persistent) return cat_persist_func(elem, epi);
+    if (elem == ELEM_I8 && fixed_class(p)) {
+        if (p.TH == 160) {
+            if (const void *f = cat_step_fixed160_func(epi)) return f;
+        }
+        if (const void *f = cat_step_fixed_func(epi)) return f;
+    }
+    return cat_step_func(elem, epi);
 }
 
 int cat_occupancy(const CatParams &p, int elem, int epi, int waves, int persistent) {
-    const void *f = cat_func(elem, epi, persistent);
+    const void *f = cat_func(p, elem, epi, persistent);
     size_t lds = cat_lds_bytes(p, elem, epi, persistent);
     // a shape the device cannot run reads as zero workgroups; its HIP error is not left pending
     if (lds > 65536 && hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess) {
@@ -128,7 +185,7 @@ static int device_cus() {
 
 KernelLaunch cat_launch_shape(const CatParams &p, int elem, int epi, int waves, int persistent) {
     KernelLaunch k;
-    k.func = cat_func(elem, epi, persistent);
+    k.func = cat_func(p, elem, epi, persistent);
     k.lds = cat_lds_bytes(p, elem, epi, persistent);
     const int ntiles = p.ntx * p.nty;
     if (persistent) {

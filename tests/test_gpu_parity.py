@@ -206,6 +206,38 @@ def test_tile_shapes(ltl, tile):
         run_and_compare(ltl, g0, rule, "cat_i8", 7, tuning=tuning)
 
 
+# The fixed shape class (224-column tiles, 32-cell margin, 8 waves: separate kernel copies with
+# these constants compiled in, 160-row tiles with the height fixed too): every epilogue, both
+# tile heights, several tile rows and columns with ragged edges, launches of T steps and a
+# shorter last launch.
+FIXED_CLASS_CASES = [
+    (inputs.sweep_rule(5), 4),                         # byte lanes
+    (inputs.sweep_rule(5), 2),
+    (inputs.sweep_rule(8), 3),                         # 7-bit window
+    (inputs.sweep_rule(16), 2),                        # full-byte window
+    (inputs.Rule(10, 0, 1, 100, 354, 120, 200), 2),    # span 255: 16-bit lanes
+    (inputs.Rule(5, 12, 1, 34, 58, 34, 45), 4),        # decay, C > 8
+    (inputs.Rule(5, 6, 0, 30, 60, 34, 45), 3),         # decay tables, C <= 8
+    (inputs.Rule(16, 8, 0, 300, 500, 330, 420), 2),    # decay tables, full-byte window
+]
+
+
+@pytest.mark.parametrize("rows", [160, 192])
+@pytest.mark.parametrize("case", FIXED_CLASS_CASES, ids=lambda c: f"{c[0].text()}-T{c[1]}")
+def test_fixed_shape_class(ltl, case, rows):
+    rule, T = case
+    assert 1 <= rule.R * (T - 1) <= 16   # a 32-cell margin
+    g0 = inputs.bernoulli_grid(700, 700, 0.5, seed=rule.R + 3 * T)
+    tuning = dict(steps_per_launch=T, tile_rows=rows, tile_cols=224, waves=8)
+    run_and_compare(ltl, g0, rule, "cat_i8", 2 * T + 1, tuning=tuning)
+
+
+def test_fixed_shape_class_periodic(ltl):
+    g0 = inputs.bernoulli_grid(700, 704, 0.5, seed=11)
+    tuning = dict(steps_per_launch=4, tile_rows=160, tile_cols=224, waves=8)
+    run_periodic(ltl, g0, inputs.sweep_rule(5), "cat_i8", 9, tuning=tuning, every_step=False)
+
+
 def test_wave_count_must_cover_the_strips(ltl):
     g0 = inputs.bernoulli_grid(64, 64, 0.5, seed=1)
     sim = ltl.Simulation(gpu_grid(g0), inputs.Rule(7, 0, 1, 56, 101, 60, 76), "cat_i8")
