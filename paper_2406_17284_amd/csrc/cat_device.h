@@ -555,7 +555,11 @@ struct LaneOff {
 // LDS (the tile goes to the output grid after the last step, with 16-byte stores). Software-
 // pipelined in pairs of output blocks: the MFMAs and centre-state reads of the next pair are
 // issued before the VALU transition of this pair, so their latencies overlap it.
-template <int ELEM, int EPI, bool MASKED>
+// SPLIT (int8, the fixed-shape kernel copies, whose row pitch is a compile-time constant): the
+// two halves' state dwords are addressed from two base registers, so each block's accesses
+// take its row offset as an instruction offset instead of one merged access per block after a
+// per-block base add. With a run-time pitch the merged form is the cheaper one.
+template <int ELEM, int EPI, bool MASKED, bool SPLIT = false>
 __device__ __forceinline__ void phase_b(const CatParams &p, uint8_t *Qt, uint8_t *At, LaneOff lo, int rb0, int count,
                                         int gr0, uint32_t cma, uint32_t cmb, const Bands &bd,
                                         const Codec &cd, const v16i &Ha, const v16i &Hb, const v16i &La,
@@ -568,12 +572,20 @@ __device__ __forceinline__ void phase_b(const CatParams &p, uint8_t *Qt, uint8_t
     uint32_t sa[4], sb[4];
     const int cw = epi_windowed(EPI) ? -p.rc.cwin : 0;
     const v4i acc0 = {cw, cw, cw, cw};
+    constexpr bool SPLIT8 = SPLIT && ELEM == ELEM_I8;   // int8: At == Qt and PA == PS
+    const uint32_t qa0 = lo.q + (uint32_t)(16 * rb0) * PS;
+    uint32_t qb0 = qa0 + 16;
+    // an opaque second base: kept from being folded back into qa0 + 16 (and the pair merged)
+    if constexpr (SPLIT8) asm volatile("" : "+v"(qb0));
     // counts and centre states of block M (slot M & 3)
 #define CAT_ISSUE(M)                                                                               \
     {                                                                                              \
         ca[(M) & 3] = vproduct<ELEM, (M)>(Ha, La, bd, acc0);                                       \
         cb[(M) & 3] = vproduct<ELEM, (M)>(Hb, Lb, bd, acc0);                                       \
-        if constexpr (epi_decays(EPI) || kIsI8<ELEM> || ELEM == ELEM_F16) {                        \
+        if constexpr (SPLIT8) {                                                                    \
+            sa[(M) & 3] = *reinterpret_cast<const uint32_t *>(Qt + qa0 + (uint32_t)(16 * (M)) * PS); \
+            sb[(M) & 3] = *reinterpret_cast<const uint32_t *>(Qt + qb0 + (uint32_t)(16 * (M)) * PS); \
+        } else if constexpr (epi_decays(EPI) || kIsI8<ELEM> || ELEM == ELEM_F16) {                 \
             const uint32_t qo = lo.q + (uint32_t)(16 * (rb0 + (M))) * PS;                          \
             sa[(M) & 3] = *reinterpret_cast<const uint32_t *>(Qt + qo);                            \
             sb[(M) & 3] = *reinterpret_cast<const uint32_t *>(Qt + qo + 16);                       \
@@ -596,13 +608,19 @@ __device__ __forceinline__ void phase_b(const CatParams &p, uint8_t *Qt, uint8_t
         {                                                                                          \
             const uint32_t qo = lo.q + (uint32_t)(16 * (rb0 + (M))) * PS;                          \
             const uint32_t ao = lo.a + (uint32_t)(16 * (rb0 + (M))) * PA;                          \
-            if constexpr (epi_decays(EPI)) {                                                       \
+            if constexpr (SPLIT8 && epi_decays(EPI)) {                                             \
+                *reinterpret_cast<uint32_t *>(Qt + qa0 + (uint32_t)(16 * (M)) * PS) = na;           \
+                *reinterpret_cast<uint32_t *>(Qt + qb0 + (uint32_t)(16 * (M)) * PS) = nb;           \
+            } else if constexpr (epi_decays(EPI)) {                                                \
                 *reinterpret_cast<uint32_t *>(Qt + qo) = na;                                       \
                 *reinterpret_cast<uint32_t *>(Qt + qo + 16) = nb;                                  \
             }                                                                                      \
             if constexpr ((ELEM == ELEM_I8 || ELEM == ELEM_F16) && epi_decays(EPI)) {              \
                 (void)ala;   /* int8 Moore and fp16 decay derive the alive bits from Q when read */ \
                 (void)alb;                                                                         \
+            } else if constexpr (SPLIT8) {   /* two-state: the state, At == Qt */                  \
+                *reinterpret_cast<uint32_t *>(At + qa0 + (uint32_t)(16 * (M)) * PS) = ala;          \
+                *reinterpret_cast<uint32_t *>(At + qb0 + (uint32_t)(16 * (M)) * PS) = alb;          \
             } else if constexpr (kIsI8<ELEM> || ELEM == ELEM_F16) {   /* two-state: the state */   \
                 *reinterpret_cast<uint32_t *>(At + ao) = ala;                                      \
                 *reinterpret_cast<uint32_t *>(At + ao + 16) = alb;                                 \
@@ -645,7 +663,7 @@ __device__ __forceinline__ void phase_b(const CatParams &p, uint8_t *Qt, uint8_t
 }
 
 // T steps of one tile, in place in LDS; ends with a barrier after the last step's writes.
-template <int ELEM, int EPI, bool MASKED>
+template <int ELEM, int EPI, bool MASKED, bool SPLIT = false>
 __device__ __forceinline__ void cat_steps(const CatParams &p, uint8_t *Qt, uint8_t *At, int gi0, int gj0, int wave,
                                           int lane, const Bands &bd, const Codec &cd) {
     constexpr int CELL = ElemT<ELEM>::CELL;
@@ -700,7 +718,7 @@ __device__ __forceinline__ void cat_steps(const CatParams &p, uint8_t *Qt, uint8
                 }
             }
             const int gr0 = gi0 + 16 * rb0 + li;
-            phase_b<ELEM, EPI, MASKED>(p, Qt, At, lo, rb0, count, gr0, cma, cmb, bd, cd, Ha, Hb, La, Lb);
+            phase_b<ELEM, EPI, MASKED, SPLIT>(p, Qt, At, lo, rb0, count, gr0, cma, cmb, bd, cd, Ha, Hb, La, Lb);
         }
         __syncthreads();   // new states complete before the next step (or the copy-out) reads them
     }
@@ -880,7 +898,7 @@ __device__ __forceinline__ void store_tile(const CatParams &p, const uint8_t *Qt
 // The window of the tile at (gi0, gj0) is in LDS at Qt (visible to every wave): derive the
 // alive map in the element encoding at At, run T steps in place, then copy the tile to the
 // output grid. Ends without a barrier.
-template <int ELEM, int EPI>
+template <int ELEM, int EPI, bool SPLIT = false>
 __device__ __forceinline__ void tile_steps(const CatParams &p, int gi0, int gj0, uint8_t *Qt, uint8_t *At, int tid,
                                            int lane, int wave, int nwaves, const Bands &bd, const Codec &cd) {
     // alive map from the loaded states, where a kernel keeps one: fp8 (its encoding of 1.0, in
@@ -910,9 +928,9 @@ __device__ __forceinline__ void tile_steps(const CatParams &p, int gi0, int gj0,
     const int E1 = (p.r * (p.T - 1) + 15) & ~15;
     const bool interior = gi0 - E1 >= 0 && gi0 + p.TH + E1 <= p.H && gj0 - E1 >= 0 && gj0 + p.TW + E1 <= p.W;
     if (interior)
-        cat_steps<ELEM, EPI, false>(p, Qt, At, gi0, gj0, wave, lane, bd, cd);
+        cat_steps<ELEM, EPI, false, SPLIT>(p, Qt, At, gi0, gj0, wave, lane, bd, cd);
     else
-        cat_steps<ELEM, EPI, true>(p, Qt, At, gi0, gj0, wave, lane, bd, cd);
+        cat_steps<ELEM, EPI, true, SPLIT>(p, Qt, At, gi0, gj0, wave, lane, bd, cd);
     // With several steps per launch the copy-out carries the non-temporal hint (+2 % at Bosco
     // 4096², T = 4); at one step per launch, where the kernel streams the grid and the next launch
     // re-reads it at once, plain stores are 13 % faster (16384², 2.04 vs 1.78 T cell-updates/s).
@@ -932,7 +950,7 @@ struct NoSideLoad {
 
 // One tile: load the window with direct LDS loads, then the alive map and T steps in place.
 // Ends without a barrier: a caller that reuses the LDS for another tile synchronizes first.
-template <int ELEM, int EPI, class Side = NoSideLoad>
+template <int ELEM, int EPI, class Side = NoSideLoad, bool SPLIT = false>
 __device__ __forceinline__ void cat_tile(const CatParams &p, int tile, uint8_t *lds, int tid, int lane, int wave,
                                          int nwaves, const Codec &cd, Side &&side = Side()) {
     const int gi0 = (tile / p.ntx) * p.TH;
@@ -945,7 +963,7 @@ __device__ __forceinline__ void cat_tile(const CatParams &p, int tile, uint8_t *
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     side.land(tid);
     __syncthreads();
-    tile_steps<ELEM, EPI>(p, gi0, gj0, Qt, At, tid, lane, wave, nwaves, bd, cd);
+    tile_steps<ELEM, EPI, SPLIT>(p, gi0, gj0, Qt, At, tid, lane, wave, nwaves, bd, cd);
 }
 
 }  // namespace ltl
