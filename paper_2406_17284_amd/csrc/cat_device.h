@@ -242,13 +242,14 @@ struct StepGeom {
     int E, nstrips, nrb, nseg, seglen;
 };
 
+// `last`: t == p.T (passed in, so that a caller that peels the last step folds it).
 template <int MAXC>
-__device__ __forceinline__ StepGeom step_geom(const CatParams &p, int t) {
+__device__ __forceinline__ StepGeom step_geom(const CatParams &p, int t, bool last) {
     StepGeom g;
     // the margin is roundup16(r (T - 1)) + 16 (+ 48 for the wide element, never 32), so a
     // 32-cell margin means 1 <= r (T - 1) <= 16 and every step but the last extends exactly 16:
     // the general rule's value, in a form a kernel with the margin fixed folds
-    g.E = (p.L == 32) ? ((t < p.T) ? 16 : 0) : ((p.r * (p.T - t) + 15) & ~15);
+    g.E = (p.L == 32) ? (last ? 0 : 16) : ((p.r * (p.T - t) + 15) & ~15);
     g.nstrips = (p.TW + 2 * g.E) >> 5;
     g.nrb = (p.TH + 2 * g.E) >> 4;
     if (g.nrb <= MAXC) {   // one segment per strip (the usual case): no integer division
@@ -663,7 +664,10 @@ __device__ __forceinline__ void phase_b(const CatParams &p, uint8_t *Qt, uint8_t
 }
 
 // T steps of one tile, in place in LDS; ends with a barrier after the last step's writes.
-template <int ELEM, int EPI, bool MASKED, bool SPLIT = false>
+// FIX (the fixed-shape kernel copies): 1 = pitch, width and 32-cell margin compiled in (phase
+// B's SPLIT accesses); 2 = the height too, and the last step (extent 0) runs as a copy of its
+// own after the loop over the others (extent 16), so each copy's geometry is constant.
+template <int ELEM, int EPI, bool MASKED, int FIX = 0>
 __device__ __forceinline__ void cat_steps(const CatParams &p, uint8_t *Qt, uint8_t *At, int gi0, int gj0, int wave,
                                           int lane, const Bands &bd, const Codec &cd) {
     constexpr int CELL = ElemT<ELEM>::CELL;
@@ -671,8 +675,8 @@ __device__ __forceinline__ void cat_steps(const CatParams &p, uint8_t *Qt, uint8
     const int li = lane & 15, lg = lane >> 4;
     const uint32_t PS = (uint32_t)p.PS, PA = (uint32_t)p.PA;
     const int L = p.L;
-    for (int t = 1; t <= p.T; ++t) {
-        const StepGeom g = step_geom<MAXC>(p, t);
+    auto step = [&](const int t, const bool last) {
+        const StepGeom g = step_geom<MAXC>(p, t, last);
         const int items = g.nstrips * g.nseg;
         int j0 = 0, rb0 = 0, count = 0;
         if (wave < items) {
@@ -718,9 +722,15 @@ __device__ __forceinline__ void cat_steps(const CatParams &p, uint8_t *Qt, uint8
                 }
             }
             const int gr0 = gi0 + 16 * rb0 + li;
-            phase_b<ELEM, EPI, MASKED, SPLIT>(p, Qt, At, lo, rb0, count, gr0, cma, cmb, bd, cd, Ha, Hb, La, Lb);
+            phase_b<ELEM, EPI, MASKED, (FIX >= 1)>(p, Qt, At, lo, rb0, count, gr0, cma, cmb, bd, cd, Ha, Hb, La, Lb);
         }
         __syncthreads();   // new states complete before the next step (or the copy-out) reads them
+    };
+    if constexpr (FIX >= 2) {
+        for (int t = 1; t < p.T; ++t) step(t, false);
+        step(p.T, true);
+    } else {
+        for (int t = 1; t <= p.T; ++t) step(t, t == p.T);
     }
 }
 
@@ -898,7 +908,7 @@ __device__ __forceinline__ void store_tile(const CatParams &p, const uint8_t *Qt
 // The window of the tile at (gi0, gj0) is in LDS at Qt (visible to every wave): derive the
 // alive map in the element encoding at At, run T steps in place, then copy the tile to the
 // output grid. Ends without a barrier.
-template <int ELEM, int EPI, bool SPLIT = false>
+template <int ELEM, int EPI, int FIX = 0>
 __device__ __forceinline__ void tile_steps(const CatParams &p, int gi0, int gj0, uint8_t *Qt, uint8_t *At, int tid,
                                            int lane, int wave, int nwaves, const Bands &bd, const Codec &cd) {
     // alive map from the loaded states, where a kernel keeps one: fp8 (its encoding of 1.0, in
@@ -928,9 +938,9 @@ __device__ __forceinline__ void tile_steps(const CatParams &p, int gi0, int gj0,
     const int E1 = (p.r * (p.T - 1) + 15) & ~15;
     const bool interior = gi0 - E1 >= 0 && gi0 + p.TH + E1 <= p.H && gj0 - E1 >= 0 && gj0 + p.TW + E1 <= p.W;
     if (interior)
-        cat_steps<ELEM, EPI, false, SPLIT>(p, Qt, At, gi0, gj0, wave, lane, bd, cd);
+        cat_steps<ELEM, EPI, false, FIX>(p, Qt, At, gi0, gj0, wave, lane, bd, cd);
     else
-        cat_steps<ELEM, EPI, true, SPLIT>(p, Qt, At, gi0, gj0, wave, lane, bd, cd);
+        cat_steps<ELEM, EPI, true, FIX>(p, Qt, At, gi0, gj0, wave, lane, bd, cd);
     // With several steps per launch the copy-out carries the non-temporal hint (+2 % at Bosco
     // 4096², T = 4); at one step per launch, where the kernel streams the grid and the next launch
     // re-reads it at once, plain stores are 13 % faster (16384², 2.04 vs 1.78 T cell-updates/s).
@@ -950,7 +960,7 @@ struct NoSideLoad {
 
 // One tile: load the window with direct LDS loads, then the alive map and T steps in place.
 // Ends without a barrier: a caller that reuses the LDS for another tile synchronizes first.
-template <int ELEM, int EPI, class Side = NoSideLoad, bool SPLIT = false>
+template <int ELEM, int EPI, class Side = NoSideLoad, int FIX = 0>
 __device__ __forceinline__ void cat_tile(const CatParams &p, int tile, uint8_t *lds, int tid, int lane, int wave,
                                          int nwaves, const Codec &cd, Side &&side = Side()) {
     const int gi0 = (tile / p.ntx) * p.TH;
@@ -963,7 +973,7 @@ __device__ __forceinline__ void cat_tile(const CatParams &p, int tile, uint8_t *
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     side.land(tid);
     __syncthreads();
-    tile_steps<ELEM, EPI, SPLIT>(p, gi0, gj0, Qt, At, tid, lane, wave, nwaves, bd, cd);
+    tile_steps<ELEM, EPI, FIX>(p, gi0, gj0, Qt, At, tid, lane, wave, nwaves, bd, cd);
 }
 
 }  // namespace ltl

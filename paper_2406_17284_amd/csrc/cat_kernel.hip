@@ -15,7 +15,8 @@ namespace ltl {
 // these compile-time constants the block-row offsets of the LDS accesses become instruction
 // offsets instead of per-block address arithmetic (with phase B's SPLIT form of the state
 // accesses), each step's extent is known (a 32-cell margin leaves 16 for every step but the
-// last), and with the height fixed the guards of the unrolled block loops fold away.
+// last), and with the height fixed the guards of the unrolled block loops fold away (and the
+// last step runs as a copy of its own, so every step's geometry is a constant).
 template <int ELEM, int EPI, int FIXED = 0, int THC = 0>
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) cat_step(CatParams p) {
     if constexpr (FIXED != 0) {
@@ -39,7 +40,7 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) c
     const int tile = (bid & 7) * (nb >> 3) + (bid >> 3);
     if (tile >= ntiles) return;
     const Codec cd = make_codec();
-    cat_tile<ELEM, EPI, NoSideLoad, FIXED != 0>(p, tile, lds, tid, lane, wave, nwaves, cd);
+    cat_tile<ELEM, EPI, NoSideLoad, FIXED == 0 ? 0 : THC == 0 ? 1 : 2>(p, tile, lds, tid, lane, wave, nwaves, cd);
 }
 
 // Persistent form (tuning.persistent = 1), for grids whose tiles stream from HBM: one
