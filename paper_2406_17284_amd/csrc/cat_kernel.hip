@@ -136,15 +136,18 @@ static const void *cat_step_fixed_func(int epi) {
     }
 }
 
-// 160-row tiles of the fixed class, two-state epilogues only: with the height fixed too the
-// decay epilogues and the 192-row tiles exceed the 128-register budget of two 8-wave
-// workgroups per CU and spill (measured slower), so they keep the height a launch parameter.
+// 160-row tiles of the fixed class, every epilogue. With the height fixed the 192-row tiles
+// exceed the 128-register budget of two 8-wave workgroups per CU and spill (measured slower),
+// so they keep the height a launch parameter.
 static const void *cat_step_fixed160_func(int epi) {
     switch (epi) {
         case EPI_BYTE: return (const void *)&cat_step<ELEM_I8, EPI_BYTE, kFixedPitch, 160>;
         case EPI_HALF: return (const void *)&cat_step<ELEM_I8, EPI_HALF, kFixedPitch, 160>;
+        case EPI_DECAY: return (const void *)&cat_step<ELEM_I8, EPI_DECAY, kFixedPitch, 160>;
         case EPI_WIN: return (const void *)&cat_step<ELEM_I8, EPI_WIN, kFixedPitch, 160>;
+        case EPI_DECAY8: return (const void *)&cat_step<ELEM_I8, EPI_DECAY8, kFixedPitch, 160>;
         case EPI_WIN8: return (const void *)&cat_step<ELEM_I8, EPI_WIN8, kFixedPitch, 160>;
+        case EPI_DECAY8W: return (const void *)&cat_step<ELEM_I8, EPI_DECAY8W, kFixedPitch, 160>;
         default: return nullptr;
     }
 }
